@@ -1,0 +1,197 @@
+/*
+ * ammse.h - C ABI of libammse, a batched GPU solver (AMD MI355X, gfx950) for
+ * weighted-sum-rate (WSR) downlink precoding by A-MMMSE, the accelerated
+ * mixed weighted-unweighted sum-MSE method of arXiv 2510.20507.
+ *
+ * Problem (Section II, WSR problem): C base stations (BS) with M antennas;
+ * users u, ordered cell by cell, with N receive antennas and d streams;
+ * channel H_{u,j} (N x M) from BS j to user u, noise power sigma2_u, weight
+ * alpha_u, per-BS sum-power budget P_c.  Find precoders V_u (M x d) that
+ * maximise sum_u alpha_u R_u subject to sum_{u in c} ||V_u||_F^2 <= P_c.
+ *
+ * Method (Algorithm 3): per iteration, receivers U and weights W by exact
+ * block minimisation (Section IV equations for U and W; only N x N and d x d
+ * factorisations), W = I during the warm-start stage (Section V-B) until the
+ * relative WSR change drops to eps1, then one projected-gradient step for V
+ * (Section V-A: gradient, projection onto the sum-power ball, adaptive step
+ * for the first T_c iterations, extrapolation weight omega^t).
+ *
+ * Conventions for every entry point:
+ *   - All data buffers are caller-owned DEVICE memory unless stated; the
+ *     library never frees or reallocates them.  Tables passed to
+ *     ammse_validate / ammse_plan_create are HOST memory and are copied.
+ *   - Complex numbers are interleaved (re, im): double2 when the plan's
+ *     precision is AMMSE_PREC_FP64, float2 for AMMSE_PREC_FP32.
+ *   - Calls that take a stream only enqueue work on it and return; outputs
+ *     are valid once the stream has synchronised.
+ *   - Errors in arguments are reported synchronously by the return code and
+ *     nothing is enqueued.  Numerical trouble in one instance (a failed
+ *     factorisation, a non-finite value) is reported in that instance's
+ *     status word and never aborts the process.  No C++ exception crosses
+ *     this interface.
+ */
+#ifndef AMMSE_H
+#define AMMSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AMMSE_VERSION 1
+
+/* Return codes. */
+typedef int32_t ammse_status_t;
+#define AMMSE_OK 0
+#define AMMSE_ERR_NULL 1        /* a required pointer argument is NULL */
+#define AMMSE_ERR_SHAPE 2       /* an instance entry has invalid sizes or offsets */
+#define AMMSE_ERR_OPTION 3      /* an option is out of range */
+#define AMMSE_ERR_WORKSPACE 4   /* workspace smaller than ammse_plan_workspace_size */
+#define AMMSE_ERR_HIP 5         /* HIP runtime error (no device, launch failure) */
+#define AMMSE_ERR_UNSUPPORTED 6 /* valid but outside this build's limits (see below) */
+#define AMMSE_ERR_ALLOC 7       /* the plan could not allocate its device tables */
+
+/* Per-instance status bits written by ammse_solve. */
+#define AMMSE_INST_OK 0
+#define AMMSE_INST_NONFINITE 1  /* a WSR or step became NaN/Inf; iteration stopped */
+#define AMMSE_INST_CHOLESKY 2   /* a covariance factorisation failed; iteration stopped */
+#define AMMSE_INST_ZERO_POWER 4 /* some BS ended with zero transmit power */
+
+/* Arithmetic of the channel products (and storage type of H and V). */
+#define AMMSE_PREC_FP64 0       /* everything in double */
+#define AMMSE_PREC_FP32 1       /* channel products in float; N x N, d x d work,
+                                   step size and projection in double */
+
+/* Limits of this build. */
+#define AMMSE_MAX_CELLS 16
+#define AMMSE_MAX_RX 4          /* N <= 4 (the paper's d <= N <= 4 regime) */
+#define AMMSE_MAX_USERS 256     /* users per instance (all cells) */
+#define AMMSE_MAX_ANTENNAS 4096
+
+/*
+ * One instance (channel realisation).  Offsets index the flat buffers passed
+ * to ammse_solve; they may be in any order but blocks must not overlap.
+ *   H:       C blocks, block c = stacked channel H_{:,c} = [H_{0,c}; ...;
+ *            H_{U-1,c}], (U*N) x M row-major; element offset h_off.
+ *   V:       C blocks, block c = V_c = [V_u, u in cell c], M x (U_c*d)
+ *            row-major, so V_u[m][s] = V_c[m][i*d + s] for the i-th user of c;
+ *            element offset v_off.
+ *   sigma2, alpha: U entries at user_off.    P: C entries at bs_off.
+ *   cell_users: C entries (users per cell) at cell_off; they sum to U.
+ */
+typedef struct ammse_instance_t {
+  int32_t C;        /* base stations (cells), 1..AMMSE_MAX_CELLS */
+  int32_t U;        /* users over all cells, 1..AMMSE_MAX_USERS */
+  int32_t M;        /* BS antennas, 1..AMMSE_MAX_ANTENNAS */
+  int32_t N;        /* receive antennas per user, 1..AMMSE_MAX_RX */
+  int32_t d;        /* streams per user, 1..N */
+  int32_t cell_off; /* index of this instance's first entry in cell_users[] */
+  int64_t h_off;    /* complex elements */
+  int64_t v_off;    /* complex elements */
+  int64_t user_off; /* entries of sigma2[] / alpha[] */
+  int64_t bs_off;   /* entries of P[] */
+} ammse_instance_t;
+
+/* Solver options (Algorithm 3 inputs). */
+typedef struct ammse_options_t {
+  int32_t precision;         /* AMMSE_PREC_* */
+  int32_t max_iters;         /* iterations T (>= 0) */
+  int32_t T_c;               /* adaptive-step window (paper: 3) */
+  int32_t warm_start;        /* 1: stage I (W = I) until eps1 (A-MMMSE); 0: A-WMMSE */
+  int32_t extrapolate;       /* 1: omega^t = max{(t-2)/(t+1),0}; 0: omega = 0 */
+  int32_t rearm_at_switch;   /* 1: also use the adaptive step in the first T_c
+                                stage-II iterations (default); 0: only t <= T_c */
+  int32_t force_switch_iter; /* -1: switch by the eps1 rule; s >= 1: first stage-II
+                                iteration is s for every instance */
+  int32_t lanczos_steps;     /* Krylov dimension for ||2A_c||_2; 0 = min(M, 64) */
+  double eps1;               /* stage-switch tolerance (paper: 0.1) */
+  double eps2;               /* stop tolerance (0: run exactly max_iters) */
+  double gamma_c;            /* > 0: fixed step after the adaptive window;
+                                <= 0: keep the last adaptive step of each BS */
+} ammse_options_t;
+
+/* Opaque plan: validated copy of the instance table on the device, the
+ * per-instance workspace map and the launch order. */
+typedef struct ammse_plan_s* ammse_plan_t;
+
+/* HIP stream handle (identical to hipStream_t). */
+typedef struct ihipStream_t* ammse_stream_t;
+
+/* Library version (AMMSE_VERSION). */
+int32_t ammse_version(void);
+
+/* Human-readable text for a return code; never NULL. */
+const char* ammse_status_string(ammse_status_t s);
+
+/* Fill *opt with the paper's defaults: FP32, T = 100, T_c = 3, warm start,
+ * extrapolation, re-armed step, eps1 = 0.1, eps2 = 0, gamma_c = 0 (keep). */
+void ammse_default_options(ammse_options_t* opt);
+
+/*
+ * Host-only validation of an instance table (no GPU needed).  table and
+ * cell_users are host arrays of `batch` entries and of the referenced cell
+ * counts.  On success the optional outputs receive the minimum lengths the
+ * flat buffers must have: complex elements of H and V, entries of
+ * sigma2/alpha, entries of P.  opt may be NULL (defaults).
+ */
+ammse_status_t ammse_validate(const ammse_instance_t* table, const int32_t* cell_users,
+                              int32_t batch, const ammse_options_t* opt, int64_t* h_elems,
+                              int64_t* v_elems, int64_t* user_elems, int64_t* bs_elems);
+
+/*
+ * Create a plan for `batch` instances on HIP device `device`.  Validates the
+ * table first (same checks as ammse_validate), then copies it to the device
+ * and sorts instances by decreasing work so that uneven batches balance.
+ * *plan is set only on success.  Allocates device memory for the tables.
+ */
+ammse_status_t ammse_plan_create(ammse_plan_t* plan, int32_t device,
+                                 const ammse_instance_t* table, const int32_t* cell_users,
+                                 int32_t batch, const ammse_options_t* opt);
+
+/* Bytes of device workspace ammse_solve / ammse_wsr need for this plan. */
+ammse_status_t ammse_plan_workspace_size(ammse_plan_t plan, size_t* bytes);
+
+/* Release the plan's device tables.  NULL is accepted. */
+ammse_status_t ammse_plan_destroy(ammse_plan_t plan);
+
+/*
+ * Run A-MMMSE (Algorithm 3) on every instance of the plan, one workgroup per
+ * instance, all iterations in one kernel launch.
+ *   H        device, complex, layout above (read only)
+ *   sigma2   device double [users]   noise powers (> 0)
+ *   alpha    device double [users]   priority weights (>= 0)
+ *   P        device double [BSs]     power budgets (>= 0)
+ *   V        device, complex: in = feasible V^0, out = final precoders
+ *   wsr      device double [batch]   WSR of the returned V, bits/channel use
+ *   iters    device int32 [batch]    iterations run (may be NULL)
+ *   switch_iter device int32 [batch] first stage-II iteration, -1 if none (may be NULL)
+ *   status   device int32 [batch]    AMMSE_INST_* bits (may be NULL)
+ *   wsr_trace device double [batch][max_iters+1]: WSR(V^0..V^t), NaN after
+ *            the last iteration run (may be NULL)
+ *   force_switch device int32 [batch]: per-instance first stage-II iteration,
+ *            <= 0 for the eps1 rule (may be NULL; overrides the option)
+ *   workspace device, >= ammse_plan_workspace_size bytes, 256-byte aligned
+ *   stream   HIP stream (NULL = default stream)
+ * Iteration t evaluates receivers, MSE matrices and WSR at V^{t-1}; the
+ * gradient at the extrapolated point; WSR(V^{t-1}) drives the stage test.
+ */
+ammse_status_t ammse_solve(ammse_plan_t plan, const void* H, const double* sigma2,
+                           const double* alpha, const double* P, void* V, double* wsr,
+                           int32_t* iters, int32_t* switch_iter, int32_t* status,
+                           double* wsr_trace, const int32_t* force_switch, void* workspace,
+                           size_t workspace_bytes, ammse_stream_t stream);
+
+/*
+ * Weighted sum rate (Section II rate definition, bits) of the precoders V for
+ * every instance of the plan; same buffer conventions as ammse_solve.
+ */
+ammse_status_t ammse_wsr(ammse_plan_t plan, const void* H, const double* sigma2,
+                         const double* alpha, const void* V, double* wsr, void* workspace,
+                         size_t workspace_bytes, ammse_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMMSE_H */

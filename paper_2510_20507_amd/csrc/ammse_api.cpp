@@ -1,0 +1,296 @@
+// Host side of libammse: validation, plans, workspace map, launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "ammse_internal.h"
+
+struct ammse_plan_s {
+  int32_t device = 0;
+  int32_t batch = 0;
+  ammse_options_t opt{};
+  size_t ws_bytes = 0;
+  ammse_desc_t* d_desc = nullptr;
+  int32_t* d_cell_users = nullptr;
+};
+
+namespace {
+
+int resolved_lanczos(const ammse_options_t& o) {
+  return o.lanczos_steps > 0 ? o.lanczos_steps : AMMSE_MAX_LANCZOS;
+}
+
+ammse_status_t check_options(const ammse_options_t& o) {
+  if (o.precision != AMMSE_PREC_FP64 && o.precision != AMMSE_PREC_FP32) return AMMSE_ERR_OPTION;
+  if (o.max_iters < 0 || o.max_iters > 1000000) return AMMSE_ERR_OPTION;
+  if (o.T_c < 0) return AMMSE_ERR_OPTION;
+  if (o.warm_start != 0 && o.warm_start != 1) return AMMSE_ERR_OPTION;
+  if (o.extrapolate != 0 && o.extrapolate != 1) return AMMSE_ERR_OPTION;
+  if (o.rearm_at_switch != 0 && o.rearm_at_switch != 1) return AMMSE_ERR_OPTION;
+  if (o.force_switch_iter != -1 && o.force_switch_iter < 1) return AMMSE_ERR_OPTION;
+  if (o.lanczos_steps < 0 || o.lanczos_steps > AMMSE_MAX_LANCZOS) return AMMSE_ERR_OPTION;
+  if (!(o.eps1 >= 0.0) || !(o.eps2 >= 0.0)) return AMMSE_ERR_OPTION;
+  if (o.T_c == 0 && !(o.gamma_c > 0.0)) return AMMSE_ERR_OPTION;
+  if (o.gamma_c != o.gamma_c) return AMMSE_ERR_OPTION;
+  return AMMSE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t ammse_version(void) { return AMMSE_VERSION; }
+
+const char* ammse_status_string(ammse_status_t s) {
+  switch (s) {
+    case AMMSE_OK: return "success";
+    case AMMSE_ERR_NULL: return "required pointer argument is NULL";
+    case AMMSE_ERR_SHAPE: return "invalid instance sizes or offsets";
+    case AMMSE_ERR_OPTION: return "option out of range";
+    case AMMSE_ERR_WORKSPACE: return "workspace too small";
+    case AMMSE_ERR_HIP: return "HIP runtime error";
+    case AMMSE_ERR_UNSUPPORTED: return "outside the limits of this build";
+    case AMMSE_ERR_ALLOC: return "device allocation for the plan failed";
+    default: return "unknown status";
+  }
+}
+
+void ammse_default_options(ammse_options_t* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->precision = AMMSE_PREC_FP32;
+  opt->max_iters = 100;
+  opt->T_c = 3;
+  opt->warm_start = 1;
+  opt->extrapolate = 1;
+  opt->rearm_at_switch = 1;
+  opt->force_switch_iter = -1;
+  opt->lanczos_steps = 0;
+  opt->eps1 = 0.1;
+  opt->eps2 = 0.0;
+  opt->gamma_c = 0.0;
+}
+
+ammse_status_t ammse_validate(const ammse_instance_t* table, const int32_t* cell_users,
+                              int32_t batch, const ammse_options_t* opt, int64_t* h_elems,
+                              int64_t* v_elems, int64_t* user_elems, int64_t* bs_elems) {
+  ammse_options_t o;
+  if (opt) {
+    o = *opt;
+  } else {
+    ammse_default_options(&o);
+  }
+  ammse_status_t st = check_options(o);
+  if (st != AMMSE_OK) return st;
+  if (batch < 0) return AMMSE_ERR_SHAPE;
+  if (batch > 0 && (!table || !cell_users)) return AMMSE_ERR_NULL;
+  int64_t hmax = 0, vmax = 0, umax = 0, bmax = 0;
+  std::vector<std::pair<int64_t, int64_t>> vspans;
+  vspans.reserve(batch);
+  for (int32_t i = 0; i < batch; ++i) {
+    const ammse_instance_t& t = table[i];
+    if (t.C < 1 || t.U < 1 || t.M < 1 || t.N < 1 || t.d < 1 || t.d > t.N) return AMMSE_ERR_SHAPE;
+    if (t.cell_off < 0 || t.h_off < 0 || t.v_off < 0 || t.user_off < 0 || t.bs_off < 0)
+      return AMMSE_ERR_SHAPE;
+    if (t.C > AMMSE_MAX_CELLS || t.U > AMMSE_MAX_USERS || t.M > AMMSE_MAX_ANTENNAS ||
+        t.N > AMMSE_MAX_RX)
+      return AMMSE_ERR_UNSUPPORTED;
+    int64_t su = 0;
+    for (int c = 0; c < t.C; ++c) {
+      const int32_t n = cell_users[(int64_t)t.cell_off + c];
+      if (n < 0) return AMMSE_ERR_SHAPE;
+      su += n;
+    }
+    if (su != t.U) return AMMSE_ERR_SHAPE;
+    const int64_t hlen = (int64_t)t.C * t.U * t.N * t.M;
+    const int64_t vlen = (int64_t)t.M * t.U * t.d;
+    hmax = std::max(hmax, t.h_off + hlen);
+    vmax = std::max(vmax, t.v_off + vlen);
+    umax = std::max(umax, t.user_off + t.U);
+    bmax = std::max(bmax, t.bs_off + t.C);
+    vspans.emplace_back(t.v_off, vlen);
+  }
+  // precoder blocks are written: they must not overlap
+  std::sort(vspans.begin(), vspans.end());
+  for (size_t i = 1; i < vspans.size(); ++i)
+    if (vspans[i - 1].first + vspans[i - 1].second > vspans[i].first) return AMMSE_ERR_SHAPE;
+  if (h_elems) *h_elems = hmax;
+  if (v_elems) *v_elems = vmax;
+  if (user_elems) *user_elems = umax;
+  if (bs_elems) *bs_elems = bmax;
+  return AMMSE_OK;
+}
+
+ammse_status_t ammse_plan_create(ammse_plan_t* plan, int32_t device,
+                                 const ammse_instance_t* table, const int32_t* cell_users,
+                                 int32_t batch, const ammse_options_t* opt) {
+  if (!plan) return AMMSE_ERR_NULL;
+  ammse_options_t o;
+  if (opt) {
+    o = *opt;
+  } else {
+    ammse_default_options(&o);
+  }
+  ammse_status_t st =
+      ammse_validate(table, cell_users, batch, &o, nullptr, nullptr, nullptr, nullptr);
+  if (st != AMMSE_OK) return st;
+  if (batch < 1) return AMMSE_ERR_SHAPE;
+  if (hipSetDevice(device) != hipSuccess) return AMMSE_ERR_HIP;
+
+  const int rb = (o.precision == AMMSE_PREC_FP64) ? 8 : 4;
+  const int ls = resolved_lanczos(o);
+  // launch order: decreasing work, so the dispatcher balances uneven batches
+  std::vector<int32_t> order(batch);
+  std::iota(order.begin(), order.end(), 0);
+  std::vector<double> cost(batch);
+  for (int32_t i = 0; i < batch; ++i) {
+    const ammse_instance_t& t = table[i];
+    cost[i] = (double)t.C * t.U * t.N * (double)t.M * t.U * t.d;
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+
+  std::vector<ammse_desc_t> desc(batch);
+  size_t off = 0;
+  int64_t ncu = 0;
+  for (int32_t i = 0; i < batch; ++i) ncu = std::max<int64_t>(ncu, table[i].cell_off + table[i].C);
+  for (int32_t k = 0; k < batch; ++k) {
+    const ammse_instance_t& t = table[order[k]];
+    ammse_desc_t& d = desc[k];
+    d.C = t.C;
+    d.U = t.U;
+    d.M = t.M;
+    d.N = t.N;
+    d.d = t.d;
+    d.cell_off = t.cell_off;
+    d.un = t.U * t.N;
+    d.ud = t.U * t.d;
+    d.b = order[k];
+    d.pad = 0;
+    d.h_off = t.h_off;
+    d.v_off = t.v_off;
+    d.user_off = t.user_off;
+    d.bs_off = t.bs_off;
+    d.ws_off = (int64_t)off;
+    off += ammse_ws_layout(rb, t.U, t.M, t.N, t.d, ls).total;
+  }
+
+  ammse_plan_s* P = new (std::nothrow) ammse_plan_s();
+  if (!P) return AMMSE_ERR_ALLOC;
+  P->device = device;
+  P->batch = batch;
+  P->opt = o;
+  P->opt.lanczos_steps = ls;
+  P->ws_bytes = std::max<size_t>(off, 256);
+  if (hipMalloc(&P->d_desc, sizeof(ammse_desc_t) * batch) != hipSuccess ||
+      hipMalloc(&P->d_cell_users, sizeof(int32_t) * std::max<int64_t>(ncu, 1)) != hipSuccess) {
+    if (P->d_desc) (void)hipFree(P->d_desc);
+    delete P;
+    return AMMSE_ERR_ALLOC;
+  }
+  if (hipMemcpy(P->d_desc, desc.data(), sizeof(ammse_desc_t) * batch, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(P->d_cell_users, cell_users, sizeof(int32_t) * ncu, hipMemcpyHostToDevice) !=
+          hipSuccess) {
+    (void)hipFree(P->d_desc);
+    (void)hipFree(P->d_cell_users);
+    delete P;
+    return AMMSE_ERR_HIP;
+  }
+  *plan = P;
+  return AMMSE_OK;
+}
+
+ammse_status_t ammse_plan_workspace_size(ammse_plan_t plan, size_t* bytes) {
+  if (!plan || !bytes) return AMMSE_ERR_NULL;
+  *bytes = plan->ws_bytes;
+  return AMMSE_OK;
+}
+
+ammse_status_t ammse_plan_destroy(ammse_plan_t plan) {
+  if (!plan) return AMMSE_OK;
+  (void)hipSetDevice(plan->device);
+  (void)hipFree(plan->d_desc);
+  (void)hipFree(plan->d_cell_users);
+  delete plan;
+  return AMMSE_OK;
+}
+
+static ammse_status_t launch(ammse_plan_t plan, ammse_kparams_t& k, hipStream_t stream) {
+  if (hipSetDevice(plan->device) != hipSuccess) return AMMSE_ERR_HIP;
+  hipError_t e = (plan->opt.precision == AMMSE_PREC_FP64) ? ammse_launch_fp64(k, stream)
+                                                          : ammse_launch_fp32(k, stream);
+  return (e == hipSuccess) ? AMMSE_OK : AMMSE_ERR_HIP;
+}
+
+static void fill_common(ammse_plan_t plan, ammse_kparams_t& k) {
+  std::memset(&k, 0, sizeof(k));
+  const ammse_options_t& o = plan->opt;
+  k.desc = plan->d_desc;
+  k.cell_users = plan->d_cell_users;
+  k.batch = plan->batch;
+  k.max_iters = o.max_iters;
+  k.T_c = o.T_c;
+  k.warm_start = o.warm_start;
+  k.extrapolate = o.extrapolate;
+  k.rearm = o.rearm_at_switch;
+  k.force_switch_iter = o.force_switch_iter;
+  k.lanczos_steps = o.lanczos_steps;
+  k.trace_len = o.max_iters + 1;
+  k.eps1 = o.eps1;
+  k.eps2 = o.eps2;
+  k.gamma_c = o.gamma_c;
+}
+
+ammse_status_t ammse_solve(ammse_plan_t plan, const void* H, const double* sigma2,
+                           const double* alpha, const double* P, void* V, double* wsr,
+                           int32_t* iters, int32_t* switch_iter, int32_t* status,
+                           double* wsr_trace, const int32_t* force_switch, void* workspace,
+                           size_t workspace_bytes, ammse_stream_t stream) {
+  if (!plan || !H || !sigma2 || !alpha || !P || !V || !wsr || !workspace) return AMMSE_ERR_NULL;
+  if (workspace_bytes < plan->ws_bytes) return AMMSE_ERR_WORKSPACE;
+  if (((uintptr_t)workspace & 255) != 0) return AMMSE_ERR_WORKSPACE;
+  ammse_kparams_t k;
+  fill_common(plan, k);
+  k.H = H;
+  k.sigma2 = sigma2;
+  k.alpha = alpha;
+  k.P = P;
+  k.V = V;
+  k.wsr = wsr;
+  k.iters = iters;
+  k.switch_iter = switch_iter;
+  k.status = status;
+  k.trace = wsr_trace;
+  k.force_switch = force_switch;
+  k.ws = (char*)workspace;
+  k.wsr_only = 0;
+  return launch(plan, k, (hipStream_t)stream);
+}
+
+ammse_status_t ammse_wsr(ammse_plan_t plan, const void* H, const double* sigma2,
+                         const double* alpha, const void* V, double* wsr, void* workspace,
+                         size_t workspace_bytes, ammse_stream_t stream) {
+  if (!plan || !H || !sigma2 || !alpha || !V || !wsr || !workspace) return AMMSE_ERR_NULL;
+  if (workspace_bytes < plan->ws_bytes) return AMMSE_ERR_WORKSPACE;
+  if (((uintptr_t)workspace & 255) != 0) return AMMSE_ERR_WORKSPACE;
+  ammse_kparams_t k;
+  fill_common(plan, k);
+  k.H = H;
+  k.sigma2 = sigma2;
+  k.alpha = alpha;
+  k.P = nullptr;   // budgets are not read when only the WSR is evaluated
+  k.V = const_cast<void*>(V);
+  k.wsr = wsr;
+  k.ws = (char*)workspace;
+  k.wsr_only = 1;
+  k.max_iters = 0;
+  k.trace_len = 1;
+  return launch(plan, k, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// Internal declarations shared by the host side and the kernels of libammse.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/ammse.h"
+
+// Per-instance descriptor in launch order (device copy built by the plan).
+struct ammse_desc_t {
+  int32_t C, U, M, N, d, cell_off;
+  int32_t un;   // U*N: rows of a stacked channel H_{:,c}
+  int32_t ud;   // U*d: columns of all precoders together
+  int32_t b;    // index of the instance in the caller's table
+  int32_t pad;
+  int64_t h_off, v_off, user_off, bs_off;
+  int64_t ws_off;  // byte offset of the instance workspace
+};
+
+// Byte offsets of the sub-buffers inside one instance workspace.
+struct ammse_ws_layout_t {
+  size_t Gp, Gq, Z, Vq, Gr;   // storage-precision complex matrices
+  size_t Jm, Dm, Ym;          // double complex per-user blocks
+  size_t Lq, Lw, Ly1, Ly2;    // Lanczos basis and work vectors (double complex)
+  size_t total;
+};
+
+// Launch parameters of the fused solve kernel.
+struct ammse_kparams_t {
+  const ammse_desc_t* desc;
+  const int32_t* cell_users;
+  const void* H;
+  const double* sigma2;
+  const double* alpha;
+  const double* P;
+  void* V;
+  double* wsr;
+  int32_t* iters;
+  int32_t* switch_iter;
+  int32_t* status;
+  double* trace;
+  const int32_t* force_switch;
+  char* ws;
+  int32_t batch;
+  int32_t max_iters;
+  int32_t T_c;
+  int32_t warm_start;
+  int32_t extrapolate;
+  int32_t rearm;
+  int32_t force_switch_iter;
+  int32_t lanczos_steps;
+  int32_t wsr_only;      // 1: evaluate WSR(V) and return (no iteration, V not written)
+  int32_t trace_len;     // max_iters + 1
+  double eps1, eps2, gamma_c;
+};
+
+#define AMMSE_BLOCK 256
+#define AMMSE_MAX_LANCZOS 64
+
+// Workspace layout of one instance (bytes), for complex storage of
+// `real_bytes` per component (8 for FP64, 4 for FP32).  Every sub-buffer
+// starts on a 256-byte boundary.
+__host__ __device__ inline size_t ammse_align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+__host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int U, int M, int N,
+                                                             int d, int lanczos_steps) {
+  const size_t cs = 2 * (size_t)real_bytes;      // storage complex
+  const size_t zs = 16;                          // double complex
+  const size_t un = (size_t)U * N, ud = (size_t)U * d;
+  ammse_ws_layout_t L;
+  size_t o = 0;
+  L.Gp = o;  o += ammse_align256(un * ud * cs);
+  L.Gq = o;  o += ammse_align256(un * ud * cs);
+  L.Z = o;   o += ammse_align256(un * ud * cs);
+  L.Vq = o;  o += ammse_align256((size_t)M * ud * cs);
+  L.Gr = o;  o += ammse_align256((size_t)M * ud * cs);
+  L.Jm = o;  o += ammse_align256((size_t)U * 16 * zs);
+  L.Dm = o;  o += ammse_align256((size_t)U * 16 * zs);
+  L.Ym = o;  o += ammse_align256((size_t)U * 16 * zs);
+  L.Lq = o;  o += ammse_align256((size_t)(lanczos_steps + 1) * M * zs);
+  L.Lw = o;  o += ammse_align256((size_t)M * zs);
+  L.Ly1 = o; o += ammse_align256(un * zs);
+  L.Ly2 = o; o += ammse_align256(un * zs);
+  L.total = o;
+  return L;
+}
+
+hipError_t ammse_launch_fp64(const ammse_kparams_t& p, hipStream_t s);
+hipError_t ammse_launch_fp32(const ammse_kparams_t& p, hipStream_t s);

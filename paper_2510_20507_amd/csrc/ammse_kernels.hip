@@ -1,0 +1,748 @@
+// Fused A-MMMSE solve kernel for gfx950 (generic path, FP64 and FP32).
+//
+// One workgroup of 256 threads owns one channel realisation for the whole
+// solve: all iterations of Algorithm 3 run inside one launch, so the batch of
+// independent instances is the data-parallel axis and no state crosses
+// workgroups.  Per iteration t:
+//   G_c  = S H_{:,c} V_c^{t-1}       channel product per BS (S = diag(1/sigma_u),
+//                                     which normalises every user to unit noise)
+//   per user: interference-plus-noise covariance J-_u, Cholesky, rate, E, U, W
+//   WSR(V^{t-1}) = sum alpha_u R_u    -> stage latch (eps1), optional eps2 stop
+//   step size 1/||2 A_c||_2 by Lanczos on A_c = H^H S D S H (adaptive window)
+//   Z_c  = S (D G^_c - Y_c)          with G^ = (1+w) G^{t-1} - w G^{t-2} (linearity)
+//   Grad = 2 H_{:,c}^H Z_c            second channel product per BS
+//   V^t  = Pi_P(V^ - gamma Grad)      extrapolated step and projection per BS
+//
+// Receiver/weight algebra (Section IV equations for U and W) is evaluated in
+// the cancellation-free form: with F = L^{-1} G_own (J- = L L^H),
+// W = E^{-1} = I + F^H F, R_u = log det W, U W = J-^{-1} G_own,
+// U = (U W) E.  These are identities of the paper's expressions (Woodbury),
+// chosen because I - U^H H V loses digits at high SNR in short precision.
+// All N x N and d x d work is in double, zero-padded to 4 x 4 so that every
+// loop has a compile-time bound.
+
+#include <math.h>
+
+#include "ammse_internal.h"
+
+namespace {
+
+template <class R>
+struct cx {
+  R x, y;
+};
+
+template <class R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <class R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <class R>
+__device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <class R>
+__device__ __forceinline__ cx<R> scal(R s, cx<R> a) { return {s * a.x, s * a.y}; }
+template <class R>
+__device__ __forceinline__ cx<R> cj(cx<R> a) { return {a.x, -a.y}; }
+// a * conj(b)
+template <class R>
+__device__ __forceinline__ cx<R> mulc(cx<R> a, cx<R> b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <class R>
+__device__ __forceinline__ R nrm2(cx<R> a) { return a.x * a.x + a.y * a.y; }
+
+using zd = cx<double>;
+
+template <class R>
+__device__ __forceinline__ zd to_d(cx<R> a) { return {(double)a.x, (double)a.y}; }
+template <class R>
+__device__ __forceinline__ cx<R> from_d(zd a) { return {(R)a.x, (R)a.y}; }
+
+constexpr int KC = 16;   // k-chunk of the channel products
+constexpr int TM = 64;   // output tile rows
+constexpr int TN = 64;   // output tile columns
+
+template <class R>
+struct Smem {
+  cx<R> As[KC * (TM + 1)];
+  cx<R> Bs[KC * (TN + 1)];
+  double invsig[AMMSE_MAX_USERS];
+  double alpha[AMMSE_MAX_USERS];
+  double rate[AMMSE_MAX_USERS];
+  int cellOf[AMMSE_MAX_USERS];
+  int local[AMMSE_MAX_USERS];
+  int cu[AMMSE_MAX_CELLS];
+  int colOff[AMMSE_MAX_CELLS + 1];
+  double Pc[AMMSE_MAX_CELLS];
+  double gamma[AMMSE_MAX_CELLS];
+  double la[AMMSE_MAX_LANCZOS];
+  double lb[AMMSE_MAX_LANCZOS];
+  zd h[AMMSE_MAX_LANCZOS];
+  double red[8];
+  int fail;
+  int imin;
+};
+
+// Sum over the 256 threads; every thread receives the same value.
+__device__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// C (m x n) = alpha * op(A) * B, row i of C further scaled by rowscale[i / rs_div]
+// when rowscale != nullptr.  op(A) = A (m x k, row-major, lda) or, with CONJA,
+// A^H where A is stored k x m row-major (lda).  B is k x n row-major (ldb).
+// All operands in global memory, staged through LDS tiles of 64 x 16.
+template <class R, bool CONJA>
+__device__ void block_gemm(int m, int n, int k, const cx<R>* __restrict__ A, long lda,
+                           const cx<R>* __restrict__ B, long ldb, cx<R>* __restrict__ Cm,
+                           long ldc, R alpha, const double* rowscale, int rs_div, cx<R>* As,
+                           cx<R>* Bs) {
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  for (int i0 = 0; i0 < m; i0 += TM) {
+    for (int j0 = 0; j0 < n; j0 += TN) {
+      cx<R> acc[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = {R(0), R(0)};
+      for (int k0 = 0; k0 < k; k0 += KC) {
+        for (int e = tid; e < TM * KC; e += AMMSE_BLOCK) {
+          int row, kk;
+          if (CONJA) {
+            row = e % TM;
+            kk = e / TM;
+          } else {
+            kk = e % KC;
+            row = e / KC;
+          }
+          const int gi = i0 + row, gk = k0 + kk;
+          cx<R> v = {R(0), R(0)};
+          if (gi < m && gk < k) v = CONJA ? cj(A[(long)gk * lda + gi]) : A[(long)gi * lda + gk];
+          As[kk * (TM + 1) + row] = v;
+        }
+        for (int e = tid; e < KC * TN; e += AMMSE_BLOCK) {
+          const int col = e % TN, kk = e / TN;
+          const int gj = j0 + col, gk = k0 + kk;
+          cx<R> v = {R(0), R(0)};
+          if (gj < n && gk < k) v = B[(long)gk * ldb + gj];
+          Bs[kk * (TN + 1) + col] = v;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < KC; ++kk) {
+          cx<R> a[4], b[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) a[i] = As[kk * (TM + 1) + ty + 16 * i];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) b[j] = Bs[kk * (TN + 1) + tx + 16 * j];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              acc[i][j].x += a[i].x * b[j].x - a[i].y * b[j].y;
+              acc[i][j].y += a[i].x * b[j].y + a[i].y * b[j].x;
+            }
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gi = i0 + ty + 16 * i;
+        if (gi >= m) continue;
+        R s = alpha;
+        if (rowscale) s *= (R)rowscale[gi / rs_div];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int gj = j0 + tx + 16 * j;
+          if (gj < n) Cm[(long)gi * ldc + gj] = scal(s, acc[i][j]);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 4 x 4 complex double helpers (row-major, fully unrolled)
+// ---------------------------------------------------------------------------
+
+// In-place Cholesky A = L L^H (lower); false if a pivot is not positive/finite.
+__device__ __forceinline__ bool chol4(zd* A) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    double s = A[j * 4 + j].x;
+#pragma unroll
+    for (int k = 0; k < j; ++k) s -= nrm2(A[j * 4 + k]);
+    ok = ok && (s > 0.0) && isfinite(s);
+    const double l = sqrt(fmax(s, 1e-300));
+    const double il = 1.0 / l;
+    A[j * 4 + j] = {l, 0.0};
+#pragma unroll
+    for (int i = j + 1; i < 4; ++i) {
+      zd t = A[i * 4 + j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t = t - mulc(A[i * 4 + k], A[j * 4 + k]);
+      A[i * 4 + j] = scal(il, t);
+    }
+#pragma unroll
+    for (int i = 0; i < j; ++i) A[i * 4 + j] = {0.0, 0.0};
+  }
+  return ok;
+}
+
+// X <- L^{-1} X (forward substitution), L lower with real diagonal.
+__device__ __forceinline__ void trsm_lower(const zd* L, zd* X) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      zd t = X[i * 4 + c];
+#pragma unroll
+      for (int k = 0; k < i; ++k) t = t - L[i * 4 + k] * X[k * 4 + c];
+      X[i * 4 + c] = scal(1.0 / L[i * 4 + i].x, t);
+    }
+  }
+}
+
+// X <- L^{-H} X (back substitution with the conjugate transpose).
+__device__ __forceinline__ void trsm_lower_h(const zd* L, zd* X) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int i = 3; i >= 0; --i) {
+      zd t = X[i * 4 + c];
+#pragma unroll
+      for (int k = i + 1; k < 4; ++k) t = t - cj(L[k * 4 + i]) * X[k * 4 + c];
+      X[i * 4 + c] = scal(1.0 / L[i * 4 + i].x, t);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Largest eigenvalue of a symmetric tridiagonal matrix by multisection on
+// Sturm counts (256 probe points per round, all threads cooperate).
+// ---------------------------------------------------------------------------
+__device__ int sturm_below(const double* a, const double* b, int m, double x) {
+  int cnt = 0;
+  double q = a[0] - x;
+  if (q < 0) ++cnt;
+  for (int i = 1; i < m; ++i) {
+    if (q == 0.0) q = 1e-300;
+    q = a[i] - x - b[i - 1] * b[i - 1] / q;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+
+template <class R>
+__device__ double tridiag_lmax(Smem<R>& sm, int m) {
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? fabs(sm.lb[i - 1]) : 0.0) + (i < m - 1 ? fabs(sm.lb[i]) : 0.0);
+    lo = fmin(lo, sm.la[i] - r);
+    hi = fmax(hi, sm.la[i] + r);
+  }
+  hi += 1e-300 + fabs(hi) * 1e-15;
+  for (int round = 0; round < 8; ++round) {
+    const double w = hi - lo;
+    if (!(w > fabs(hi) * 1e-16)) break;
+    if (threadIdx.x == 0) sm.imin = AMMSE_BLOCK;
+    __syncthreads();
+    const double x = lo + w * (double)(threadIdx.x + 1) / (double)(AMMSE_BLOCK + 1);
+    if (sturm_below(sm.la, sm.lb, m, x) == m) atomicMin(&sm.imin, (int)threadIdx.x);
+    __syncthreads();
+    const int t = sm.imin;
+    const double nhi = (t < AMMSE_BLOCK) ? lo + w * (double)(t + 1) / (double)(AMMSE_BLOCK + 1) : hi;
+    const double nlo = (t > 0) ? lo + w * (double)t / (double)(AMMSE_BLOCK + 1) : lo;
+    lo = nlo;
+    hi = nhi;
+    __syncthreads();
+  }
+  return hi;
+}
+
+__device__ __forceinline__ double rel_change(double a, double b) {
+  if (b > 0) return fabs(a - b) / b;
+  return (a == b) ? 0.0 : INFINITY;
+}
+
+// ---------------------------------------------------------------------------
+// The fused kernel
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_t p) {
+  __shared__ Smem<R> sm;
+  const ammse_desc_t D = p.desc[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int C = D.C, U = D.U, M = D.M, N = D.N, d = D.d, un = D.un;
+  const int b = D.b;
+
+  // ---- per-instance tables in LDS
+  for (int u = tid; u < U; u += AMMSE_BLOCK) {
+    sm.invsig[u] = 1.0 / sqrt(p.sigma2[D.user_off + u]);
+    sm.alpha[u] = p.alpha[D.user_off + u];
+  }
+  if (tid == 0) {
+    int col = 0, u = 0;
+    for (int c = 0; c < C; ++c) {
+      const int n = p.cell_users[D.cell_off + c];
+      sm.cu[c] = n;
+      sm.colOff[c] = col;
+      sm.Pc[c] = p.wsr_only ? 0.0 : p.P[D.bs_off + c];
+      sm.gamma[c] = 0.0;
+      for (int i = 0; i < n; ++i, ++u) {
+        sm.cellOf[u] = c;
+        sm.local[u] = i;
+      }
+      col += n * d;
+    }
+    sm.colOff[C] = col;
+    sm.fail = 0;
+  }
+  __syncthreads();
+
+  const ammse_ws_layout_t L = ammse_ws_layout((int)sizeof(R), U, M, N, d, p.lanczos_steps);
+  char* ws = p.ws + D.ws_off;
+  cx<R>* Gp = (cx<R>*)(ws + L.Gp);
+  cx<R>* Gq = (cx<R>*)(ws + L.Gq);
+  cx<R>* Z = (cx<R>*)(ws + L.Z);
+  cx<R>* Vq = (cx<R>*)(ws + L.Vq);
+  cx<R>* Gr = (cx<R>*)(ws + L.Gr);
+  zd* Jm = (zd*)(ws + L.Jm);
+  zd* Dm = (zd*)(ws + L.Dm);
+  zd* Ym = (zd*)(ws + L.Ym);
+  zd* Lq = (zd*)(ws + L.Lq);
+  zd* Lw = (zd*)(ws + L.Lw);
+  zd* Ly1 = (zd*)(ws + L.Ly1);
+  zd* Ly2 = (zd*)(ws + L.Ly2);
+  const cx<R>* H = (const cx<R>*)p.H + D.h_off;
+  cx<R>* V = (cx<R>*)p.V + D.v_off;
+  const long Vtot = (long)M * D.ud;
+
+  auto channel_product = [&](cx<R>* G, const cx<R>* Vsrc) {
+    for (int c = 0; c < C; ++c) {
+      const int nc = sm.cu[c] * d;
+      if (nc == 0) continue;
+      block_gemm<R, false>(un, nc, M, H + (long)c * un * M, M, Vsrc + (long)M * sm.colOff[c], nc,
+                           G + (long)un * sm.colOff[c], nc, R(1), sm.invsig, N, sm.As, sm.Bs);
+    }
+  };
+
+  // Per-user receiver algebra on G (normalised products of the current V).
+  // Writes alpha_u R_u into sm.rate; keeps UW and E in the caller's registers.
+  auto interference_cov = [&](const cx<R>* G) {
+    const int np = N * (N + 1) / 2;
+    for (int e = tid; e < U * np; e += AMMSE_BLOCK) {
+      const int u = e / np;
+      int q = e % np, n1 = 0;
+      while (q >= N - n1) {
+        q -= N - n1;
+        ++n1;
+      }
+      const int n2 = n1 + q;
+      const int cown = sm.cellOf[u], j0 = sm.local[u] * d;
+      zd acc = {0.0, 0.0};
+      for (int c = 0; c < C; ++c) {
+        const int nc = sm.cu[c] * d;
+        const cx<R>* Gc = G + (long)un * sm.colOff[c];
+        const cx<R>* r1 = Gc + (long)(u * N + n1) * nc;
+        const cx<R>* r2 = Gc + (long)(u * N + n2) * nc;
+        for (int j = 0; j < nc; ++j) {
+          if (c == cown && j >= j0 && j < j0 + d) continue;
+          acc = acc + mulc(to_d(r1[j]), to_d(r2[j]));
+        }
+      }
+      if (n1 == n2) acc = {acc.x + 1.0, 0.0};
+      Jm[u * 16 + n1 * 4 + n2] = acc;
+      Jm[u * 16 + n2 * 4 + n1] = cj(acc);
+    }
+    __syncthreads();
+  };
+
+  auto user_rates = [&](const cx<R>* G, zd* UW, zd* E) {
+    if (tid < U) {
+      const int u = tid;
+      zd J[16], F[16], X[16];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          J[i * 4 + j] = (i < N && j < N) ? Jm[u * 16 + i * 4 + j]
+                                          : zd{(i == j) ? 1.0 : 0.0, 0.0};
+          F[i * 4 + j] = {0.0, 0.0};
+        }
+      const int c = sm.cellOf[u], nc = sm.cu[c] * d, j0 = sm.local[u] * d;
+      const cx<R>* Gc = G + (long)un * sm.colOff[c];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          if (i < N && s < d) F[i * 4 + s] = to_d(Gc[(long)(u * N + i) * nc + j0 + s]);
+      bool ok = chol4(J);
+      trsm_lower(J, F);                           // F = L^{-1} G_own
+#pragma unroll
+      for (int i = 0; i < 4; ++i)                 // X = I + F^H F
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          zd t = {(i == j) ? 1.0 : 0.0, 0.0};
+#pragma unroll
+          for (int k = 0; k < 4; ++k) t = t + mulc(F[k * 4 + j], F[k * 4 + i]);
+          X[i * 4 + j] = t;
+        }
+      trsm_lower_h(J, F);                         // UW = J-^{-1} G_own
+      ok = chol4(X) && ok;                        // W = I + F^H F = Lw Lw^H
+      double r = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) r += 2.0 * log(X[i * 4 + i].x);
+      // E = W^{-1} = Lw^{-H} Lw^{-1}
+      zd Li[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) Li[i] = {((i % 5) == 0) ? 1.0 : 0.0, 0.0};
+      trsm_lower(X, Li);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          zd t = {0.0, 0.0};
+#pragma unroll
+          for (int k = 0; k < 4; ++k) t = t + mulc(Li[k * 4 + j], Li[k * 4 + i]);
+          E[i * 4 + j] = t;
+        }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) UW[i] = F[i];
+      sm.rate[u] = sm.alpha[u] * r;
+      if (!ok) atomicOr(&sm.fail, AMMSE_INST_CHOLESKY);
+    }
+  };
+
+  // WSR in bits of the rates in sm.rate (all threads get the value).
+  auto wsr_sum = [&]() {
+    double v = 0.0;
+    for (int u = tid; u < U; u += AMMSE_BLOCK) v += sm.rate[u];
+    return block_sum(v, sm.red) * (1.0 / M_LN2);
+  };
+
+  // D_u = alpha U W U^H, Y_u = alpha U W into the workspace (padded 4 x 4).
+  auto user_weights = [&](const zd* UW, const zd* E, bool stage2) {
+    if (tid < U) {
+      const int u = tid;
+      const double a = sm.alpha[u];
+      zd T[16];                                   // T = UW E  (= U)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          zd t = {0.0, 0.0};
+#pragma unroll
+          for (int k = 0; k < 4; ++k) t = t + UW[i * 4 + k] * E[k * 4 + j];
+          T[i * 4 + j] = t;
+        }
+      // stage I: W = I, D = a U U^H, Y = a U;  stage II: D = a T UW^H, Y = a UW
+      const zd* Ur = stage2 ? UW : T;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          zd t = {0.0, 0.0};
+#pragma unroll
+          for (int k = 0; k < 4; ++k) t = t + mulc(T[i * 4 + k], Ur[j * 4 + k]);
+          Dm[u * 16 + i * 4 + j] = scal(a, t);
+          Ym[u * 16 + i * 4 + j] = scal(a, Ur[i * 4 + j]);
+        }
+    }
+    __syncthreads();
+    // symmetrise D (exactly Hermitian for the step-size operator)
+    for (int e = tid; e < U * 16; e += AMMSE_BLOCK) {
+      const int u = e >> 4, i = (e >> 2) & 3, j = e & 3;
+      if (i < j) {
+        const zd x = Dm[u * 16 + i * 4 + j], y = Dm[u * 16 + j * 4 + i];
+        const zd m = {0.5 * (x.x + y.x), 0.5 * (x.y - y.y)};
+        Dm[u * 16 + i * 4 + j] = m;
+        Dm[u * 16 + j * 4 + i] = cj(m);
+      } else if (i == j) {
+        Dm[u * 16 + i * 4 + j].y = 0.0;
+      }
+    }
+    __syncthreads();
+  };
+
+  // lambda_max(A_c), A_c = H_c^H S D S H_c, by Lanczos with full
+  // re-orthogonalisation (classical Gram-Schmidt applied twice).
+  auto lanczos_lmax = [&](int c) {
+    const cx<R>* Hc = H + (long)c * un * M;
+    const int m = min(p.lanczos_steps, M);
+    for (int i = tid; i < M; i += AMMSE_BLOCK) {
+      const double s = 1.0 + 0.5 * sin(0.731 * i + 0.25), t = cos(1.37 * i + 0.5);
+      Lq[i] = {s, 0.3 * t};
+    }
+    double nn = 0.0;
+    for (int i = tid; i < M; i += AMMSE_BLOCK) nn += nrm2(Lq[i]);
+    nn = block_sum(nn, sm.red);
+    {
+      const double inv = 1.0 / sqrt(nn);
+      for (int i = tid; i < M; i += AMMSE_BLOCK) Lq[i] = scal(inv, Lq[i]);
+    }
+    __syncthreads();
+    int msz = 0;
+    double beta_prev = 0.0, tmax = 0.0;
+    const int wv = tid >> 6, ln = tid & 63;
+    for (int j = 0; j < m; ++j) {
+      const zd* q = Lq + (long)j * M;
+      // y1 = S H q
+      for (int r = wv; r < un; r += AMMSE_BLOCK / 64) {
+        zd acc = {0.0, 0.0};
+        for (int i = ln; i < M; i += 64) acc = acc + to_d(Hc[(long)r * M + i]) * q[i];
+        acc.x = wave_sum(acc.x);
+        acc.y = wave_sum(acc.y);
+        if (ln == 0) Ly1[r] = scal(sm.invsig[r / N], acc);
+      }
+      __syncthreads();
+      // y2 = S D y1
+      for (int r = tid; r < un; r += AMMSE_BLOCK) {
+        const int u = r / N, n = r % N;
+        zd acc = {0.0, 0.0};
+        for (int k = 0; k < N; ++k) acc = acc + Dm[u * 16 + n * 4 + k] * Ly1[u * N + k];
+        Ly2[r] = scal(sm.invsig[u], acc);
+      }
+      __syncthreads();
+      // w = H^H y2 ; alpha_j = Re q^H w
+      double al = 0.0;
+      for (int i = tid; i < M; i += AMMSE_BLOCK) {
+        zd acc = {0.0, 0.0};
+        for (int r = 0; r < un; ++r) acc = acc + cj(to_d(Hc[(long)r * M + i])) * Ly2[r];
+        Lw[i] = acc;
+        al += q[i].x * acc.x + q[i].y * acc.y;
+      }
+      al = block_sum(al, sm.red);
+      for (int i = tid; i < M; i += AMMSE_BLOCK) {
+        zd w = Lw[i] - scal(al, q[i]);
+        if (j > 0) w = w - scal(beta_prev, Lq[(long)(j - 1) * M + i]);
+        Lw[i] = w;
+      }
+      __syncthreads();
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int k = tid; k <= j; k += AMMSE_BLOCK) {
+          const zd* qk = Lq + (long)k * M;
+          zd h = {0.0, 0.0};
+          for (int i = 0; i < M; ++i) h = h + mulc(Lw[i], qk[i]);
+          sm.h[k] = h;
+        }
+        __syncthreads();
+        for (int i = tid; i < M; i += AMMSE_BLOCK) {
+          zd w = Lw[i];
+          for (int k = 0; k <= j; ++k) w = w - sm.h[k] * Lq[(long)k * M + i];
+          Lw[i] = w;
+        }
+        __syncthreads();
+      }
+      double bb = 0.0;
+      for (int i = tid; i < M; i += AMMSE_BLOCK) bb += nrm2(Lw[i]);
+      bb = sqrt(block_sum(bb, sm.red));
+      if (tid == 0) {
+        sm.la[j] = al;
+        sm.lb[j] = bb;
+      }
+      msz = j + 1;
+      tmax = fmax(tmax, fabs(al) + bb);
+      if (!(bb > 1e-13 * tmax)) break;
+      const double ib = 1.0 / bb;
+      zd* qn = Lq + (long)(j + 1) * M;
+      for (int i = tid; i < M; i += AMMSE_BLOCK) qn[i] = scal(ib, Lw[i]);
+      beta_prev = bb;
+      __syncthreads();
+    }
+    __syncthreads();
+    if (!(tmax > 0.0)) return 0.0;
+    return tridiag_lmax(sm, msz);
+  };
+
+  // ---- initial state: G^0, copies for the t = 1 extrapolation
+  channel_product(Gp, V);
+  __syncthreads();
+  const int T = p.wsr_only ? 0 : p.max_iters;
+  if (!p.wsr_only) {
+    for (long e = tid; e < Vtot; e += AMMSE_BLOCK) Vq[e] = V[e];
+    for (long e = tid; e < (long)un * D.ud; e += AMMSE_BLOCK) Gq[e] = Gp[e];
+  }
+  __syncthreads();
+
+  int fsw = p.force_switch_iter;
+  if (p.force_switch && p.force_switch[b] > 0) fsw = p.force_switch[b];
+  bool stage2 = (fsw >= 1) ? (fsw <= 1) : (p.warm_start == 0);
+  int switch_iter = stage2 ? 1 : -1;
+  bool prev_step_stage2 = false;
+  double wsr_prev = 0.0, wsr_prev2 = 0.0;   // WSR(V^{t-1}), WSR(V^{t-2})
+  int iters_run = 0;
+  int status = 0;
+  zd UW[16], E[16];
+
+  for (int t = 1; t <= T; ++t) {
+    // receivers and rate of V^{t-1}
+    interference_cov(Gp);
+    user_rates(Gp, UW, E);
+    __syncthreads();
+    wsr_prev2 = wsr_prev;
+    wsr_prev = wsr_sum();
+    if (p.trace) {
+      if (tid == 0) p.trace[(long)b * p.trace_len + (t - 1)] = wsr_prev;
+    }
+    if (sm.fail) {
+      status |= sm.fail;
+      break;
+    }
+    if (!isfinite(wsr_prev)) {
+      status |= AMMSE_INST_NONFINITE;
+      break;
+    }
+    if (p.eps2 > 0 && t >= 2 && prev_step_stage2 && rel_change(wsr_prev, wsr_prev2) <= p.eps2)
+      break;
+    if (!stage2) {
+      const bool trig = (fsw >= 1) ? (t >= fsw)
+                                   : (t >= 2 && rel_change(wsr_prev, wsr_prev2) <= p.eps1);
+      if (trig) {
+        stage2 = true;
+        switch_iter = t;
+      }
+    }
+    user_weights(UW, E, stage2);
+
+    // step size
+    const bool adaptive = t <= p.T_c || (p.rearm && switch_iter >= 1 && t >= switch_iter &&
+                                         t < switch_iter + p.T_c);
+    if (adaptive) {
+      for (int c = 0; c < C; ++c) {
+        const double lm = (sm.cu[c] > 0) ? lanczos_lmax(c) : 0.0;
+        if (tid == 0) sm.gamma[c] = (lm > 0.0) ? 1.0 / (2.0 * lm) : 0.0;
+        __syncthreads();
+      }
+    } else if (p.gamma_c > 0.0) {
+      if (tid < C) sm.gamma[tid] = p.gamma_c;
+      __syncthreads();
+    }
+
+    // Z = S (D G^ - Y), G^ = (1+w) G^{t-1} - w G^{t-2}
+    const double om = p.extrapolate ? fmax((t - 2.0) / (t + 1.0), 0.0) : 0.0;
+    for (int c = 0; c < C; ++c) {
+      const int nc = sm.cu[c] * d;
+      const long base = (long)un * sm.colOff[c];
+      for (long e = tid; e < (long)un * nc; e += AMMSE_BLOCK) {
+        const int r = (int)(e / nc), j = (int)(e % nc);
+        const int u = r / N, n = r % N;
+        zd acc = {0.0, 0.0};
+        for (int k = 0; k < N; ++k) {
+          const long idx = base + (long)(u * N + k) * nc + j;
+          const zd gh = {(1.0 + om) * (double)Gp[idx].x - om * (double)Gq[idx].x,
+                         (1.0 + om) * (double)Gp[idx].y - om * (double)Gq[idx].y};
+          acc = acc + Dm[u * 16 + n * 4 + k] * gh;
+        }
+        if (sm.cellOf[u] == c && j / d == sm.local[u]) acc = acc - Ym[u * 16 + n * 4 + (j % d)];
+        Z[base + e] = from_d<R>(scal(sm.invsig[u], acc));
+      }
+    }
+    __syncthreads();
+
+    // gradient: Gr_c = 2 H_c^H Z_c
+    for (int c = 0; c < C; ++c) {
+      const int nc = sm.cu[c] * d;
+      if (nc == 0) continue;
+      block_gemm<R, true>(M, nc, un, H + (long)c * un * M, M, Z + (long)un * sm.colOff[c], nc,
+                          Gr + (long)M * sm.colOff[c], nc, R(2), nullptr, 1, sm.As, sm.Bs);
+    }
+    __syncthreads();
+
+    // extrapolated projected step per BS
+    for (int c = 0; c < C; ++c) {
+      const int nc = sm.cu[c] * d;
+      const long base = (long)M * sm.colOff[c];
+      const long n = (long)M * nc;
+      const double g = sm.gamma[c];
+      double pw = 0.0;
+      for (long e = tid; e < n; e += AMMSE_BLOCK) {
+        const zd v = to_d(V[base + e]), vq = to_d(Vq[base + e]), gr = to_d(Gr[base + e]);
+        const zd x = {(1.0 + om) * v.x - om * vq.x - g * gr.x, (1.0 + om) * v.y - om * vq.y - g * gr.y};
+        const cx<R> xs = from_d<R>(x);
+        Gr[base + e] = xs;
+        pw += nrm2(to_d(xs));
+      }
+      pw = block_sum(pw, sm.red);
+      const double s = (pw > sm.Pc[c]) ? sqrt(sm.Pc[c] / pw) : 1.0;
+      for (long e = tid; e < n; e += AMMSE_BLOCK) {
+        Vq[base + e] = V[base + e];
+        V[base + e] = from_d<R>(scal(s, to_d(Gr[base + e])));
+      }
+    }
+    __syncthreads();
+
+    // G^{t} = S H V^t ; keep G^{t-1}
+    {
+      cx<R>* tmp = Gq;
+      Gq = Gp;
+      Gp = tmp;
+    }
+    channel_product(Gp, V);
+    __syncthreads();
+    prev_step_stage2 = stage2;
+    iters_run = t;
+  }
+
+  // ---- WSR of the returned precoders
+  double wsr_final;
+  if (iters_run == T && !status) {
+    interference_cov(Gp);
+    user_rates(Gp, UW, E);
+    __syncthreads();
+    wsr_final = wsr_sum();
+    if (sm.fail) status |= sm.fail;
+    if (!isfinite(wsr_final)) status |= AMMSE_INST_NONFINITE;
+    if (p.trace && tid == 0) p.trace[(long)b * p.trace_len + T] = wsr_final;
+  } else {
+    wsr_final = wsr_prev;   // stopped early: V holds V^{iters_run}, WSR already known
+  }
+  // zero-power check
+  for (int c = 0; c < C; ++c) {
+    const long base = (long)M * sm.colOff[c];
+    const long n = (long)M * sm.cu[c] * d;
+    double pw = 0.0;
+    for (long e = tid; e < n; e += AMMSE_BLOCK) pw += nrm2(to_d(V[base + e]));
+    pw = block_sum(pw, sm.red);
+    if (n > 0 && pw == 0.0) status |= AMMSE_INST_ZERO_POWER;
+  }
+  if (tid == 0) {
+    p.wsr[b] = wsr_final;
+    if (p.iters) p.iters[b] = iters_run;
+    if (p.switch_iter) p.switch_iter[b] = p.wsr_only ? -1 : switch_iter;
+    if (p.status) p.status[b] = status;
+  }
+  if (p.trace) {
+    const int last = (iters_run == T && !(status & (AMMSE_INST_CHOLESKY | AMMSE_INST_NONFINITE)))
+                         ? T : iters_run;
+    for (int k = last + 1 + tid; k <= T; k += AMMSE_BLOCK)
+      p.trace[(long)b * p.trace_len + k] = NAN;
+  }
+}
+
+}  // namespace
+
+hipError_t ammse_launch_fp64(const ammse_kparams_t& p, hipStream_t s) {
+  hipLaunchKernelGGL(ammse_solve_kernel<double>, dim3(p.batch), dim3(AMMSE_BLOCK), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t ammse_launch_fp32(const ammse_kparams_t& p, hipStream_t s) {
+  hipLaunchKernelGGL(ammse_solve_kernel<float>, dim3(p.batch), dim3(AMMSE_BLOCK), 0, s, p);
+  return hipGetLastError();
+}
