@@ -1,0 +1,262 @@
+#!/usr/bin/env python3
+"""Benchmark of batched A-MMMSE precoding on one MI355X.
+
+Workload (one "step"): the single-cell Rayleigh sweep - 1024 independent
+channel realisations (M = 64 BS antennas, 16 users, N = 4 receive antennas,
+d = 4 streams, sigma2 = 1, alpha ~ U[0.5, 1.5], 256 instances at each of
+P = 0, 10, 20, 30 dB), 100 A-MMMSE iterations with the two-stage warm start,
+FP32 channel products - solved by ONE ammse_solve launch from device-resident
+inputs.
+
+Metric: instances per second whose final WSR reaches 99 % of the FP64 WMMSE
+reference WSR of the same instance (stored by tests/golden/make_wmmse_reference.py
+from the CPU oracle).  Printed as one JSON line, with the roofline of the solve
+kernel (HIP events on the launch stream), the same count for the plain
+per-instance form (one launch per instance) on the same GPU, and the CPU
+oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2]
+    python bench.py --parse-pmc DIR_FETCH DIR_WRITE   # HBM traffic from rocprofv3 --pmc
+"""
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+REF_FILE = os.path.join(ROOT, "tests", "golden", "wmmse_ref_rayleigh_sweep4x256.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ammse_solve_fp32_rayleigh_sweep1024_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2510_20507_amd", "csrc", f)
+                  for f in ("ammse_kernels.hip", "ammse_internal.h")]
+PEAK_FP32_MFMA_TFLOPS = 157.3
+ITERS = 100
+CALIB_COPY_MIB = 1024
+
+
+def kernel_sha() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_sha") != kernel_sha():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(batch, ref, per_p: int = 16):
+    """FP64 oracle A-MMMSE (as it stands) on a bounded sample of the workload."""
+    import oracle as O
+    workers = max(1, min(16, os.cpu_count() or 1))
+    idx = [k * 256 + i for k in range(4) for i in range(per_p)]
+    insts = [batch.instance(i) for i in idx]
+    t0 = time.perf_counter()
+    res = O.solve_batch(insts, "ammmse", workers=workers, iters=ITERS)
+    dt = time.perf_counter() - t0
+    ok = sum(1 for r, i in zip(res, idx) if r["wsr"] >= 0.99 * ref[i])
+    return {"value": ok / dt, "unit": "instances/s", "cores": workers, "kind": "oracle",
+            "sample": f"{len(idx)} of the {batch.batch} instances ({per_p} per SNR), "
+                      f"{ITERS} iterations, FP64 NumPy, process pool of {workers}",
+            "seconds": dt, "reached_99": ok}
+
+
+def plain_per_instance(batch, ref, opts, per_p: int = 8, reps: int = 2):
+    """The plain form on the same GPU: one plan and one launch per instance."""
+    import torch
+    from paper_2510_20507_amd import ammse
+    idx = [k * 256 + i for k in range(4) for i in range(per_p)]
+    runs = []
+    for i in idx:
+        sub = batch.subset([i])
+        db = ammse.to_device(sub, opts.precision)
+        plan = ammse.Plan(db.table, db.cell_users, opts)
+        ws = plan.workspace()
+        V = torch.empty_like(db.V0)
+        wsr = torch.empty(1, dtype=torch.float64, device="cuda")
+        runs.append((plan, db, ws, V, wsr))
+    for plan, db, ws, V, wsr in runs:            # warm-up
+        V.copy_(db.V0)
+        plan.solve(db.H, db.sigma2, db.alpha, db.P, V, wsr, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for plan, db, ws, V, wsr in runs:
+            V.copy_(db.V0)
+            plan.solve(db.H, db.sigma2, db.alpha, db.P, V, wsr, workspace=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ok = sum(1 for (plan, db, ws, V, wsr), i in zip(runs, idx)
+             if float(wsr.item()) >= 0.99 * ref[i])
+    for r in runs:
+        r[0].close()
+    return {"value": ok / dt, "unit": "instances/s", "instances": len(idx),
+            "ms_per_instance": dt / len(idx) * 1e3, "reached_99": ok}
+
+
+def parse_pmc(dirs):
+    """Sum FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the solve kernel and of
+    the calibration copy from rocprofv3 --pmc CSV output directories."""
+    out = {}
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection*.csv"), recursive=True):
+            with open(f) as fh:
+                for row in csv.DictReader(fh):
+                    name = row.get("Kernel_Name", "")
+                    cname = row.get("Counter_Name", "")
+                    val = float(row.get("Counter_Value", 0) or 0)
+                    kind = ("solve" if "ammse_solve_kernel" in name else
+                            "copy" if ("copy" in name.lower() or "elementwise" in name.lower())
+                            else None)
+                    if kind is None:
+                        continue
+                    key = (kind, cname, row.get("Dispatch_Id", row.get("Correlation_Id", "")))
+                    out[key] = out.get(key, 0.0) + val
+    agg = {}
+    for (kind, cname, _), v in out.items():
+        agg.setdefault((kind, cname), []).append(v)
+    return {f"{k[0]}:{k[1]}": (float(np.mean(v)), len(v)) for k, v in agg.items()}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help=f"also run a {CALIB_COPY_MIB} MiB device copy (counter calibration)")
+    ap.add_argument("--parse-pmc", nargs="+", metavar="DIR")
+    a = ap.parse_args()
+
+    if a.parse_pmc:
+        print(json.dumps(parse_pmc(a.parse_pmc), indent=1))
+        return 0
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); instances "
+              "are independent, so a multi-GPU run would shard the batch with no communication.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2510_20507_amd import ammse, synth
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    ammse.lib()
+
+    batch = synth.rayleigh_sweep(B_per_p=256)
+    with open(REF_FILE) as f:
+        refj = json.load(f)
+    ref = np.asarray(refj["wsr"])
+    assert refj["workload"] == batch.name and ref.shape == (batch.batch,)
+
+    opts = ammse.Options(precision=ammse.PREC_FP32, max_iters=ITERS)
+    db = ammse.to_device(batch, opts.precision)
+    plan = ammse.Plan(db.table, db.cell_users, opts)
+    ws = plan.workspace()
+    B = batch.batch
+    V = torch.empty_like(db.V0)
+    wsr = torch.empty(B, dtype=torch.float64, device="cuda")
+    status = torch.empty(B, dtype=torch.int32, device="cuda")
+    sw = torch.empty(B, dtype=torch.int32, device="cuda")
+
+    def step(ev0=None, ev1=None):
+        V.copy_(db.V0)
+        if ev0 is not None:
+            ev0.record()
+        plan.solve(db.H, db.sigma2, db.alpha, db.P, V, wsr, None, sw, status, workspace=ws)
+        if ev1 is not None:
+            ev1.record()
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        step(e0, e1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+    ms_per_step = dt / a.steps * 1e3
+
+    w = wsr.cpu().numpy()
+    st = status.cpu().numpy()
+    reached = (w >= 0.99 * ref) & (st == 0)
+    S = int(reached.sum())
+    value = S / (ms_per_step / 1e3)
+
+    flops = float(batch.total_flops_per_iter().sum()) * ITERS
+    achieved = flops / (kern_ms / 1e3) / 1e12
+    traffic = read_traffic()
+    line = {
+        "metric": "instances/s reaching 99% of FP64 WMMSE WSR; batched/mixed vs plain, same GPU",
+        "value": value,
+        "unit": "instances/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": batch.name, "instances": B, "M": 64, "users": 16, "N": 4, "d": 4,
+                   "snr_db": [0, 10, 20, 30], "iters": ITERS, "precision": "fp32",
+                   "algorithm": "A-MMMSE (warm start eps1=0.1, T_c=3, extrapolation)"},
+        "reached_99": S,
+        "reached_99_by_snr": {str(db_): int(reached[k * 256:(k + 1) * 256].sum())
+                              for k, db_ in enumerate((0, 10, 20, 30))},
+        "instances_per_s_all": B / (ms_per_step / 1e3),
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
+                     "traffic": traffic, "kernel": "ammse_solve_kernel<float>",
+                     "kernel_ms": kern_ms, "flops_per_launch": flops},
+    }
+    if not a.no_plain:
+        line["plain_per_instance"] = plain_per_instance(batch, ref, opts)
+    if a.calib_copy:
+        n = CALIB_COPY_MIB * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        line["calib_copy_bytes"] = n * 4
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(batch, ref)
+    print(json.dumps(line), flush=True)
+    plan.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,170 @@
+// Device-side helpers shared by the solve kernels of libammse (gfx950).
+#pragma once
+
+#include <math.h>
+
+#include "ammse_internal.h"
+
+namespace ammse_dev {
+
+
+template <class R>
+struct cx {
+  R x, y;
+};
+
+template <class R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <class R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <class R>
+__device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <class R>
+__device__ __forceinline__ cx<R> scal(R s, cx<R> a) { return {s * a.x, s * a.y}; }
+template <class R>
+__device__ __forceinline__ cx<R> cj(cx<R> a) { return {a.x, -a.y}; }
+// a * conj(b)
+template <class R>
+__device__ __forceinline__ cx<R> mulc(cx<R> a, cx<R> b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <class R>
+__device__ __forceinline__ R nrm2(cx<R> a) { return a.x * a.x + a.y * a.y; }
+
+using zd = cx<double>;
+
+template <class R>
+__device__ __forceinline__ zd to_d(cx<R> a) { return {(double)a.x, (double)a.y}; }
+template <class R>
+__device__ __forceinline__ cx<R> from_d(zd a) { return {(R)a.x, (R)a.y}; }
+
+// Sum over the block (a multiple of 64 threads, at most 512); every thread
+// receives the same value.
+__device__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+  return s;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// 4 x 4 complex double helpers (row-major, fully unrolled)
+// ---------------------------------------------------------------------------
+
+// In-place Cholesky A = L L^H (lower); false if a pivot is not positive/finite.
+__device__ __forceinline__ bool chol4(zd* A) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    double s = A[j * 4 + j].x;
+#pragma unroll
+    for (int k = 0; k < j; ++k) s -= nrm2(A[j * 4 + k]);
+    ok = ok && (s > 0.0) && isfinite(s);
+    const double l = sqrt(fmax(s, 1e-300));
+    const double il = 1.0 / l;
+    A[j * 4 + j] = {l, 0.0};
+#pragma unroll
+    for (int i = j + 1; i < 4; ++i) {
+      zd t = A[i * 4 + j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t = t - mulc(A[i * 4 + k], A[j * 4 + k]);
+      A[i * 4 + j] = scal(il, t);
+    }
+#pragma unroll
+    for (int i = 0; i < j; ++i) A[i * 4 + j] = {0.0, 0.0};
+  }
+  return ok;
+}
+
+// X <- L^{-1} X (forward substitution), L lower with real diagonal.
+__device__ __forceinline__ void trsm_lower(const zd* L, zd* X) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      zd t = X[i * 4 + c];
+#pragma unroll
+      for (int k = 0; k < i; ++k) t = t - L[i * 4 + k] * X[k * 4 + c];
+      X[i * 4 + c] = scal(1.0 / L[i * 4 + i].x, t);
+    }
+  }
+}
+
+// X <- L^{-H} X (back substitution with the conjugate transpose).
+__device__ __forceinline__ void trsm_lower_h(const zd* L, zd* X) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int i = 3; i >= 0; --i) {
+      zd t = X[i * 4 + c];
+#pragma unroll
+      for (int k = i + 1; k < 4; ++k) t = t - cj(L[k * 4 + i]) * X[k * 4 + c];
+      X[i * 4 + c] = scal(1.0 / L[i * 4 + i].x, t);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Largest eigenvalue of a symmetric tridiagonal matrix by multisection on
+// Sturm counts (256 probe points per round, all threads cooperate).
+// ---------------------------------------------------------------------------
+__device__ int sturm_below(const double* a, const double* b, int m, double x) {
+  int cnt = 0;
+  double q = a[0] - x;
+  if (q < 0) ++cnt;
+  for (int i = 1; i < m; ++i) {
+    if (q == 0.0) q = 1e-300;
+    q = a[i] - x - b[i - 1] * b[i - 1] / q;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+
+// la, lb: diagonal and off-diagonal in LDS; imin: an LDS int used for the
+// reduction.  Every thread of the block must call it.
+__device__ double tridiag_lmax(const double* la, const double* lb, int m, int* imin) {
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? fabs(lb[i - 1]) : 0.0) + (i < m - 1 ? fabs(lb[i]) : 0.0);
+    lo = fmin(lo, la[i] - r);
+    hi = fmax(hi, la[i] + r);
+  }
+  hi += 1e-300 + fabs(hi) * 1e-15;
+  for (int round = 0; round < 8; ++round) {
+    const double w = hi - lo;
+    if (!(w > fabs(hi) * 1e-16)) break;
+    if (threadIdx.x == 0) *imin = blockDim.x;
+    __syncthreads();
+    const double x = lo + w * (double)(threadIdx.x + 1) / (double)(blockDim.x + 1);
+    if (sturm_below(la, lb, m, x) == m) atomicMin(imin, (int)threadIdx.x);
+    __syncthreads();
+    const int t = *imin;
+    const double nhi = (t < (int)blockDim.x) ? lo + w * (double)(t + 1) / (double)(blockDim.x + 1) : hi;
+    const double nlo = (t > 0) ? lo + w * (double)t / (double)(blockDim.x + 1) : lo;
+    lo = nlo;
+    hi = nhi;
+    __syncthreads();
+  }
+  return hi;
+}
+
+__device__ __forceinline__ double rel_change(double a, double b) {
+  if (b > 0) return fabs(a - b) / b;
+  return (a == b) ? 0.0 : INFINITY;
+}
+
+
+}  // namespace ammse_dev

@@ -78,7 +78,7 @@ __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int
   L.Jm = o;  o += ammse_align256((size_t)U * 16 * zs);
   L.Dm = o;  o += ammse_align256((size_t)U * 16 * zs);
   L.Ym = o;  o += ammse_align256((size_t)U * 16 * zs);
-  L.Lq = o;  o += ammse_align256((size_t)(lanczos_steps + 1) * M * zs);
+  L.Lq = o;  o += ammse_align256((size_t)3 * M * zs);   // three Lanczos vectors
   L.Lw = o;  o += ammse_align256((size_t)M * zs);
   L.Ly1 = o; o += ammse_align256(un * zs);
   L.Ly2 = o; o += ammse_align256(un * zs);

@@ -25,39 +25,10 @@
 
 #include "ammse_internal.h"
 
+#include "ammse_device.h"
+
 namespace {
-
-template <class R>
-struct cx {
-  R x, y;
-};
-
-template <class R>
-__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.x + b.x, a.y + b.y}; }
-template <class R>
-__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.x - b.x, a.y - b.y}; }
-template <class R>
-__device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b) {
-  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-template <class R>
-__device__ __forceinline__ cx<R> scal(R s, cx<R> a) { return {s * a.x, s * a.y}; }
-template <class R>
-__device__ __forceinline__ cx<R> cj(cx<R> a) { return {a.x, -a.y}; }
-// a * conj(b)
-template <class R>
-__device__ __forceinline__ cx<R> mulc(cx<R> a, cx<R> b) {
-  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
-}
-template <class R>
-__device__ __forceinline__ R nrm2(cx<R> a) { return a.x * a.x + a.y * a.y; }
-
-using zd = cx<double>;
-
-template <class R>
-__device__ __forceinline__ zd to_d(cx<R> a) { return {(double)a.x, (double)a.y}; }
-template <class R>
-__device__ __forceinline__ cx<R> from_d(zd a) { return {(R)a.x, (R)a.y}; }
+using namespace ammse_dev;
 
 constexpr int KC = 16;   // k-chunk of the channel products
 constexpr int TM = 64;   // output tile rows
@@ -83,23 +54,6 @@ struct Smem {
   int fail;
   int imin;
 };
-
-// Sum over the 256 threads; every thread receives the same value.
-__device__ double block_sum(double v, double* red) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[w] = v;
-  __syncthreads();
-  return (red[0] + red[1]) + (red[2] + red[3]);
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 // C (m x n) = alpha * op(A) * B, row i of C further scaled by rowscale[i / rs_div]
 // when rowscale != nullptr.  op(A) = A (m x k, row-major, lda) or, with CONJA,
@@ -173,111 +127,6 @@ __device__ void block_gemm(int m, int n, int k, const cx<R>* __restrict__ A, lon
       }
     }
   }
-}
-
-// ---------------------------------------------------------------------------
-// 4 x 4 complex double helpers (row-major, fully unrolled)
-// ---------------------------------------------------------------------------
-
-// In-place Cholesky A = L L^H (lower); false if a pivot is not positive/finite.
-__device__ __forceinline__ bool chol4(zd* A) {
-  bool ok = true;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    double s = A[j * 4 + j].x;
-#pragma unroll
-    for (int k = 0; k < j; ++k) s -= nrm2(A[j * 4 + k]);
-    ok = ok && (s > 0.0) && isfinite(s);
-    const double l = sqrt(fmax(s, 1e-300));
-    const double il = 1.0 / l;
-    A[j * 4 + j] = {l, 0.0};
-#pragma unroll
-    for (int i = j + 1; i < 4; ++i) {
-      zd t = A[i * 4 + j];
-#pragma unroll
-      for (int k = 0; k < j; ++k) t = t - mulc(A[i * 4 + k], A[j * 4 + k]);
-      A[i * 4 + j] = scal(il, t);
-    }
-#pragma unroll
-    for (int i = 0; i < j; ++i) A[i * 4 + j] = {0.0, 0.0};
-  }
-  return ok;
-}
-
-// X <- L^{-1} X (forward substitution), L lower with real diagonal.
-__device__ __forceinline__ void trsm_lower(const zd* L, zd* X) {
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      zd t = X[i * 4 + c];
-#pragma unroll
-      for (int k = 0; k < i; ++k) t = t - L[i * 4 + k] * X[k * 4 + c];
-      X[i * 4 + c] = scal(1.0 / L[i * 4 + i].x, t);
-    }
-  }
-}
-
-// X <- L^{-H} X (back substitution with the conjugate transpose).
-__device__ __forceinline__ void trsm_lower_h(const zd* L, zd* X) {
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-#pragma unroll
-    for (int i = 3; i >= 0; --i) {
-      zd t = X[i * 4 + c];
-#pragma unroll
-      for (int k = i + 1; k < 4; ++k) t = t - cj(L[k * 4 + i]) * X[k * 4 + c];
-      X[i * 4 + c] = scal(1.0 / L[i * 4 + i].x, t);
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Largest eigenvalue of a symmetric tridiagonal matrix by multisection on
-// Sturm counts (256 probe points per round, all threads cooperate).
-// ---------------------------------------------------------------------------
-__device__ int sturm_below(const double* a, const double* b, int m, double x) {
-  int cnt = 0;
-  double q = a[0] - x;
-  if (q < 0) ++cnt;
-  for (int i = 1; i < m; ++i) {
-    if (q == 0.0) q = 1e-300;
-    q = a[i] - x - b[i - 1] * b[i - 1] / q;
-    if (q < 0) ++cnt;
-  }
-  return cnt;
-}
-
-template <class R>
-__device__ double tridiag_lmax(Smem<R>& sm, int m) {
-  double lo = 1e300, hi = -1e300;
-  for (int i = 0; i < m; ++i) {
-    const double r = (i > 0 ? fabs(sm.lb[i - 1]) : 0.0) + (i < m - 1 ? fabs(sm.lb[i]) : 0.0);
-    lo = fmin(lo, sm.la[i] - r);
-    hi = fmax(hi, sm.la[i] + r);
-  }
-  hi += 1e-300 + fabs(hi) * 1e-15;
-  for (int round = 0; round < 8; ++round) {
-    const double w = hi - lo;
-    if (!(w > fabs(hi) * 1e-16)) break;
-    if (threadIdx.x == 0) sm.imin = AMMSE_BLOCK;
-    __syncthreads();
-    const double x = lo + w * (double)(threadIdx.x + 1) / (double)(AMMSE_BLOCK + 1);
-    if (sturm_below(sm.la, sm.lb, m, x) == m) atomicMin(&sm.imin, (int)threadIdx.x);
-    __syncthreads();
-    const int t = sm.imin;
-    const double nhi = (t < AMMSE_BLOCK) ? lo + w * (double)(t + 1) / (double)(AMMSE_BLOCK + 1) : hi;
-    const double nlo = (t > 0) ? lo + w * (double)t / (double)(AMMSE_BLOCK + 1) : lo;
-    lo = nlo;
-    hi = nhi;
-    __syncthreads();
-  }
-  return hi;
-}
-
-__device__ __forceinline__ double rel_change(double a, double b) {
-  if (b > 0) return fabs(a - b) / b;
-  return (a == b) ? 0.0 : INFINITY;
 }
 
 // ---------------------------------------------------------------------------
@@ -480,8 +329,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
     __syncthreads();
   };
 
-  // lambda_max(A_c), A_c = H_c^H S D S H_c, by Lanczos with full
-  // re-orthogonalisation (classical Gram-Schmidt applied twice).
+  // lambda_max(A_c), A_c = H_c^H S D S H_c, by Lanczos.
   auto lanczos_lmax = [&](int c) {
     const cx<R>* Hc = H + (long)c * un * M;
     const int m = min(p.lanczos_steps, M);
@@ -497,15 +345,26 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
       for (int i = tid; i < M; i += AMMSE_BLOCK) Lq[i] = scal(inv, Lq[i]);
     }
     __syncthreads();
+    // plain three-term Lanczos: the largest Ritz value converges to
+    // lambda_max without re-orthogonalisation (lost orthogonality only adds
+    // copies of converged eigenvalues); convergence is tested every 8 steps
+    const double ltol = (sizeof(R) == 8) ? 1e-14 : 1e-10;
+    zd* qa = Lq;            // q_{j-1}
+    zd* qb = Lq + M;        // q_j
+    zd* qc = Lq + 2 * M;    // w
+    for (int i = tid; i < M; i += AMMSE_BLOCK) {
+      qb[i] = Lq[i];
+      qa[i] = {0.0, 0.0};
+    }
+    __syncthreads();
     int msz = 0;
-    double beta_prev = 0.0, tmax = 0.0;
+    double beta_prev = 0.0, tmax = 0.0, theta = 0.0;
     const int wv = tid >> 6, ln = tid & 63;
     for (int j = 0; j < m; ++j) {
-      const zd* q = Lq + (long)j * M;
       // y1 = S H q
       for (int r = wv; r < un; r += AMMSE_BLOCK / 64) {
         zd acc = {0.0, 0.0};
-        for (int i = ln; i < M; i += 64) acc = acc + to_d(Hc[(long)r * M + i]) * q[i];
+        for (int i = ln; i < M; i += 64) acc = acc + to_d(Hc[(long)r * M + i]) * qb[i];
         acc.x = wave_sum(acc.x);
         acc.y = wave_sum(acc.y);
         if (ln == 0) Ly1[r] = scal(sm.invsig[r / N], acc);
@@ -523,34 +382,18 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
       double al = 0.0;
       for (int i = tid; i < M; i += AMMSE_BLOCK) {
         zd acc = {0.0, 0.0};
+#pragma unroll 8
         for (int r = 0; r < un; ++r) acc = acc + cj(to_d(Hc[(long)r * M + i])) * Ly2[r];
-        Lw[i] = acc;
-        al += q[i].x * acc.x + q[i].y * acc.y;
+        qc[i] = acc;
+        al += qb[i].x * acc.x + qb[i].y * acc.y;
       }
       al = block_sum(al, sm.red);
-      for (int i = tid; i < M; i += AMMSE_BLOCK) {
-        zd w = Lw[i] - scal(al, q[i]);
-        if (j > 0) w = w - scal(beta_prev, Lq[(long)(j - 1) * M + i]);
-        Lw[i] = w;
-      }
-      __syncthreads();
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int k = tid; k <= j; k += AMMSE_BLOCK) {
-          const zd* qk = Lq + (long)k * M;
-          zd h = {0.0, 0.0};
-          for (int i = 0; i < M; ++i) h = h + mulc(Lw[i], qk[i]);
-          sm.h[k] = h;
-        }
-        __syncthreads();
-        for (int i = tid; i < M; i += AMMSE_BLOCK) {
-          zd w = Lw[i];
-          for (int k = 0; k <= j; ++k) w = w - sm.h[k] * Lq[(long)k * M + i];
-          Lw[i] = w;
-        }
-        __syncthreads();
-      }
       double bb = 0.0;
-      for (int i = tid; i < M; i += AMMSE_BLOCK) bb += nrm2(Lw[i]);
+      for (int i = tid; i < M; i += AMMSE_BLOCK) {
+        const zd w = qc[i] - scal(al, qb[i]) - scal(beta_prev, qa[i]);
+        qc[i] = w;
+        bb += nrm2(w);
+      }
       bb = sqrt(block_sum(bb, sm.red));
       if (tid == 0) {
         sm.la[j] = al;
@@ -558,16 +401,24 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
       }
       msz = j + 1;
       tmax = fmax(tmax, fabs(al) + bb);
-      if (!(bb > 1e-13 * tmax)) break;
+      const bool breakdown = !(bb > 1e-13 * tmax);
+      if (breakdown || (msz % 8) == 0 || msz == m) {
+        __syncthreads();
+        const double th = (tmax > 0.0) ? tridiag_lmax(sm.la, sm.lb, msz, &sm.imin) : 0.0;
+        const bool conv = fabs(th - theta) <= ltol * fabs(th);
+        theta = th;
+        if (breakdown || conv) break;
+      }
       const double ib = 1.0 / bb;
-      zd* qn = Lq + (long)(j + 1) * M;
-      for (int i = tid; i < M; i += AMMSE_BLOCK) qn[i] = scal(ib, Lw[i]);
+      for (int i = tid; i < M; i += AMMSE_BLOCK) {
+        qa[i] = qb[i];
+        qb[i] = scal(ib, qc[i]);
+      }
       beta_prev = bb;
       __syncthreads();
     }
     __syncthreads();
-    if (!(tmax > 0.0)) return 0.0;
-    return tridiag_lmax(sm, msz);
+    return theta;
   };
 
   // ---- initial state: G^0, copies for the t = 1 extrapolation
