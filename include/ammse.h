@@ -64,6 +64,10 @@ typedef int32_t ammse_status_t;
 #define AMMSE_PREC_FP32 1       /* channel products in float; N x N, d x d work,
                                    step size and projection in double */
 
+/* Kernel selection (ammse_options_t.path). */
+#define AMMSE_PATH_AUTO 0
+#define AMMSE_PATH_GENERAL 1
+
 /* Limits of this build. */
 #define AMMSE_MAX_CELLS 16
 #define AMMSE_MAX_RX 4          /* N <= 4 (the paper's d <= N <= 4 regime) */
@@ -106,6 +110,10 @@ typedef struct ammse_options_t {
   int32_t force_switch_iter; /* -1: switch by the eps1 rule; s >= 1: first stage-II
                                 iteration is s for every instance */
   int32_t lanczos_steps;     /* Krylov dimension for ||2A_c||_2; 0 = min(M, 64) */
+  int32_t path;              /* AMMSE_PATH_AUTO: LDS-resident MFMA kernel when every
+                                instance fits it, else the general kernel;
+                                AMMSE_PATH_GENERAL: always the general kernel */
+  int32_t reserved;          /* must be 0 */
   double eps1;               /* stage-switch tolerance (paper: 0.1) */
   double eps2;               /* stop tolerance (0: run exactly max_iters) */
   double gamma_c;            /* > 0: fixed step after the adaptive window;

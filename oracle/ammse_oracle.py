@@ -277,7 +277,7 @@ def _inv_hermitian(E: np.ndarray) -> np.ndarray:
 def ammmse(prob: Problem, V0u: np.ndarray, iters: int, eps1: float = 0.1, eps2: float = 0.0,
            Tc: int = 3, gamma_c: Optional[float] = None, extrapolate: bool = True,
            warm_start: bool = True, force_switch_iter: Optional[int] = None,
-           rearm_at_switch: bool = True) -> dict:
+           rearm_at_switch: bool = True, perturb=None) -> dict:
     """A-MMMSE (Algorithm 3), FP64, one instance.
 
     Per iteration t = 1..iters:
@@ -294,7 +294,9 @@ def ammmse(prob: Problem, V0u: np.ndarray, iters: int, eps1: float = 0.1, eps2: 
     iteration of the stage switch (-1 if none) and the number of iterations run.
     ``force_switch_iter = s`` makes the first stage-II iteration exactly s.
     ``warm_start=False`` runs stage II from t = 1 (A-WMMSE).  With Tc = 0 a
-    positive ``gamma_c`` must be given."""
+    positive ``gamma_c`` must be given.  ``perturb(t, V)``, if given, replaces
+    every new iterate V^t by its return value; the tests use it to measure how
+    strongly a trajectory amplifies rounding-sized perturbations."""
     if Tc <= 0 and not (gamma_c is not None and gamma_c > 0):
         raise ValueError("Tc = 0 needs a positive fixed step gamma_c")
     V_prev = V0u.copy()
@@ -339,6 +341,8 @@ def ammmse(prob: Problem, V0u: np.ndarray, iters: int, eps1: float = 0.1, eps2: 
         gammas.append(gamma.copy())
         grad = gradient_v(prob, Uu, Wu, Vhat, A)
         V_new = project_spc(prob, Vhat - gamma[prob.cell][:, None, None] * grad)
+        if perturb is not None:
+            V_new = perturb(t, V_new)
         V_prev2, V_prev = V_prev, V_new
         trace.append(wsr_bits(prob, V_new))
         prev_step_stage2 = stage2

@@ -22,6 +22,8 @@ STATUS_NAMES = {0: "OK", 1: "ERR_NULL", 2: "ERR_SHAPE", 3: "ERR_OPTION", 4: "ERR
                 5: "ERR_HIP", 6: "ERR_UNSUPPORTED", 7: "ERR_ALLOC"}
 PREC_FP64 = 0
 PREC_FP32 = 1
+PATH_AUTO = 0
+PATH_GENERAL = 1
 INST_NONFINITE = 1
 INST_CHOLESKY = 2
 INST_ZERO_POWER = 4
@@ -43,7 +45,7 @@ class AmmseOptions(ctypes.Structure):
                 ("T_c", ctypes.c_int32), ("warm_start", ctypes.c_int32),
                 ("extrapolate", ctypes.c_int32), ("rearm_at_switch", ctypes.c_int32),
                 ("force_switch_iter", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32),
-                ("eps1", ctypes.c_double), ("eps2", ctypes.c_double),
+                ("path", ctypes.c_int32), ("reserved", ctypes.c_int32), ("eps1", ctypes.c_double), ("eps2", ctypes.c_double),
                 ("gamma_c", ctypes.c_double)]
 
 
@@ -112,6 +114,8 @@ class Options:
     rearm_at_switch: int = 1
     force_switch_iter: int = -1
     lanczos_steps: int = 0
+    path: int = 0
+    reserved: int = 0
     eps1: float = 0.1
     eps2: float = 0.0
     gamma_c: float = 0.0

@@ -12,6 +12,7 @@
 struct ammse_plan_s {
   int32_t device = 0;
   int32_t batch = 0;
+  int32_t use_fast = 0;
   ammse_options_t opt{};
   size_t ws_bytes = 0;
   ammse_desc_t* d_desc = nullptr;
@@ -33,6 +34,8 @@ ammse_status_t check_options(const ammse_options_t& o) {
   if (o.rearm_at_switch != 0 && o.rearm_at_switch != 1) return AMMSE_ERR_OPTION;
   if (o.force_switch_iter != -1 && o.force_switch_iter < 1) return AMMSE_ERR_OPTION;
   if (o.lanczos_steps < 0 || o.lanczos_steps > AMMSE_MAX_LANCZOS) return AMMSE_ERR_OPTION;
+  if (o.path != AMMSE_PATH_AUTO && o.path != AMMSE_PATH_GENERAL) return AMMSE_ERR_OPTION;
+  if (o.reserved != 0) return AMMSE_ERR_OPTION;
   if (!(o.eps1 >= 0.0) || !(o.eps2 >= 0.0)) return AMMSE_ERR_OPTION;
   if (o.T_c == 0 && !(o.gamma_c > 0.0)) return AMMSE_ERR_OPTION;
   if (o.gamma_c != o.gamma_c) return AMMSE_ERR_OPTION;
@@ -70,6 +73,8 @@ void ammse_default_options(ammse_options_t* opt) {
   opt->rearm_at_switch = 1;
   opt->force_switch_iter = -1;
   opt->lanczos_steps = 0;
+  opt->path = AMMSE_PATH_AUTO;
+  opt->reserved = 0;
   opt->eps1 = 0.1;
   opt->eps2 = 0.0;
   opt->gamma_c = 0.0;
@@ -154,6 +159,12 @@ ammse_status_t ammse_plan_create(ammse_plan_t* plan, int32_t device,
   std::stable_sort(order.begin(), order.end(),
                    [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
 
+  bool fast = (o.precision == AMMSE_PREC_FP32) && (o.path == AMMSE_PATH_AUTO);
+  for (int32_t i = 0; fast && i < batch; ++i) {
+    const ammse_instance_t& t = table[i];
+    fast = ammse_fast_eligible(t.C, t.U, t.M, t.N, t.d);
+  }
+
   std::vector<ammse_desc_t> desc(batch);
   size_t off = 0;
   int64_t ncu = 0;
@@ -176,13 +187,14 @@ ammse_status_t ammse_plan_create(ammse_plan_t* plan, int32_t device,
     d.user_off = t.user_off;
     d.bs_off = t.bs_off;
     d.ws_off = (int64_t)off;
-    off += ammse_ws_layout(rb, t.U, t.M, t.N, t.d, ls).total;
+    if (!fast) off += ammse_ws_layout(rb, t.U, t.M, t.N, t.d, ls).total;
   }
 
   ammse_plan_s* P = new (std::nothrow) ammse_plan_s();
   if (!P) return AMMSE_ERR_ALLOC;
   P->device = device;
   P->batch = batch;
+  P->use_fast = fast ? 1 : 0;
   P->opt = o;
   P->opt.lanczos_steps = ls;
   P->ws_bytes = std::max<size_t>(off, 256);
@@ -222,8 +234,9 @@ ammse_status_t ammse_plan_destroy(ammse_plan_t plan) {
 
 static ammse_status_t launch(ammse_plan_t plan, ammse_kparams_t& k, hipStream_t stream) {
   if (hipSetDevice(plan->device) != hipSuccess) return AMMSE_ERR_HIP;
-  hipError_t e = (plan->opt.precision == AMMSE_PREC_FP64) ? ammse_launch_fp64(k, stream)
-                                                          : ammse_launch_fp32(k, stream);
+  hipError_t e = plan->use_fast ? ammse_launch_fast_fp32(k, stream)
+                 : (plan->opt.precision == AMMSE_PREC_FP64) ? ammse_launch_fp64(k, stream)
+                                                            : ammse_launch_fp32(k, stream);
   return (e == hipSuccess) ? AMMSE_OK : AMMSE_ERR_HIP;
 }
 

@@ -161,6 +161,90 @@ __device__ double tridiag_lmax(const double* la, const double* lb, int m, int* i
   return hi;
 }
 
+// ---------------------------------------------------------------------------
+// Per-user receiver / weight algebra (Section IV equations for U and W)
+// ---------------------------------------------------------------------------
+// Input: J = I + sum of interference covariances (normalised noise), padded
+// to 4 x 4 with identity; F = own-signal image G_own (N x d), zero padded.
+// Output: UW = J^{-1} G_own (= U W), E = (I + G_own^H J^{-1} G_own)^{-1}
+// (= the MSE matrix at the MMSE receiver), *rate = log det E^{-1} (nats).
+// Returns false when a factorisation fails.
+__device__ __forceinline__ bool user_receiver(zd* J, zd* F, zd* UW, zd* E, double* rate) {
+  zd X[16];
+  bool ok = chol4(J);
+  trsm_lower(J, F);                           // F = L^{-1} G_own
+#pragma unroll
+  for (int i = 0; i < 4; ++i)                 // X = I + F^H F
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      zd t = {(i == j) ? 1.0 : 0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) t = t + mulc(F[k * 4 + j], F[k * 4 + i]);
+      X[i * 4 + j] = t;
+    }
+  trsm_lower_h(J, F);                         // UW = J^{-1} G_own
+  ok = chol4(X) && ok;                        // E^{-1} = I + F^H F = Lw Lw^H
+  double r = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r += 2.0 * log(X[i * 4 + i].x);
+  zd Li[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) Li[i] = {((i % 5) == 0) ? 1.0 : 0.0, 0.0};
+  trsm_lower(X, Li);                          // Li = Lw^{-1}
+#pragma unroll
+  for (int i = 0; i < 4; ++i)                 // E = Li^H Li
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      zd t = {0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) t = t + mulc(Li[k * 4 + j], Li[k * 4 + i]);
+      E[i * 4 + j] = t;
+    }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) UW[i] = F[i];
+  *rate = r;
+  return ok;
+}
+
+// D = alpha U W U^H and Y = alpha U W (padded 4 x 4): stage I uses W = I
+// (U = UW E), stage II uses W = E^{-1} (U W = UW, U W U^H = UW E UW^H).
+__device__ __forceinline__ void user_weights(const zd* UW, const zd* E, bool stage2, double a,
+                                             zd* Dout, zd* Yout) {
+  zd T[16];                                   // T = UW E  (= U)
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      zd t = {0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) t = t + UW[i * 4 + k] * E[k * 4 + j];
+      T[i * 4 + j] = t;
+    }
+  const zd* Ur = stage2 ? UW : T;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      zd t = {0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) t = t + mulc(T[i * 4 + k], Ur[j * 4 + k]);
+      Dout[i * 4 + j] = scal(a, t);
+      Yout[i * 4 + j] = scal(a, Ur[i * 4 + j]);
+    }
+  // exactly Hermitian D (the step-size operator must be symmetric)
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    Dout[i * 4 + i].y = 0.0;
+#pragma unroll
+    for (int j = i + 1; j < 4; ++j) {
+      const zd x = Dout[i * 4 + j], y = Dout[j * 4 + i];
+      const zd m = {0.5 * (x.x + y.x), 0.5 * (x.y - y.y)};
+      Dout[i * 4 + j] = m;
+      Dout[j * 4 + i] = cj(m);
+    }
+  }
+}
+
 __device__ __forceinline__ double rel_change(double a, double b) {
   if (b > 0) return fabs(a - b) / b;
   return (a == b) ? 0.0 : INFINITY;

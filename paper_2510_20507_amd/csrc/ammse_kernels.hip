@@ -225,7 +225,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
   auto user_rates = [&](const cx<R>* G, zd* UW, zd* E) {
     if (tid < U) {
       const int u = tid;
-      zd J[16], F[16], X[16];
+      zd J[16], F[16];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -241,38 +241,8 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
 #pragma unroll
         for (int s = 0; s < 4; ++s)
           if (i < N && s < d) F[i * 4 + s] = to_d(Gc[(long)(u * N + i) * nc + j0 + s]);
-      bool ok = chol4(J);
-      trsm_lower(J, F);                           // F = L^{-1} G_own
-#pragma unroll
-      for (int i = 0; i < 4; ++i)                 // X = I + F^H F
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          zd t = {(i == j) ? 1.0 : 0.0, 0.0};
-#pragma unroll
-          for (int k = 0; k < 4; ++k) t = t + mulc(F[k * 4 + j], F[k * 4 + i]);
-          X[i * 4 + j] = t;
-        }
-      trsm_lower_h(J, F);                         // UW = J-^{-1} G_own
-      ok = chol4(X) && ok;                        // W = I + F^H F = Lw Lw^H
-      double r = 0.0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) r += 2.0 * log(X[i * 4 + i].x);
-      // E = W^{-1} = Lw^{-H} Lw^{-1}
-      zd Li[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) Li[i] = {((i % 5) == 0) ? 1.0 : 0.0, 0.0};
-      trsm_lower(X, Li);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          zd t = {0.0, 0.0};
-#pragma unroll
-          for (int k = 0; k < 4; ++k) t = t + mulc(Li[k * 4 + j], Li[k * 4 + i]);
-          E[i * 4 + j] = t;
-        }
-#pragma unroll
-      for (int i = 0; i < 16; ++i) UW[i] = F[i];
+      double r;
+      const bool ok = user_receiver(J, F, UW, E, &r);
       sm.rate[u] = sm.alpha[u] * r;
       if (!ok) atomicOr(&sm.fail, AMMSE_INST_CHOLESKY);
     }
@@ -286,44 +256,14 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
   };
 
   // D_u = alpha U W U^H, Y_u = alpha U W into the workspace (padded 4 x 4).
-  auto user_weights = [&](const zd* UW, const zd* E, bool stage2) {
+  auto user_weights_ws = [&](const zd* UW, const zd* E, bool stage2) {
     if (tid < U) {
-      const int u = tid;
-      const double a = sm.alpha[u];
-      zd T[16];                                   // T = UW E  (= U)
+      zd Dl[16], Yl[16];
+      user_weights(UW, E, stage2, sm.alpha[tid], Dl, Yl);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          zd t = {0.0, 0.0};
-#pragma unroll
-          for (int k = 0; k < 4; ++k) t = t + UW[i * 4 + k] * E[k * 4 + j];
-          T[i * 4 + j] = t;
-        }
-      // stage I: W = I, D = a U U^H, Y = a U;  stage II: D = a T UW^H, Y = a UW
-      const zd* Ur = stage2 ? UW : T;
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          zd t = {0.0, 0.0};
-#pragma unroll
-          for (int k = 0; k < 4; ++k) t = t + mulc(T[i * 4 + k], Ur[j * 4 + k]);
-          Dm[u * 16 + i * 4 + j] = scal(a, t);
-          Ym[u * 16 + i * 4 + j] = scal(a, Ur[i * 4 + j]);
-        }
-    }
-    __syncthreads();
-    // symmetrise D (exactly Hermitian for the step-size operator)
-    for (int e = tid; e < U * 16; e += AMMSE_BLOCK) {
-      const int u = e >> 4, i = (e >> 2) & 3, j = e & 3;
-      if (i < j) {
-        const zd x = Dm[u * 16 + i * 4 + j], y = Dm[u * 16 + j * 4 + i];
-        const zd m = {0.5 * (x.x + y.x), 0.5 * (x.y - y.y)};
-        Dm[u * 16 + i * 4 + j] = m;
-        Dm[u * 16 + j * 4 + i] = cj(m);
-      } else if (i == j) {
-        Dm[u * 16 + i * 4 + j].y = 0.0;
+      for (int i = 0; i < 16; ++i) {
+        Dm[tid * 16 + i] = Dl[i];
+        Ym[tid * 16 + i] = Yl[i];
       }
     }
     __syncthreads();
@@ -469,7 +409,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
         switch_iter = t;
       }
     }
-    user_weights(UW, E, stage2);
+    user_weights_ws(UW, E, stage2);
 
     // step size
     const bool adaptive = t <= p.T_c || (p.rearm && switch_iter >= 1 && t >= switch_iter &&

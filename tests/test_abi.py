@@ -44,8 +44,8 @@ def test_version_and_status_strings(L):
 def test_struct_layout_matches_header():
     assert ctypes.sizeof(ammse.AmmseInstance) == 56
     assert ammse.AmmseInstance.h_off.offset == 24
-    assert ctypes.sizeof(ammse.AmmseOptions) == 56
-    assert ammse.AmmseOptions.eps1.offset == 32
+    assert ctypes.sizeof(ammse.AmmseOptions) == 64
+    assert ammse.AmmseOptions.eps1.offset == 40
 
 
 def test_default_options_match_paper(L):
@@ -94,6 +94,7 @@ def test_validate_rejects_overlapping_precoders(L):
 @pytest.mark.parametrize("opt", [
     dict(precision=7), dict(max_iters=-1), dict(T_c=-1), dict(lanczos_steps=65),
     dict(force_switch_iter=0), dict(eps1=-0.1), dict(T_c=0), dict(eps2=float("nan")),
+    dict(path=2), dict(reserved=1),
 ])
 def test_validate_rejects_bad_options(L, opt):
     table, cu = _one()
