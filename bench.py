@@ -36,7 +36,8 @@ if ROOT not in sys.path:
 REF_FILE = os.path.join(ROOT, "tests", "golden", "wmmse_ref_rayleigh_sweep4x256.json")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ammse_solve_fp32_rayleigh_sweep1024_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2510_20507_amd", "csrc", f)
-                  for f in ("ammse_kernels.hip", "ammse_internal.h")]
+                  for f in ("ammse_fast.hip", "ammse_kernels.hip", "ammse_device.h",
+                            "ammse_internal.h")]
 PEAK_FP32_MFMA_TFLOPS = 157.3
 ITERS = 100
 CALIB_COPY_MIB = 1024
@@ -128,8 +129,9 @@ def parse_pmc(dirs):
                     name = row.get("Kernel_Name", "")
                     cname = row.get("Counter_Name", "")
                     val = float(row.get("Counter_Value", 0) or 0)
-                    kind = ("solve" if "ammse_solve_kernel" in name else
-                            "copy" if ("copy" in name.lower() or "elementwise" in name.lower())
+                    grid = int(row.get("Grid_Size", 0) or 0)
+                    kind = ("solve" if ("ammse_" in name and "_kernel" in name) else
+                            "copy" if ("copyBuffer" in name and grid >= 131072 and val > 100000)
                             else None)
                     if kind is None:
                         continue
@@ -138,7 +140,22 @@ def parse_pmc(dirs):
     agg = {}
     for (kind, cname, _), v in out.items():
         agg.setdefault((kind, cname), []).append(v)
-    return {f"{k[0]}:{k[1]}": (float(np.mean(v)), len(v)) for k, v in agg.items()}
+    res = {f"{k[0]}:{k[1]}": (float(np.mean(v)), len(v)) for k, v in agg.items()}
+    # calibration: the --calib-copy run copies CALIB_COPY_MIB MiB device-to-device
+    known_kib = CALIB_COPY_MIB * 1024.0
+    out2 = {"raw_kib_per_dispatch": res}
+    if "copy:FETCH_SIZE" in res and "solve:FETCH_SIZE" in res:
+        sf = known_kib / res["copy:FETCH_SIZE"][0]
+        out2["fetch_scale"] = sf
+        out2["solve_fetch_bytes"] = res["solve:FETCH_SIZE"][0] * 1024 * sf
+    if "copy:WRITE_SIZE" in res and "solve:WRITE_SIZE" in res:
+        sw = known_kib / res["copy:WRITE_SIZE"][0]
+        out2["write_scale"] = sw
+        out2["solve_write_bytes"] = res["solve:WRITE_SIZE"][0] * 1024 * sw
+    if "solve_fetch_bytes" in out2 and "solve_write_bytes" in out2:
+        out2["traffic_bytes_per_launch"] = out2["solve_fetch_bytes"] + out2["solve_write_bytes"]
+    out2["kernel_sha"] = kernel_sha()
+    return out2
 
 
 def main():
@@ -238,7 +255,10 @@ def main():
         "instances_per_s_all": B / (ms_per_step / 1e3),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
-                     "traffic": traffic, "kernel": "ammse_solve_kernel<float>",
+                     "traffic": traffic,
+                     "kernel": ("ammse_fast_kernel (LDS-resident, MFMA FP32)"
+                                if plan.kernel == ammse.KERNEL_LDS_MFMA
+                                else "ammse_solve_kernel<float> (general)"),
                      "kernel_ms": kern_ms, "flops_per_launch": flops},
     }
     if not a.no_plain:

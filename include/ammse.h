@@ -161,6 +161,11 @@ ammse_status_t ammse_plan_create(ammse_plan_t* plan, int32_t device,
 /* Bytes of device workspace ammse_solve / ammse_wsr need for this plan. */
 ammse_status_t ammse_plan_workspace_size(ammse_plan_t plan, size_t* bytes);
 
+/* Kernel a plan launches (AMMSE_KERNEL_*) and its LDS bytes per workgroup. */
+#define AMMSE_KERNEL_LDS_MFMA 0  /* LDS-resident, MFMA FP32 channel products */
+#define AMMSE_KERNEL_GENERAL 1   /* any shape; workspace-resident state */
+ammse_status_t ammse_plan_info(ammse_plan_t plan, int32_t* kernel, size_t* lds_bytes);
+
 /* Release the plan's device tables.  NULL is accepted. */
 ammse_status_t ammse_plan_destroy(ammse_plan_t plan);
 

@@ -30,7 +30,9 @@ INST_ZERO_POWER = 4
 
 EXPORTED = ("ammse_version", "ammse_status_string", "ammse_default_options", "ammse_validate",
             "ammse_plan_create", "ammse_plan_workspace_size", "ammse_plan_destroy",
-            "ammse_solve", "ammse_wsr")
+            "ammse_solve", "ammse_wsr", "ammse_plan_info")
+KERNEL_LDS_MFMA = 0
+KERNEL_GENERAL = 1
 
 
 class AmmseInstance(ctypes.Structure):
@@ -81,6 +83,8 @@ def lib() -> ctypes.CDLL:
     L.ammse_plan_create.argtypes = [P(vp), i32, P(AmmseInstance), P(i32), i32, P(AmmseOptions)]
     L.ammse_plan_workspace_size.restype = i32
     L.ammse_plan_workspace_size.argtypes = [vp, P(sz)]
+    L.ammse_plan_info.restype = i32
+    L.ammse_plan_info.argtypes = [vp, P(i32), P(sz)]
     L.ammse_plan_destroy.restype = i32
     L.ammse_plan_destroy.argtypes = [vp]
     L.ammse_solve.restype = i32
@@ -180,6 +184,11 @@ class Plan:
         _check(L.ammse_plan_workspace_size(self._handle, ctypes.byref(ws)),
                "ammse_plan_workspace_size")
         self.workspace_bytes = int(ws.value)
+        kern, lds = ctypes.c_int32(), ctypes.c_size_t()
+        _check(L.ammse_plan_info(self._handle, ctypes.byref(kern), ctypes.byref(lds)),
+               "ammse_plan_info")
+        self.kernel = int(kern.value)
+        self.lds_bytes = int(lds.value)
 
     def close(self):
         if getattr(self, "_handle", None) is not None and self._handle.value:

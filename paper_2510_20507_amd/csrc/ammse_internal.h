@@ -87,6 +87,7 @@ __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int
 }
 
 hipError_t ammse_launch_fp64(const ammse_kparams_t& p, hipStream_t s);
+size_t ammse_general_lds_bytes(int precision);
 // LDS-resident MFMA kernel (FP32): shapes it serves, its LDS use, launch.
 bool ammse_fast_eligible(int C, int U, int M, int N, int d);
 size_t ammse_fast_lds_bytes();

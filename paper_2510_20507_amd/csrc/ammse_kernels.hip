@@ -528,6 +528,10 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
 
 }  // namespace
 
+size_t ammse_general_lds_bytes(int precision) {
+  return precision == AMMSE_PREC_FP64 ? sizeof(Smem<double>) : sizeof(Smem<float>);
+}
+
 hipError_t ammse_launch_fp64(const ammse_kparams_t& p, hipStream_t s) {
   hipLaunchKernelGGL(ammse_solve_kernel<double>, dim3(p.batch), dim3(AMMSE_BLOCK), 0, s, p);
   return hipGetLastError();

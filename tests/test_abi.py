@@ -28,7 +28,7 @@ def L():
 
 def test_every_declared_symbol_is_exported(L):
     names = _declared_functions()
-    assert len(names) == 9
+    assert len(names) == 10
     assert set(names) == set(ammse.EXPORTED)
     for n in names:
         assert hasattr(L, n), n
@@ -121,5 +121,6 @@ def test_plan_create_validates_before_touching_the_device(L):
 def test_null_arguments(L):
     assert L.ammse_plan_workspace_size(None, None) == 1
     assert L.ammse_plan_destroy(None) == 0
+    assert L.ammse_plan_info(None, None, None) == 1
     assert L.ammse_solve(None, *([None] * 12), 0, None) == 1
     assert L.ammse_wsr(None, *([None] * 6), 0, None) == 1
