@@ -42,7 +42,7 @@ __device__ __forceinline__ cx<R> from_d(zd a) { return {(R)a.x, (R)a.y}; }
 
 // Sum over the block (a multiple of 64 threads, at most 512); every thread
 // receives the same value.
-__device__ double block_sum(double v, double* red) {
+__device__ inline double block_sum(double v, double* red) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   const int w = threadIdx.x >> 6;
@@ -121,7 +121,7 @@ __device__ __forceinline__ void trsm_lower_h(const zd* L, zd* X) {
 // Largest eigenvalue of a symmetric tridiagonal matrix by multisection on
 // Sturm counts (256 probe points per round, all threads cooperate).
 // ---------------------------------------------------------------------------
-__device__ int sturm_below(const double* a, const double* b, int m, double x) {
+__device__ inline int sturm_below(const double* a, const double* b, int m, double x) {
   int cnt = 0;
   double q = a[0] - x;
   if (q < 0) ++cnt;
@@ -134,8 +134,10 @@ __device__ int sturm_below(const double* a, const double* b, int m, double x) {
 }
 
 // la, lb: diagonal and off-diagonal in LDS; imin: an LDS int used for the
-// reduction.  Every thread of the block must call it.
-__device__ double tridiag_lmax(const double* la, const double* lb, int m, int* imin) {
+// reduction; stops when the bracket is narrower than rtol * lambda.  Every
+// thread of the block must call it.
+__device__ inline double tridiag_lmax(const double* la, const double* lb, int m, int* imin,
+                                     double rtol = 1e-16) {
   double lo = 1e300, hi = -1e300;
   for (int i = 0; i < m; ++i) {
     const double r = (i > 0 ? fabs(lb[i - 1]) : 0.0) + (i < m - 1 ? fabs(lb[i]) : 0.0);
@@ -145,7 +147,7 @@ __device__ double tridiag_lmax(const double* la, const double* lb, int m, int* i
   hi += 1e-300 + fabs(hi) * 1e-15;
   for (int round = 0; round < 8; ++round) {
     const double w = hi - lo;
-    if (!(w > fabs(hi) * 1e-16)) break;
+    if (!(w > fabs(hi) * rtol)) break;
     if (threadIdx.x == 0) *imin = blockDim.x;
     __syncthreads();
     const double x = lo + w * (double)(threadIdx.x + 1) / (double)(blockDim.x + 1);

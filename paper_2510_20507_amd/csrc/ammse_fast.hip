@@ -1,24 +1,34 @@
 // LDS-resident A-MMMSE solve kernel on MFMA (FP32 storage), gfx950.
 //
-// For single-cell instances whose stacked channel H (U*N x M), precoders
-// (M x U*d) and channel product (U*N x U*d) fit in LDS together, one
-// workgroup of 256 threads (4 waves) loads H once and keeps it in LDS for
-// all iterations; HBM is touched only to read H, V0 and the per-user
-// scalars and to write the results.  The two complex channel products per
-// iteration run on v_mfma_f32_16x16x4f32: a complex product is three real
-// accumulators (Re*Re, Im*Im, Re*Im + Im*Re), fed from interleaved complex
-// LDS tiles.  Each wave owns whole 16-row strips of the outputs, so the
-// iteration state lives in registers in the MFMA output layout:
-//   G^{t-1}, G^{t-2} (for the extrapolated product by linearity) and
-//   V^{t-1}, V^{t-2} (for the extrapolated precoder).
-// A lane holds 4 consecutive rows of one column; with N in {1, 2, 4} these
-// are whole users, so Z = S (D G^ - Y) is formed in registers.
+// For single-cell instances with M = 64 and U*N = U*d = 64, one workgroup of
+// 256 threads (4 waves) owns one instance for the whole solve; H stays in
+// LDS for all iterations and HBM is touched only to read H, V0 and the
+// per-user scalars and to write the results.  LDS use is kept under 80 KiB
+// so that two instances share a compute unit and one instance's serial
+// phases overlap the other's matrix products.
 //
-// Per iteration (Algorithm 3 with the readings of the generic kernel):
-//   Gs <- G^{t-1}; per-user J-, Cholesky, rate, U, W (double);
-//   WSR(V^{t-1}), stage latch, adaptive step by Lanczos on H in LDS;
-//   Z -> LDS; Grad = 2 H^H Z (MFMA); V^t = Pi(V^ - gamma Grad) in registers;
-//   V^t -> LDS; G^t = S H V^t (MFMA).
+// Channel products: v_mfma_f32_16x16x4f32, a complex product being three
+// real accumulators (Re*Re, Im*Im, Re*Im + Im*Re) fed from interleaved
+// complex LDS tiles.  Each wave owns whole 16-row strips of the outputs, so
+// the iteration state stays in registers in the MFMA output layout:
+//   G^{t-1}, G^{t-2}  (the extrapolated product follows by linearity)
+//   V^{t-1}, V^{t-2}  (the extrapolated precoder)
+// A lane holds 4 consecutive rows of one column.  Four consecutive rows form
+// a "block user": one user for N = 4, two for N = 2, four for N = 1; its
+// N x N and d x d algebra is done as one block-diagonal 4 x 4 problem.
+//
+// Per-user algebra (Section IV equations for U and W, in the Woodbury form
+// used throughout this library) runs lane-parallel in double: the 16 lanes
+// of a 4-lane-row group hold the 16 entries of a 4 x 4 complex matrix and
+// exchange them with cross-lane shuffles.  The interference-plus-noise
+// covariance of every user is reduced directly from the G registers.
+//
+// Per iteration t (Algorithm 3):
+//   J- from registers (reduce-scatter over the 16 lanes of a row group);
+//   Cholesky, rate, U, W per block user; WSR(V^{t-1}); stage latch;
+//   adaptive step by Lanczos on H in LDS;  Z = S (D G^ - Y) -> LDS;
+//   Grad = 2 H^H Z (MFMA);  V^t = Pi(V^ - gamma Grad) in registers -> LDS;
+//   G^t = S H V^t (MFMA), own blocks -> LDS.
 
 #include "ammse_device.h"
 
@@ -34,39 +44,102 @@ struct Shape {
   static constexpr int HLD = M + 2;                 // padded LDS row strides (complex)
   static constexpr int BROWS = (M > UN) ? M : UN;
   static constexpr int BLD = UD + 2;
-  static constexpr int GLD = UD + 2;
   static constexpr int GRB = UNB / 4;               // row blocks per wave in G
   static constexpr int VRB = MB / 4;                // row blocks per wave in V / Grad
-  static constexpr int MAXU = UN;                   // U <= U*N
+  static constexpr int NG = UN / 4;                 // block users (4 rows each)
   static_assert(MB % 4 == 0 && UNB % 4 == 0, "row blocks must split over 4 waves");
   // LDS carve (bytes)
   static constexpr size_t oH = 0;
   static constexpr size_t oB = oH + sizeof(float2) * UN * HLD;
-  static constexpr size_t oG = oB + sizeof(float2) * BROWS * BLD;
-  static constexpr size_t oD = oG + sizeof(float2) * UN * GLD;
-  static constexpr size_t oY = oD + sizeof(float2) * MAXU * 16;
-  static constexpr size_t oJ = oY + sizeof(float2) * MAXU * 16;     // J-: U*N*N <= 4*U*N
-  static constexpr size_t oQ = oJ + sizeof(zd) * 4 * UN;            // 3 Lanczos vectors
-  static constexpr size_t oY1 = oQ + sizeof(zd) * 3 * M;
-  static constexpr size_t oY2 = oY1 + sizeof(zd) * UN;
-  static constexpr size_t oS = oY2 + sizeof(zd) * UN;               // invsig, alpha, rate
-  static constexpr size_t oL = oS + sizeof(double) * 3 * MAXU;      // la, lb
+  static constexpr size_t oF = oB + sizeof(float2) * BROWS * BLD;   // own blocks of G
+  static constexpr size_t oD = oF + sizeof(float2) * NG * 16;       // D per block user
+  static constexpr size_t oY = oD + sizeof(float2) * NG * 16;       // Y per block user
+  static constexpr size_t oS = oY + sizeof(float2) * NG * 16;       // invsig, alpha per row
+  static constexpr size_t oL = oS + sizeof(double) * 2 * UN;        // la, lb
   static constexpr size_t oR = oL + sizeof(double) * 2 * AMMSE_MAX_LANCZOS;
   static constexpr size_t bytes = oR + sizeof(double) * 8 + 16;
+  // Lanczos vectors (double complex) alias the product-operand area, which
+  // is free between the last product of an iteration and the Z build.
+  static_assert(sizeof(zd) * (3 * M + 2 * UN) <= sizeof(float2) * BROWS * BLD, "Lanczos area");
 };
 
 __device__ __forceinline__ float2 c2(float x, float y) { return make_float2(x, y); }
 
-// g[i] for a run-time i in [0, 4) without dynamic register indexing.
-__device__ __forceinline__ float2 pick4(const float2 (&g)[4], int i) {
-  float2 r = g[0];
-  r = (i == 1) ? g[1] : r;
-  r = (i == 2) ? g[2] : r;
-  r = (i == 3) ? g[3] : r;
-  return r;
+// complex double from lane `src` (every lane of the wave must execute it)
+__device__ __forceinline__ zd shz(zd v, int src) {
+  return {__shfl(v.x, src, 64), __shfl(v.y, src, 64)};
 }
 
-// One wave: P[i][j] (three real accumulators) += op(A) B for the wave's row
+// ---------------------------------------------------------------------------
+// 4 x 4 complex double matrices spread over a 16-lane group: lane base + 4a + b
+// holds entry (a, b).  All functions must be executed by the whole wave.
+// ---------------------------------------------------------------------------
+struct Lane4 {
+  int base, a, b;
+  __device__ __forceinline__ zd at(zd v, int r, int c) const { return shz(v, base + 4 * r + c); }
+};
+
+// In place Cholesky (lower); ok is cleared when a pivot is not positive/finite.
+__device__ __forceinline__ zd chol16(const Lane4& L, zd A, bool& ok) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double dkk = L.at(A, k, k).x;
+    ok = ok && (dkk > 0.0) && isfinite(dkk);
+    const double l = sqrt(fmax(dkk, 1e-300));
+    if (L.b == k && L.a > k) A = scal(1.0 / l, A);
+    if (L.a == k && L.b == k) A = {l, 0.0};
+    const zd lak = L.at(A, L.a, k), lbk = L.at(A, L.b, k);
+    if (L.a > k && L.b > k) A = A - mulc(lak, lbk);
+  }
+  if (L.b > L.a) A = {0.0, 0.0};
+  return A;
+}
+
+// X <- Lo^{-1} X (forward substitution, Lo lower with real diagonal)
+__device__ __forceinline__ zd trsm16(const Lane4& L, zd Lo, zd X) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double lkk = L.at(Lo, k, k).x;
+    if (L.a == k) X = scal(1.0 / lkk, X);
+    const zd xkb = L.at(X, k, L.b), lak = L.at(Lo, L.a, k);
+    if (L.a > k) X = X - lak * xkb;
+  }
+  return X;
+}
+
+// X <- Lo^{-H} X (back substitution with the conjugate transpose)
+__device__ __forceinline__ zd trsm16h(const Lane4& L, zd Lo, zd X) {
+#pragma unroll
+  for (int k = 3; k >= 0; --k) {
+    const double lkk = L.at(Lo, k, k).x;
+    if (L.a == k) X = scal(1.0 / lkk, X);
+    const zd xkb = L.at(X, k, L.b), lka = L.at(Lo, k, L.a);
+    if (L.a < k) X = X - cj(lka) * xkb;
+  }
+  return X;
+}
+
+// A^H B, A B, A B^H
+__device__ __forceinline__ zd mm_hn(const Lane4& L, zd A, zd B) {
+  zd c = {0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) c = c + cj(L.at(A, k, L.a)) * L.at(B, k, L.b);
+  return c;
+}
+__device__ __forceinline__ zd mm_nn(const Lane4& L, zd A, zd B) {
+  zd c = {0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) c = c + L.at(A, L.a, k) * L.at(B, k, L.b);
+  return c;
+}
+__device__ __forceinline__ zd mm_nh(const Lane4& L, zd A, zd B) {
+  zd c = {0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) c = c + mulc(L.at(A, L.a, k), L.at(B, L.b, k));
+  return c;
+}
+
+// One wave: P[i][j] (three real accumulators) = op(A) B for the wave's row
 // blocks i (global row block wave + 4 i) and all column blocks j.
 // op(A)[r][k] = A[r*lda + k], or conj(A[k*lda + r]) with CONJA.
 template <int NRB, int NCB, bool CONJA>
@@ -121,47 +194,45 @@ __device__ __forceinline__ void wave_cgemm(const float2* __restrict__ A, int lda
 }
 
 template <class S>
-__global__ __launch_bounds__(256) void ammse_fast_kernel(ammse_kparams_t p) {
+__global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   extern __shared__ __align__(16) char smem[];
   float2* Hs = (float2*)(smem + S::oH);
   float2* Bs = (float2*)(smem + S::oB);
-  float2* Gs = (float2*)(smem + S::oG);
+  float2* Fs = (float2*)(smem + S::oF);
   float2* Ds = (float2*)(smem + S::oD);
   float2* Ys = (float2*)(smem + S::oY);
-  zd* Jm = (zd*)(smem + S::oJ);
-  zd* Lq = (zd*)(smem + S::oQ);
-  zd* Ly1 = (zd*)(smem + S::oY1);
-  zd* Ly2 = (zd*)(smem + S::oY2);
-  double* invsig = (double*)(smem + S::oS);
-  double* alpha = invsig + S::MAXU;
-  double* rate = alpha + S::MAXU;
+  double* invsig = (double*)(smem + S::oS);    // per row: 1/sigma of the row's user
+  double* alpha = invsig + S::UN;              // per row: alpha of the row's user
   double* la = (double*)(smem + S::oL);
   double* lb = la + AMMSE_MAX_LANCZOS;
   double* red = (double*)(smem + S::oR);
-  int* misc = (int*)(red + 8);      // [0] fail flag, [1] multisection index
+  int* misc = (int*)(red + 8);                 // [0] fail flag, [1] multisection index
+  zd* Lq = (zd*)Bs;                            // Lanczos vectors (alias, see Shape)
 
   constexpr int M = S::M, UN = S::UN, UD = S::UD;
   const ammse_desc_t Dd = p.desc[blockIdx.x];
-  const int U = Dd.U, N = Dd.N, d = Dd.d;
+  const int N = Dd.N, d = Dd.d;
   const int b = Dd.b;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
+  const Lane4 L4{lane & ~15, li >> 2, li & 3};
 
   const float2* Hg = (const float2*)p.H + Dd.h_off;
   float2* Vg = (float2*)p.V + Dd.v_off;
   const double Pc = p.wsr_only ? 0.0 : p.P[Dd.bs_off];
 
-  for (int u = tid; u < U; u += 256) {
-    invsig[u] = 1.0 / sqrt(p.sigma2[Dd.user_off + u]);
-    alpha[u] = p.alpha[Dd.user_off + u];
+  for (int r = tid; r < UN; r += 256) {
+    invsig[r] = 1.0 / sqrt(p.sigma2[Dd.user_off + r / N]);
+    alpha[r] = p.alpha[Dd.user_off + r / N];
   }
+  for (int e = tid; e < S::NG * 16; e += 256) Fs[e] = c2(0.f, 0.f);
   if (tid == 0) misc[0] = 0;
   for (int e = tid; e < UN * M; e += 256) Hs[(e / M) * S::HLD + (e % M)] = Hg[e];
   for (int e = tid; e < M * UD; e += 256) Bs[(e / UD) * S::BLD + (e % UD)] = Vg[e];
   __syncthreads();
 
-  // register state in the MFMA output layout:
-  // element [i][j][r] is row 16 (wave + 4 i) + 4 lk + r, column 16 j + li
+  // register state: element [i][j][r] is row 16 (wave + 4 i) + 4 lk + r,
+  // column 16 j + li
   float2 Vp[S::VRB][S::UDB][4], Vq[S::VRB][S::UDB][4];
   float2 Gp[S::GRB][S::UDB][4], Gq[S::GRB][S::UDB][4];
 #pragma unroll
@@ -175,7 +246,7 @@ __global__ __launch_bounds__(256) void ammse_fast_kernel(ammse_kparams_t p) {
         Vq[i][j][r] = Vp[i][j][r];
       }
 
-  // G = S H V (from Bs) into Gp, and the copy in Gs for the per-user phase
+  // G = S H V (V in Bs) into Gp (previous Gp to Gq); own blocks into Fs
   auto product_G = [&]() {
     floatx4 P[S::GRB][S::UDB][3];
     wave_cgemm<S::GRB, S::UDB, false>(Hs, S::HLD, Bs, S::BLD, M, wave, P);
@@ -186,86 +257,108 @@ __global__ __launch_bounds__(256) void ammse_fast_kernel(ammse_kparams_t p) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = 16 * (wave + 4 * i) + 4 * lk + r, col = 16 * j + li;
-          const float s = (float)invsig[row / N];
+          const float s = (float)invsig[row];
           const float2 g = c2(s * (P[i][j][0][r] - P[i][j][1][r]), s * P[i][j][2][r]);
           Gq[i][j][r] = Gp[i][j][r];
           Gp[i][j][r] = g;
-          Gs[row * S::GLD + col] = g;
-        }
-  };
-
-  // receivers and rates of the precoders whose product is in Gs
-  zd UW[16], E[16];
-  auto receivers = [&]() {
-    const int np = N * (N + 1) / 2;
-    for (int e = tid; e < U * np; e += 256) {
-      const int u = e / np;
-      int q = e % np, n1 = 0;
-      while (q >= N - n1) {
-        q -= N - n1;
-        ++n1;
-      }
-      const int n2 = n1 + q;
-      const float2* r1 = Gs + (u * N + n1) * S::GLD;
-      const float2* r2 = Gs + (u * N + n2) * S::GLD;
-      const int j0 = u * d;
-      zd acc = {0.0, 0.0};
-      for (int j = 0; j < UD; ++j) {
-        if (j >= j0 && j < j0 + d) continue;
-        acc.x += (double)r1[j].x * r2[j].x + (double)r1[j].y * r2[j].y;
-        acc.y += (double)r1[j].y * r2[j].x - (double)r1[j].x * r2[j].y;
-      }
-      if (n1 == n2) acc = {acc.x + 1.0, 0.0};
-      Jm[(u * N + n1) * N + n2] = acc;
-      Jm[(u * N + n2) * N + n1] = cj(acc);
-    }
-    __syncthreads();
-    // user u on thread (u % 4) * 64 + u / 4: spreads the users over the 4 SIMDs
-    const int u = (tid & 63) * 4 + (tid >> 6);
-    if ((tid & 63) < (U + 3) / 4 && u < U) {
-      zd J[16], F[16];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          J[i * 4 + j] = (i < N && j < N) ? Jm[(u * N + i) * N + j]
-                                          : zd{(i == j) ? 1.0 : 0.0, 0.0};
-          F[i * 4 + j] = {0.0, 0.0};
-          if (i < N && j < d) {
-            const float2 g = Gs[(u * N + i) * S::GLD + u * d + j];
-            F[i * 4 + j] = {(double)g.x, (double)g.y};
+          const int u = row / N, c = col - u * d;
+          if (c >= 0 && c < d) {
+            const int g4 = row >> 2, u0 = (g4 * 4) / N;
+            Fs[g4 * 16 + r * 4 + (u - u0) * N + c] = g;
           }
         }
-      double rr;
-      const bool ok = user_receiver(J, F, UW, E, &rr);
-      rate[u] = alpha[u] * rr;
-      if (!ok) atomicOr(&misc[0], AMMSE_INST_CHOLESKY);
-    }
   };
-  auto wsr_sum = [&]() {
-    double v = 0.0;
-    for (int u = tid; u < U; u += 256) v += rate[u];
-    return block_sum(v, red) * (1.0 / M_LN2);
-  };
-  auto weights = [&](bool stage2) {
-    const int u = (tid & 63) * 4 + (tid >> 6);
-    if ((tid & 63) < (U + 3) / 4 && u < U) {
-      zd Dl[16], Yl[16];
-      user_weights(UW, E, stage2, alpha[u], Dl, Yl);
+
+  // Per block user (i = row block of this wave, group lk): J-, Cholesky,
+  // rate, UW = J-^{-1} G_own and E = (I + G_own^H J-^{-1} G_own)^{-1}.
+  // Returns the weighted rate contribution of this lane (diagonal lanes).
+  zd UWr[S::GRB], Er[S::GRB];
+  auto receivers = [&]() {
+    double rsum = 0.0;
+    bool ok = true;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        Ds[u * 16 + i] = c2((float)Dl[i].x, (float)Dl[i].y);
-        Ys[u * 16 + i] = c2((float)Yl[i].x, (float)Yl[i].y);
+    for (int i = 0; i < S::GRB; ++i) {
+      const int row0 = 16 * (wave + 4 * i) + 4 * lk;
+      // partial J over this lane's columns, all 16 entries (a, b)
+      zd s[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) s[e] = {0.0, 0.0};
+#pragma unroll
+      for (int j = 0; j < S::UDB; ++j) {
+        const int col = 16 * j + li;
+        zd g[4];
+        bool own[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          g[r] = {(double)Gp[i][j][r].x, (double)Gp[i][j][r].y};
+          own[r] = (col / d) == ((row0 + r) / N);
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const bool use = ((row0 + a) / N == (row0 + c) / N) && !own[a];
+            const zd t = mulc(g[a], g[c]);
+            if (use) s[a * 4 + c] = s[a * 4 + c] + t;
+          }
       }
+      // reduce-scatter over the 16 lanes: lane li ends with entry li
+#pragma unroll
+      for (int step = 0; step < 4; ++step) {
+        const int bit = 8 >> step;                 // 8, 4, 2, 1
+        const int half = bit;                      // entries exchanged
+        const bool hi = (li & bit) != 0;
+#pragma unroll
+        for (int e = 0; e < half; ++e) {
+          const zd keep = hi ? s[e + half] : s[e];
+          const zd send = hi ? s[e] : s[e + half];
+          const zd got = {__shfl_xor(send.x, bit, 64), __shfl_xor(send.y, bit, 64)};
+          s[e] = keep + got;
+        }
+      }
+      zd J = s[0];
+      if (L4.a == L4.b) J = {J.x + 1.0, 0.0};
+      const float2 fo = Fs[(row0 >> 2) * 16 + li];
+      zd F = {(double)fo.x, (double)fo.y};
+      const zd Lo = chol16(L4, J, ok);
+      F = trsm16(L4, Lo, F);                      // L^{-1} G_own
+      zd X = mm_hn(L4, F, F);                     // I + F^H F
+      if (L4.a == L4.b) X = {X.x + 1.0, 0.0};
+      UWr[i] = trsm16h(L4, Lo, F);                // J-^{-1} G_own
+      const zd Lw = chol16(L4, X, ok);
+      if (L4.a == L4.b) rsum += alpha[row0 + L4.a] * 2.0 * log(Lw.x);
+      const zd Li = trsm16(L4, Lw, zd{(L4.a == L4.b) ? 1.0 : 0.0, 0.0});
+      Er[i] = mm_hn(L4, Li, Li);                  // E = Lw^{-H} Lw^{-1}
+    }
+    if (!ok) atomicOr(&misc[0], AMMSE_INST_CHOLESKY);
+    return rsum;
+  };
+
+  // D = alpha U W U^H and Y = alpha U W per block user, into LDS
+  auto weights = [&](bool stage2) {
+#pragma unroll
+    for (int i = 0; i < S::GRB; ++i) {
+      const int row0 = 16 * (wave + 4 * i) + 4 * lk;
+      const zd T = mm_nn(L4, UWr[i], Er[i]);     // U
+      const zd Ur = stage2 ? UWr[i] : T;
+      zd Dv = mm_nh(L4, T, Ur);
+      const zd Dt = L4.at(Dv, L4.b, L4.a);
+      Dv = {0.5 * (Dv.x + Dt.x), 0.5 * (Dv.y - Dt.y)};   // exactly Hermitian
+      const double al = alpha[row0 + L4.a];
+      const int g4 = row0 >> 2;
+      Ds[g4 * 16 + li] = c2((float)(al * Dv.x), (float)(al * Dv.y));
+      Ys[g4 * 16 + li] = c2((float)(al * Ur.x), (float)(al * Ur.y));
     }
     __syncthreads();
   };
 
-  // lambda_max(H^H S D S H) by plain Lanczos, everything in LDS
+  // lambda_max(H^H S D S H) by plain Lanczos; H, D and the vectors in LDS
   auto lanczos = [&]() {
     zd* qa = Lq;
     zd* qb = Lq + M;
     zd* qc = Lq + 2 * M;
+    zd* Ly1 = Lq + 3 * M;
+    zd* Ly2 = Ly1 + UN;
     for (int i = tid; i < M; i += 256) {
       qb[i] = {1.0 + 0.5 * sin(0.731 * i + 0.25), 0.3 * cos(1.37 * i + 0.5)};
       qa[i] = {0.0, 0.0};
@@ -276,7 +369,7 @@ __global__ __launch_bounds__(256) void ammse_fast_kernel(ammse_kparams_t p) {
     for (int i = tid; i < M; i += 256) qb[i] = scal(1.0 / sqrt(nn), qb[i]);
     __syncthreads();
     const int m = min(p.lanczos_steps, M);
-    const double ltol = 1e-10;
+    const double ltol = 1e-7;
     double beta_prev = 0.0, tmax = 0.0, theta = 0.0;
     constexpr int TPR = 256 / UN;          // threads per row of H
     constexpr int TPC = 256 / M;           // threads per column of H
@@ -293,17 +386,18 @@ __global__ __launch_bounds__(256) void ammse_fast_kernel(ammse_kparams_t p) {
           acc.x += __shfl_xor(acc.x, o, 64);
           acc.y += __shfl_xor(acc.y, o, 64);
         }
-        if (part == 0) Ly1[r] = scal(invsig[r / N], acc);
+        if (part == 0) Ly1[r] = scal(invsig[r], acc);
       }
       __syncthreads();
-      for (int r = tid; r < UN; r += 256) {   // y2 = S D y1
-        const int u = r / N, n = r % N;
+      for (int r = tid; r < UN; r += 256) {   // y2 = S D y1 (block users)
+        const int g4 = r >> 2, a = r & 3;
         zd acc = {0.0, 0.0};
-        for (int k = 0; k < N; ++k) {
-          const float2 dd = Ds[u * 16 + n * 4 + k];
-          acc = acc + zd{(double)dd.x, (double)dd.y} * Ly1[u * N + k];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float2 dd = Ds[g4 * 16 + a * 4 + k];
+          acc = acc + zd{(double)dd.x, (double)dd.y} * Ly1[g4 * 4 + k];
         }
-        Ly2[r] = scal(invsig[u], acc);
+        Ly2[r] = scal(invsig[r], acc);
       }
       __syncthreads();
       double al = 0.0;
@@ -339,9 +433,9 @@ __global__ __launch_bounds__(256) void ammse_fast_kernel(ammse_kparams_t p) {
       const int msz = j + 1;
       tmax = fmax(tmax, fabs(al) + bb);
       const bool breakdown = !(bb > 1e-13 * tmax);
-      if (breakdown || (msz % 8) == 0 || msz == m) {
+      if (breakdown || (msz >= 8 && (msz % 4) == 0) || msz == m) {
         __syncthreads();
-        const double th = (tmax > 0.0) ? tridiag_lmax(la, lb, msz, &misc[1]) : 0.0;
+        const double th = (tmax > 0.0) ? tridiag_lmax(la, lb, msz, &misc[1], 1e-9) : 0.0;
         const bool conv = fabs(th - theta) <= ltol * fabs(th);
         theta = th;
         if (breakdown || conv) break;
@@ -377,10 +471,9 @@ __global__ __launch_bounds__(256) void ammse_fast_kernel(ammse_kparams_t p) {
   int iters_run = 0, status = 0;
 
   for (int t = 1; t <= T; ++t) {
-    receivers();
-    __syncthreads();
+    const double rs = receivers();
     wsr_prev2 = wsr_prev;
-    wsr_prev = wsr_sum();
+    wsr_prev = block_sum(rs, red) * (1.0 / M_LN2);
     if (p.trace && tid == 0) p.trace[(long)b * p.trace_len + (t - 1)] = wsr_prev;
     if (misc[0]) {
       status |= misc[0];
@@ -413,7 +506,13 @@ __global__ __launch_bounds__(256) void ammse_fast_kernel(ammse_kparams_t p) {
     // Z = S (D G^ - Y) from the registers, into Bs
     const float om = p.extrapolate ? (float)fmax((t - 2.0) / (t + 1.0), 0.0) : 0.f;
 #pragma unroll
-    for (int i = 0; i < S::GRB; ++i)
+    for (int i = 0; i < S::GRB; ++i) {
+      const int row0 = 16 * (wave + 4 * i) + 4 * lk, g4 = row0 >> 2, u0 = row0 / N;
+      float2 dm[4][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) dm[r][k] = Ds[g4 * 16 + r * 4 + k];
 #pragma unroll
       for (int j = 0; j < S::UDB; ++j) {
         float2 gh[4];
@@ -421,30 +520,26 @@ __global__ __launch_bounds__(256) void ammse_fast_kernel(ammse_kparams_t p) {
         for (int r = 0; r < 4; ++r)
           gh[r] = c2((1.f + om) * Gp[i][j][r].x - om * Gq[i][j][r].x,
                      (1.f + om) * Gp[i][j][r].y - om * Gq[i][j][r].y);
-        const int row0 = 16 * (wave + 4 * i) + 4 * lk, col = 16 * j + li;
+        const int col = 16 * j + li;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = row0 + r, u = row / N, n = row % N, base = u * N - row0;
           float zx = 0.f, zy = 0.f;
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
-            if (k < N) {
-              const float2 dd = Ds[u * 16 + n * 4 + k];
-              const float2 g = pick4(gh, base + k);
-              zx += dd.x * g.x - dd.y * g.y;
-              zy += dd.x * g.y + dd.y * g.x;
-            }
+            zx += dm[r][k].x * gh[k].x - dm[r][k].y * gh[k].y;
+            zy += dm[r][k].x * gh[k].y + dm[r][k].y * gh[k].x;
           }
-          const int s = col - u * d;
-          if (s >= 0 && s < d) {
-            const float2 y = Ys[u * 16 + n * 4 + s];
+          const int u = (row0 + r) / N, c = col - u * d;
+          if (c >= 0 && c < d) {
+            const float2 y = Ys[g4 * 16 + r * 4 + (u - u0) * N + c];
             zx -= y.x;
             zy -= y.y;
           }
-          const float is = (float)invsig[u];
-          Bs[row * S::BLD + col] = c2(is * zx, is * zy);
+          const float is = (float)invsig[row0 + r];
+          Bs[(row0 + r) * S::BLD + col] = c2(is * zx, is * zy);
         }
       }
+    }
     __syncthreads();
 
     // gradient and the extrapolated projected step, in registers
@@ -491,9 +586,8 @@ __global__ __launch_bounds__(256) void ammse_fast_kernel(ammse_kparams_t p) {
 
   double wsr_final;
   if (iters_run == T && !status) {
-    receivers();
-    __syncthreads();
-    wsr_final = wsr_sum();
+    const double rs = receivers();
+    wsr_final = block_sum(rs, red) * (1.0 / M_LN2);
     if (misc[0]) status |= misc[0];
     if (!isfinite(wsr_final)) status |= AMMSE_INST_NONFINITE;
     if (p.trace && tid == 0) p.trace[(long)b * p.trace_len + T] = wsr_final;
