@@ -193,6 +193,34 @@ __device__ __forceinline__ void wave_cgemm(const float2* __restrict__ A, int lda
   }
 }
 
+// Largest eigenvalue of a symmetric tridiagonal matrix (la, lb in LDS, m x m)
+// by multisection inside one wave: 64 probes per round on Sturm counts.
+
+__device__ __forceinline__ double wave_tridiag_lmax(const double* la, const double* lb, int m,
+                                                    double rtol) {
+  const int lane = threadIdx.x & 63;
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? fabs(lb[i - 1]) : 0.0) + (i < m - 1 ? fabs(lb[i]) : 0.0);
+    lo = fmin(lo, la[i] - r);
+    hi = fmax(hi, la[i] + r);
+  }
+  hi += fabs(hi) * 1e-6 + 1e-300;
+  for (int round = 0; round < 8; ++round) {
+    const double w = hi - lo;
+    if (!(w > fabs(hi) * rtol)) break;
+    const double x = lo + w * (double)(lane + 1) / 65.0;
+    const bool full = sturm_below(la, lb, m, x) == m;
+    const unsigned long long mask = __ballot(full);
+    const int t = mask ? (__ffsll((long long)mask) - 1) : 64;
+    const double nhi = (t < 64) ? lo + w * (double)(t + 1) / 65.0 : hi;
+    const double nlo = (t > 0) ? lo + w * (double)t / 65.0 : lo;
+    lo = nlo;
+    hi = nhi;
+  }
+  return hi;
+}
+
 template <class S>
 __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   extern __shared__ __align__(16) char smem[];
@@ -352,98 +380,118 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
     __syncthreads();
   };
 
-  // lambda_max(H^H S D S H) by plain Lanczos; H, D and the vectors in LDS
+  // lambda_max(H^H S D S H) by plain Lanczos with three block barriers per
+  // step.  Rows and columns of H are split over the waves in 16-row / 16-
+  // column strips (4 lanes per row or column, 16 entries each); the three
+  // inner products of a step are reduced together, and
+  //   beta^2 = ||w||^2 - alpha^2 - 2 beta_prev Re(p^H w) + beta_prev^2
+  // (w = A q, p = previous q, q unit and orthogonal to p).
   auto lanczos = [&]() {
-    zd* qa = Lq;
-    zd* qb = Lq + M;
-    zd* qc = Lq + 2 * M;
-    zd* Ly1 = Lq + 3 * M;
-    zd* Ly2 = Ly1 + UN;
+    static_assert(M == 64 && UN == 64, "16-row / 16-column strips per wave");
+    zd* qv = Lq;            // q_j
+    zd* pv = Lq + M;        // q_{j-1}
+    zd* y2v = Lq + 2 * M;   // S D S H q
+    double* part = (double*)(Lq + 2 * M + UN);   // [4 waves][4] partial sums
+    const int sub = lane & 3, idx = 16 * wave + (lane >> 2);   // row / column of this lane
     for (int i = tid; i < M; i += 256) {
-      qb[i] = {1.0 + 0.5 * sin(0.731 * i + 0.25), 0.3 * cos(1.37 * i + 0.5)};
-      qa[i] = {0.0, 0.0};
+      qv[i] = {1.0 + 0.5 * sin(0.731 * i + 0.25), 0.3 * cos(1.37 * i + 0.5)};
+      pv[i] = {0.0, 0.0};
     }
     double nn = 0.0;
-    for (int i = tid; i < M; i += 256) nn += nrm2(qb[i]);
+    for (int i = tid; i < M; i += 256) nn += nrm2(qv[i]);
     nn = block_sum(nn, red);
-    for (int i = tid; i < M; i += 256) qb[i] = scal(1.0 / sqrt(nn), qb[i]);
+    for (int i = tid; i < M; i += 256) qv[i] = scal(1.0 / sqrt(nn), qv[i]);
     __syncthreads();
     const int m = min(p.lanczos_steps, M);
-    const double ltol = 1e-7;
+    const double ltol = 1e-8;
     double beta_prev = 0.0, tmax = 0.0, theta = 0.0;
-    constexpr int TPR = 256 / UN;          // threads per row of H
-    constexpr int TPC = 256 / M;           // threads per column of H
+    const double isg = invsig[idx];
+    const int a4 = idx & 3;
     for (int j = 0; j < m; ++j) {
-      {  // y1 = S H q
-        const int r = tid / TPR, part = tid % TPR;
-        zd acc = {0.0, 0.0};
-        for (int c = part; c < M; c += TPR) {
-          const float2 h = Hs[r * S::HLD + c];
-          acc = acc + zd{(double)h.x, (double)h.y} * qb[c];
-        }
+      // y1 for row idx (4 lanes x 16 columns), then y2 = S D y1 in the block user
+      zd y1 = {0.0, 0.0};
+#pragma unroll 4
+      for (int k = 0; k < 16; ++k) {
+        const int c = 16 * sub + ((k + idx) & 15);
+        const float2 h = Hs[idx * S::HLD + c];
+        y1 = y1 + zd{(double)h.x, (double)h.y} * qv[c];
+      }
+      y1.x += __shfl_xor(y1.x, 1, 64);
+      y1.y += __shfl_xor(y1.y, 1, 64);
+      y1.x += __shfl_xor(y1.x, 2, 64);
+      y1.y += __shfl_xor(y1.y, 2, 64);
+      y1 = scal(isg, y1);
+      zd y2 = {0.0, 0.0};
 #pragma unroll
-        for (int o = 1; o < TPR; o <<= 1) {
-          acc.x += __shfl_xor(acc.x, o, 64);
-          acc.y += __shfl_xor(acc.y, o, 64);
-        }
-        if (part == 0) Ly1[r] = scal(invsig[r], acc);
+      for (int k = 0; k < 4; ++k) {      // rows (idx & ~3) + k live on lanes 16*(..)+4k+sub
+        const float2 dd = Ds[(idx >> 2) * 16 + a4 * 4 + k];
+        const zd yk = shz(y1, (lane & ~15) + 4 * k + sub);
+        y2 = y2 + zd{(double)dd.x, (double)dd.y} * yk;
+      }
+      if (sub == 0) y2v[idx] = scal(isg, y2);
+      __syncthreads();
+      // w for column idx (4 lanes x 16 rows) and the partial inner products
+      zd w = {0.0, 0.0};
+#pragma unroll 4
+      for (int k = 0; k < 16; ++k) {
+        const int r = 16 * sub + k;
+        const float2 h = Hs[r * S::HLD + idx];
+        w = w + zd{(double)h.x, -(double)h.y} * y2v[r];
+      }
+      w.x += __shfl_xor(w.x, 1, 64);
+      w.y += __shfl_xor(w.y, 1, 64);
+      w.x += __shfl_xor(w.x, 2, 64);
+      w.y += __shfl_xor(w.y, 2, 64);
+      const zd qc = qv[idx], pc = pv[idx];
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+      if (sub == 0) {
+        s0 = nrm2(w);
+        s1 = qc.x * w.x + qc.y * w.y;
+        s2 = pc.x * w.x + pc.y * w.y;
+      }
+      s0 = wave_sum(s0);
+      s1 = wave_sum(s1);
+      s2 = wave_sum(s2);
+      if (lane == 0) {
+        part[wave * 4 + 0] = s0;
+        part[wave * 4 + 1] = s1;
+        part[wave * 4 + 2] = s2;
       }
       __syncthreads();
-      for (int r = tid; r < UN; r += 256) {   // y2 = S D y1 (block users)
-        const int g4 = r >> 2, a = r & 3;
-        zd acc = {0.0, 0.0};
+      double ww = 0.0, al = 0.0, pw = 0.0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const float2 dd = Ds[g4 * 16 + a * 4 + k];
-          acc = acc + zd{(double)dd.x, (double)dd.y} * Ly1[g4 * 4 + k];
-        }
-        Ly2[r] = scal(invsig[r], acc);
+      for (int q = 0; q < 4; ++q) {
+        ww += part[q * 4 + 0];
+        al += part[q * 4 + 1];
+        pw += part[q * 4 + 2];
       }
-      __syncthreads();
-      double al = 0.0;
-      {  // w = H^H y2
-        const int c = tid / TPC, part = tid % TPC;
-        zd acc = {0.0, 0.0};
-        for (int r = part; r < UN; r += TPC) {
-          const float2 h = Hs[r * S::HLD + c];
-          acc = acc + zd{(double)h.x, -(double)h.y} * Ly2[r];
-        }
-#pragma unroll
-        for (int o = 1; o < TPC; o <<= 1) {
-          acc.x += __shfl_xor(acc.x, o, 64);
-          acc.y += __shfl_xor(acc.y, o, 64);
-        }
-        if (part == 0) {
-          qc[c] = acc;
-          al = qb[c].x * acc.x + qb[c].y * acc.y;
-        }
-      }
-      al = block_sum(al, red);
-      double bb = 0.0;
-      for (int i = tid; i < M; i += 256) {
-        const zd w = qc[i] - scal(al, qb[i]) - scal(beta_prev, qa[i]);
-        qc[i] = w;
-        bb += nrm2(w);
-      }
-      bb = sqrt(block_sum(bb, red));
+      const double bb = sqrt(fmax(ww - al * al - 2.0 * beta_prev * pw + beta_prev * beta_prev, 0.0));
       if (tid == 0) {
         la[j] = al;
         lb[j] = bb;
       }
       const int msz = j + 1;
       tmax = fmax(tmax, fabs(al) + bb);
-      const bool breakdown = !(bb > 1e-13 * tmax);
-      if (breakdown || (msz >= 8 && (msz % 4) == 0) || msz == m) {
+      const bool breakdown = !(bb > 1e-12 * tmax);
+      bool stop = breakdown;
+      if (breakdown || (msz >= 12 && (msz % 4) == 0) || msz == m) {
+        // wave 0 brackets the largest Ritz value; the others wait
         __syncthreads();
-        const double th = (tmax > 0.0) ? tridiag_lmax(la, lb, msz, &misc[1], 1e-9) : 0.0;
-        const bool conv = fabs(th - theta) <= ltol * fabs(th);
+        if (wave == 0) {
+          const double th = (tmax > 0.0) ? wave_tridiag_lmax(la, lb, msz, 1e-10) : 0.0;
+          if (lane == 0) red[7] = th;
+        }
+        __syncthreads();
+        const double th = red[7];
+        stop = stop || fabs(th - theta) <= ltol * fabs(th);
         theta = th;
-        if (breakdown || conv) break;
       }
-      const double ib = 1.0 / bb;
-      for (int i = tid; i < M; i += 256) {
-        qa[i] = qb[i];
-        qb[i] = scal(ib, qc[i]);
+      if (stop) break;
+      __syncthreads();        // everyone has read q_j, p before they are replaced
+      if (sub == 0) {
+        const zd wn = w - scal(al, qc) - scal(beta_prev, pc);
+        pv[idx] = qc;
+        qv[idx] = scal(1.0 / bb, wn);
       }
       beta_prev = bb;
       __syncthreads();

@@ -252,10 +252,12 @@ def test_fp32_rayleigh_sweep_subset():
     sub = b.subset(idx)
     opts = ammse.Options(precision=ammse.PREC_FP32, max_iters=100)
     say("case: rayleigh sweep fp32 subset")
-    res = ammse.solve(sub, opts)
+    res = ammse.solve(sub, opts, want_trace=True)
     assert np.all(res.status == 0)
     refs = oracle_runs(sub, range(sub.batch), iters=100)
-    compare_wsr(sub, res, refs, list(range(sub.batch)), opts, 1e-4)
+    h = compare_traces(sub, res, refs, list(range(sub.batch)), opts, 1e-4, 100)
+    say("stable horizons", h)
+    assert sum(x == 100 for x in h) >= 4
 
 
 def test_fp32_full_bench_batch_sampled():
@@ -275,7 +277,8 @@ def test_fp32_full_bench_batch_sampled():
         assert np.vdot(Vi, Vi).real <= b.P[i] * (1 + 1e-5)
     idx = [3, 300, 555, 1000]
     refs = oracle_runs(b, idx, iters=100)
-    compare_wsr(b, res, refs, idx, opts, 1e-4)
+    h = compare_traces(b, res, refs, idx, opts, 1e-4, 100)
+    say("stable horizons", h)
 
 
 def test_fp64_hexcell_iterates():
