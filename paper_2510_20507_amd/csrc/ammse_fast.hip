@@ -54,13 +54,17 @@ struct Shape {
   static constexpr size_t oF = oB + sizeof(float2) * BROWS * BLD;   // own blocks of G
   static constexpr size_t oD = oF + sizeof(float2) * NG * 16;       // D per block user
   static constexpr size_t oY = oD + sizeof(float2) * NG * 16;       // Y per block user
-  static constexpr size_t oS = oY + sizeof(float2) * NG * 16;       // invsig, alpha per row
+  static constexpr size_t oQ = oY + sizeof(float2) * NG * 16;       // S H H^H S (UN x UN)
+  static constexpr size_t QLD = UN + 2;
+  static constexpr size_t oC = oQ + sizeof(float2) * UN * QLD;      // C per block user (D = C C^H)
+  static constexpr size_t oS = oC + sizeof(zd) * NG * 16;           // invsig, alpha per row
   static constexpr size_t oL = oS + sizeof(double) * 2 * UN;        // la, lb
   static constexpr size_t oR = oL + sizeof(double) * 2 * AMMSE_MAX_LANCZOS;
   static constexpr size_t bytes = oR + sizeof(double) * 8 + 16;
-  // Lanczos vectors (double complex) alias the product-operand area, which
-  // is free between the last product of an iteration and the Z build.
-  static_assert(sizeof(zd) * (3 * M + 2 * UN) <= sizeof(float2) * BROWS * BLD, "Lanczos area");
+  // Lanczos vectors alias the product-operand area, which is free between
+  // the last product of an iteration and the Z build.
+  static_assert(sizeof(zd) * 2 * UN + 64 * sizeof(double) <= sizeof(float2) * BROWS * BLD,
+                "Lanczos area");
 };
 
 __device__ __forceinline__ float2 c2(float x, float y) { return make_float2(x, y); }
@@ -141,8 +145,9 @@ __device__ __forceinline__ zd mm_nh(const Lane4& L, zd A, zd B) {
 
 // One wave: P[i][j] (three real accumulators) = op(A) B for the wave's row
 // blocks i (global row block wave + 4 i) and all column blocks j.
-// op(A)[r][k] = A[r*lda + k], or conj(A[k*lda + r]) with CONJA.
-template <int NRB, int NCB, bool CONJA>
+// op(A)[r][k] = A[r*lda + k], or conj(A[k*lda + r]) with CONJA; B[k][j] is
+// B[k*ldb + j], or conj(B[j*ldb + k]) with CONJBT.
+template <int NRB, int NCB, bool CONJA, bool CONJBT = false>
 __device__ __forceinline__ void wave_cgemm(const float2* __restrict__ A, int lda,
                                            const float2* __restrict__ B, int ldb, int K,
                                            int wave, floatx4 (&P)[NRB][NCB][3]) {
@@ -169,7 +174,14 @@ __device__ __forceinline__ void wave_cgemm(const float2* __restrict__ A, int lda
       }
     }
 #pragma unroll
-    for (int j = 0; j < NCB; ++j) b[j] = B[kk * ldb + 16 * j + li];
+    for (int j = 0; j < NCB; ++j) {
+      if (CONJBT) {
+        const float2 h = B[(16 * j + li) * ldb + kk];
+        b[j] = c2(h.x, -h.y);
+      } else {
+        b[j] = B[kk * ldb + 16 * j + li];
+      }
+    }
 #pragma unroll
     for (int i = 0; i < NRB; ++i)
 #pragma unroll
@@ -229,6 +241,8 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   float2* Fs = (float2*)(smem + S::oF);
   float2* Ds = (float2*)(smem + S::oD);
   float2* Ys = (float2*)(smem + S::oY);
+  float2* Qs = (float2*)(smem + S::oQ);
+  zd* Cs = (zd*)(smem + S::oC);
   double* invsig = (double*)(smem + S::oS);    // per row: 1/sigma of the row's user
   double* alpha = invsig + S::UN;              // per row: alpha of the row's user
   double* la = (double*)(smem + S::oL);
@@ -240,6 +254,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   constexpr int M = S::M, UN = S::UN, UD = S::UD;
   const ammse_desc_t Dd = p.desc[blockIdx.x];
   const int N = Dd.N, d = Dd.d;
+  const int lgN = __builtin_ctz(N), lgd = __builtin_ctz(d);   // N, d in {1, 2, 4}
   const int b = Dd.b;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
@@ -274,6 +289,35 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
         Vq[i][j][r] = Vp[i][j][r];
       }
 
+  // Q = S H H^H S for the step-size operator, once per solve
+  {
+    floatx4 P[S::GRB][S::UNB][3];
+    wave_cgemm<S::GRB, S::UNB, false, true>(Hs, S::HLD, Hs, S::HLD, M, wave, P);
+#pragma unroll
+    for (int i = 0; i < S::GRB; ++i)
+#pragma unroll
+      for (int j = 0; j < S::UNB; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * (wave + 4 * i) + 4 * lk + r, col = 16 * j + li;
+          const float s = (float)(invsig[row] * invsig[col]);
+          Qs[row * S::QLD + col] = c2(s * (P[i][j][0][r] - P[i][j][1][r]), s * P[i][j][2][r]);
+        }
+    __syncthreads();
+    for (int e = tid; e < UN * UN; e += 256) {      // exactly Hermitian
+      const int r = e / UN, c = e % UN;
+      if (r < c) {
+        const float2 x = Qs[r * S::QLD + c], y = Qs[c * S::QLD + r];
+        const float2 mm = c2(0.5f * (x.x + y.x), 0.5f * (x.y - y.y));
+        Qs[r * S::QLD + c] = mm;
+        Qs[c * S::QLD + r] = c2(mm.x, -mm.y);
+      } else if (r == c) {
+        Qs[r * S::QLD + c].y = 0.f;
+      }
+    }
+    __syncthreads();
+  }
+
   // G = S H V (V in Bs) into Gp (previous Gp to Gq); own blocks into Fs
   auto product_G = [&]() {
     floatx4 P[S::GRB][S::UDB][3];
@@ -289,10 +333,10 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
           const float2 g = c2(s * (P[i][j][0][r] - P[i][j][1][r]), s * P[i][j][2][r]);
           Gq[i][j][r] = Gp[i][j][r];
           Gp[i][j][r] = g;
-          const int u = row / N, c = col - u * d;
+          const int u = row >> lgN, c = col - (u << lgd);
           if (c >= 0 && c < d) {
-            const int g4 = row >> 2, u0 = (g4 * 4) / N;
-            Fs[g4 * 16 + r * 4 + (u - u0) * N + c] = g;
+            const int g4 = row >> 2, u0 = (g4 * 4) >> lgN;
+            Fs[g4 * 16 + r * 4 + ((u - u0) << lgN) + c] = g;
           }
         }
   };
@@ -300,7 +344,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   // Per block user (i = row block of this wave, group lk): J-, Cholesky,
   // rate, UW = J-^{-1} G_own and E = (I + G_own^H J-^{-1} G_own)^{-1}.
   // Returns the weighted rate contribution of this lane (diagonal lanes).
-  zd UWr[S::GRB], Er[S::GRB];
+  zd UWr[S::GRB], Er[S::GRB], Lir[S::GRB];
   auto receivers = [&]() {
     double rsum = 0.0;
     bool ok = true;
@@ -319,13 +363,13 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           g[r] = {(double)Gp[i][j][r].x, (double)Gp[i][j][r].y};
-          own[r] = (col / d) == ((row0 + r) / N);
+          own[r] = (col >> lgd) == ((row0 + r) >> lgN);
         }
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
-            const bool use = ((row0 + a) / N == (row0 + c) / N) && !own[a];
+            const bool use = ((row0 + a) >> lgN == (row0 + c) >> lgN) && !own[a];
             const zd t = mulc(g[a], g[c]);
             if (use) s[a * 4 + c] = s[a * 4 + c] + t;
           }
@@ -357,6 +401,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
       if (L4.a == L4.b) rsum += alpha[row0 + L4.a] * 2.0 * log(Lw.x);
       const zd Li = trsm16(L4, Lw, zd{(L4.a == L4.b) ? 1.0 : 0.0, 0.0});
       Er[i] = mm_hn(L4, Li, Li);                  // E = Lw^{-H} Lw^{-1}
+      Lir[i] = Li;
     }
     if (!ok) atomicOr(&misc[0], AMMSE_INST_CHOLESKY);
     return rsum;
@@ -376,78 +421,67 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
       const int g4 = row0 >> 2;
       Ds[g4 * 16 + li] = c2((float)(al * Dv.x), (float)(al * Dv.y));
       Ys[g4 * 16 + li] = c2((float)(al * Ur.x), (float)(al * Ur.y));
+      // D = C C^H: C = sqrt(alpha) U (stage I) or sqrt(alpha) UW Lw^{-H} (stage II)
+      const zd Cv = stage2 ? mm_nh(L4, UWr[i], Lir[i]) : T;
+      Cs[g4 * 16 + li] = scal(sqrt(al), Cv);
     }
     __syncthreads();
   };
 
-  // lambda_max(H^H S D S H) by plain Lanczos with three block barriers per
-  // step.  Rows and columns of H are split over the waves in 16-row / 16-
-  // column strips (4 lanes per row or column, 16 entries each); the three
-  // inner products of a step are reduced together, and
-  //   beta^2 = ||w||^2 - alpha^2 - 2 beta_prev Re(p^H w) + beta_prev^2
-  // (w = A q, p = previous q, q unit and orthogonal to p).
+  // lambda_max(A), A = H^H S D S H.  With D = C C^H (C block diagonal) and
+  // Q = S H H^H S (formed once per solve), lambda_max(A) = lambda_max(K) for
+  // the U N x U N matrix K = C^H Q C; plain Lanczos on K, two block barriers
+  // per step.  Row r of K is handled by 4 lanes (16 columns each); the
+  // Lanczos vectors stay in registers (every lane of a row holds its entry);
+  // u = C x goes through LDS for the dense product with Q;
+  //   beta^2 = ||y||^2 - alpha^2 - 2 beta_prev Re(p^H y) + beta_prev^2.
   auto lanczos = [&]() {
-    static_assert(M == 64 && UN == 64, "16-row / 16-column strips per wave");
-    zd* qv = Lq;            // q_j
-    zd* pv = Lq + M;        // q_{j-1}
-    zd* y2v = Lq + 2 * M;   // S D S H q
-    double* part = (double*)(Lq + 2 * M + UN);   // [4 waves][4] partial sums
-    const int sub = lane & 3, idx = 16 * wave + (lane >> 2);   // row / column of this lane
-    for (int i = tid; i < M; i += 256) {
-      qv[i] = {1.0 + 0.5 * sin(0.731 * i + 0.25), 0.3 * cos(1.37 * i + 0.5)};
-      pv[i] = {0.0, 0.0};
+    static_assert(UN == 64, "16-row strips per wave");
+    zd* uv = Lq;                                  // u = C x
+    double* part = (double*)(Lq + UN);            // [4 waves][4] partial sums
+    const int sub = lane & 3, idx = 16 * wave + (lane >> 2), gq = lane & ~15;
+    const int g4 = idx >> 2, a4 = idx & 3;
+    zd cr[4], cc[4];                              // row a4 of C, column a4 of C
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      cr[k] = Cs[g4 * 16 + a4 * 4 + k];
+      cc[k] = Cs[g4 * 16 + k * 4 + a4];
     }
-    double nn = 0.0;
-    for (int i = tid; i < M; i += 256) nn += nrm2(qv[i]);
-    nn = block_sum(nn, red);
-    for (int i = tid; i < M; i += 256) qv[i] = scal(1.0 / sqrt(nn), qv[i]);
+    zd x = {1.0 + 0.5 * sin(0.731 * idx + 0.25), 0.3 * cos(1.37 * idx + 0.5)};
+    const double nn = block_sum((sub == 0) ? nrm2(x) : 0.0, red);
+    x = scal(1.0 / sqrt(nn), x);
+    zd pp = {0.0, 0.0};
+    auto put_u = [&]() {                          // u = C x for row idx
+      zd u = {0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) u = u + cr[k] * shz(x, gq + 4 * k + sub);
+      if (sub == 0) uv[idx] = u;
+    };
+    put_u();
     __syncthreads();
-    const int m = min(p.lanczos_steps, M);
+    const int m = min(p.lanczos_steps, UN);
     const double ltol = 1e-8;
     double beta_prev = 0.0, tmax = 0.0, theta = 0.0;
-    const double isg = invsig[idx];
-    const int a4 = idx & 3;
     for (int j = 0; j < m; ++j) {
-      // y1 for row idx (4 lanes x 16 columns), then y2 = S D y1 in the block user
-      zd y1 = {0.0, 0.0};
+      zd z = {0.0, 0.0};
 #pragma unroll 4
       for (int k = 0; k < 16; ++k) {
         const int c = 16 * sub + ((k + idx) & 15);
-        const float2 h = Hs[idx * S::HLD + c];
-        y1 = y1 + zd{(double)h.x, (double)h.y} * qv[c];
+        const float2 q = Qs[idx * S::QLD + c];
+        z = z + zd{(double)q.x, (double)q.y} * uv[c];
       }
-      y1.x += __shfl_xor(y1.x, 1, 64);
-      y1.y += __shfl_xor(y1.y, 1, 64);
-      y1.x += __shfl_xor(y1.x, 2, 64);
-      y1.y += __shfl_xor(y1.y, 2, 64);
-      y1 = scal(isg, y1);
-      zd y2 = {0.0, 0.0};
+      z.x += __shfl_xor(z.x, 1, 64);
+      z.y += __shfl_xor(z.y, 1, 64);
+      z.x += __shfl_xor(z.x, 2, 64);
+      z.y += __shfl_xor(z.y, 2, 64);
+      zd y = {0.0, 0.0};                          // y = C^H z in the block user
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {      // rows (idx & ~3) + k live on lanes 16*(..)+4k+sub
-        const float2 dd = Ds[(idx >> 2) * 16 + a4 * 4 + k];
-        const zd yk = shz(y1, (lane & ~15) + 4 * k + sub);
-        y2 = y2 + zd{(double)dd.x, (double)dd.y} * yk;
-      }
-      if (sub == 0) y2v[idx] = scal(isg, y2);
-      __syncthreads();
-      // w for column idx (4 lanes x 16 rows) and the partial inner products
-      zd w = {0.0, 0.0};
-#pragma unroll 4
-      for (int k = 0; k < 16; ++k) {
-        const int r = 16 * sub + k;
-        const float2 h = Hs[r * S::HLD + idx];
-        w = w + zd{(double)h.x, -(double)h.y} * y2v[r];
-      }
-      w.x += __shfl_xor(w.x, 1, 64);
-      w.y += __shfl_xor(w.y, 1, 64);
-      w.x += __shfl_xor(w.x, 2, 64);
-      w.y += __shfl_xor(w.y, 2, 64);
-      const zd qc = qv[idx], pc = pv[idx];
+      for (int k = 0; k < 4; ++k) y = y + cj(cc[k]) * shz(z, gq + 4 * k + sub);
       double s0 = 0.0, s1 = 0.0, s2 = 0.0;
       if (sub == 0) {
-        s0 = nrm2(w);
-        s1 = qc.x * w.x + qc.y * w.y;
-        s2 = pc.x * w.x + pc.y * w.y;
+        s0 = nrm2(y);
+        s1 = x.x * y.x + x.y * y.y;
+        s2 = pp.x * y.x + pp.y * y.y;
       }
       s0 = wave_sum(s0);
       s1 = wave_sum(s1);
@@ -458,14 +492,14 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
         part[wave * 4 + 2] = s2;
       }
       __syncthreads();
-      double ww = 0.0, al = 0.0, pw = 0.0;
+      double yy = 0.0, al = 0.0, py = 0.0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        ww += part[q * 4 + 0];
+        yy += part[q * 4 + 0];
         al += part[q * 4 + 1];
-        pw += part[q * 4 + 2];
+        py += part[q * 4 + 2];
       }
-      const double bb = sqrt(fmax(ww - al * al - 2.0 * beta_prev * pw + beta_prev * beta_prev, 0.0));
+      const double bb = sqrt(fmax(yy - al * al - 2.0 * beta_prev * py + beta_prev * beta_prev, 0.0));
       if (tid == 0) {
         la[j] = al;
         lb[j] = bb;
@@ -475,7 +509,6 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
       const bool breakdown = !(bb > 1e-12 * tmax);
       bool stop = breakdown;
       if (breakdown || (msz >= 12 && (msz % 4) == 0) || msz == m) {
-        // wave 0 brackets the largest Ritz value; the others wait
         __syncthreads();
         if (wave == 0) {
           const double th = (tmax > 0.0) ? wave_tridiag_lmax(la, lb, msz, 1e-10) : 0.0;
@@ -487,13 +520,11 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
         theta = th;
       }
       if (stop) break;
-      __syncthreads();        // everyone has read q_j, p before they are replaced
-      if (sub == 0) {
-        const zd wn = w - scal(al, qc) - scal(beta_prev, pc);
-        pv[idx] = qc;
-        qv[idx] = scal(1.0 / bb, wn);
-      }
+      const zd xn = scal(1.0 / bb, y - scal(al, x) - scal(beta_prev, pp));
+      pp = x;
+      x = xn;
       beta_prev = bb;
+      put_u();
       __syncthreads();
     }
     __syncthreads();
@@ -555,7 +586,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
     const float om = p.extrapolate ? (float)fmax((t - 2.0) / (t + 1.0), 0.0) : 0.f;
 #pragma unroll
     for (int i = 0; i < S::GRB; ++i) {
-      const int row0 = 16 * (wave + 4 * i) + 4 * lk, g4 = row0 >> 2, u0 = row0 / N;
+      const int row0 = 16 * (wave + 4 * i) + 4 * lk, g4 = row0 >> 2, u0 = row0 >> lgN;
       float2 dm[4][4];
 #pragma unroll
       for (int r = 0; r < 4; ++r)
@@ -577,9 +608,9 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
             zx += dm[r][k].x * gh[k].x - dm[r][k].y * gh[k].y;
             zy += dm[r][k].x * gh[k].y + dm[r][k].y * gh[k].x;
           }
-          const int u = (row0 + r) / N, c = col - u * d;
+          const int u = (row0 + r) >> lgN, c = col - (u << lgd);
           if (c >= 0 && c < d) {
-            const float2 y = Ys[g4 * 16 + r * 4 + (u - u0) * N + c];
+            const float2 y = Ys[g4 * 16 + r * 4 + ((u - u0) << lgN) + c];
             zx -= y.x;
             zy -= y.y;
           }
