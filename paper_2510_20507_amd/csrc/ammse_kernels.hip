@@ -129,6 +129,99 @@ __device__ void block_gemm(int m, int n, int k, const cx<R>* __restrict__ A, lon
   }
 }
 
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+// FP32 variant on MFMA (v_mfma_f32_16x16x4f32): same LDS staging, each wave
+// computes a 16 x 64 strip of the 64 x 64 output tile; a complex product is
+// three real accumulators (Re*Re, Im*Im, Re*Im + Im*Re).
+template <bool CONJA>
+__device__ void block_gemm_mfma(int m, int n, int k, const cx<float>* __restrict__ A, long lda,
+                                const cx<float>* __restrict__ B, long ldb,
+                                cx<float>* __restrict__ Cm, long ldc, float alpha,
+                                const double* rowscale, int rs_div, cx<float>* As,
+                                cx<float>* Bs) {
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  for (int i0 = 0; i0 < m; i0 += TM) {
+    for (int j0 = 0; j0 < n; j0 += TN) {
+      floatx4_t P[4][3];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) P[j][q] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+      for (int k0 = 0; k0 < k; k0 += KC) {
+        for (int e = tid; e < TM * KC; e += AMMSE_BLOCK) {
+          int row, kk;
+          if (CONJA) {
+            row = e % TM;
+            kk = e / TM;
+          } else {
+            kk = e % KC;
+            row = e / KC;
+          }
+          const int gi = i0 + row, gk = k0 + kk;
+          cx<float> v = {0.f, 0.f};
+          if (gi < m && gk < k) v = CONJA ? cj(A[(long)gk * lda + gi]) : A[(long)gi * lda + gk];
+          As[kk * (TM + 1) + row] = v;
+        }
+        for (int e = tid; e < KC * TN; e += AMMSE_BLOCK) {
+          const int col = e % TN, kk = e / TN;
+          const int gj = j0 + col, gk = k0 + kk;
+          cx<float> v = {0.f, 0.f};
+          if (gj < n && gk < k) v = B[(long)gk * ldb + gj];
+          Bs[kk * (TN + 1) + col] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += 4) {
+          const cx<float> a = As[(kk + lk) * (TM + 1) + 16 * wave + li];
+          cx<float> b[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) b[j] = Bs[(kk + lk) * (TN + 1) + 16 * j + li];
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            P[j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b[j].x, P[j][0], 0, 0, 0);
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            P[j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b[j].y, P[j][1], 0, 0, 0);
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            P[j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b[j].y, P[j][2], 0, 0, 0);
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            P[j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b[j].x, P[j][2], 0, 0, 0);
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = i0 + 16 * wave + 4 * lk + r;
+        if (gi >= m) continue;
+        float s = alpha;
+        if (rowscale) s *= (float)rowscale[gi / rs_div];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int gj = j0 + 16 * j + li;
+          if (gj < n) Cm[(long)gi * ldc + gj] = {s * (P[j][0][r] - P[j][1][r]), s * P[j][2][r]};
+        }
+      }
+    }
+  }
+}
+
+// Channel product dispatch: MFMA for FP32 storage, LDS-tiled FMA for FP64.
+template <class R, bool CONJA>
+__device__ __forceinline__ void channel_gemm(int m, int n, int k, const cx<R>* A, long lda,
+                                             const cx<R>* B, long ldb, cx<R>* Cm, long ldc,
+                                             R alpha, const double* rowscale, int rs_div,
+                                             cx<R>* As, cx<R>* Bs) {
+  if constexpr (sizeof(R) == 4) {
+    block_gemm_mfma<CONJA>(m, n, k, A, lda, B, ldb, Cm, ldc, alpha, rowscale, rs_div, As, Bs);
+  } else {
+    block_gemm<R, CONJA>(m, n, k, A, lda, B, ldb, Cm, ldc, alpha, rowscale, rs_div, As, Bs);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // The fused kernel
 // ---------------------------------------------------------------------------
@@ -186,7 +279,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
     for (int c = 0; c < C; ++c) {
       const int nc = sm.cu[c] * d;
       if (nc == 0) continue;
-      block_gemm<R, false>(un, nc, M, H + (long)c * un * M, M, Vsrc + (long)M * sm.colOff[c], nc,
+      channel_gemm<R, false>(un, nc, M, H + (long)c * un * M, M, Vsrc + (long)M * sm.colOff[c], nc,
                            G + (long)un * sm.colOff[c], nc, R(1), sm.invsig, N, sm.As, sm.Bs);
     }
   };
@@ -450,7 +543,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
     for (int c = 0; c < C; ++c) {
       const int nc = sm.cu[c] * d;
       if (nc == 0) continue;
-      block_gemm<R, true>(M, nc, un, H + (long)c * un * M, M, Z + (long)un * sm.colOff[c], nc,
+      channel_gemm<R, true>(M, nc, un, H + (long)c * un * M, M, Z + (long)un * sm.colOff[c], nc,
                           Gr + (long)M * sm.colOff[c], nc, R(2), nullptr, 1, sm.As, sm.Bs);
     }
     __syncthreads();
