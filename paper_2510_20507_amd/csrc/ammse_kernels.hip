@@ -50,7 +50,7 @@ struct Smem {
   double la[AMMSE_MAX_LANCZOS];
   double lb[AMMSE_MAX_LANCZOS];
   zd h[AMMSE_MAX_LANCZOS];
-  double red[8];
+  double red[16];
   int fail;
   int imin;
 };
@@ -362,90 +362,125 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
     __syncthreads();
   };
 
-  // lambda_max(A_c), A_c = H_c^H S D S H_c, by Lanczos.
+  // lambda_max(A_c), A_c = H_c^H S D S H_c, by plain three-term Lanczos (the
+  // largest Ritz value converges without re-orthogonalisation).  Products
+  // with H use several threads per row / column (a power of two within one
+  // wave, combined by shuffles); the three inner products of a step are
+  // reduced together.  FP64 forms ||w - alpha q - beta p|| explicitly, FP32
+  // uses beta^2 = ||w||^2 - alpha^2 - 2 beta_prev Re(p^H w) + beta_prev^2.
   auto lanczos_lmax = [&](int c) {
-    const cx<R>* Hc = H + (long)c * un * M;
-    const int m = min(p.lanczos_steps, M);
+    const cx<R>* __restrict__ Hc = H + (long)c * un * M;
+    zd* qv = Lq;
+    zd* pv = Lq + M;
+    zd* wv = Lq + 2 * M;
+    int tpr = 1;
+    while (tpr < 64 && tpr * 2 * un <= AMMSE_BLOCK) tpr *= 2;
+    int tpc = 1;
+    while (tpc < 64 && tpc * 2 * M <= AMMSE_BLOCK) tpc *= 2;
     for (int i = tid; i < M; i += AMMSE_BLOCK) {
-      const double s = 1.0 + 0.5 * sin(0.731 * i + 0.25), t = cos(1.37 * i + 0.5);
-      Lq[i] = {s, 0.3 * t};
+      qv[i] = {1.0 + 0.5 * sin(0.731 * i + 0.25), 0.3 * cos(1.37 * i + 0.5)};
+      pv[i] = {0.0, 0.0};
     }
     double nn = 0.0;
-    for (int i = tid; i < M; i += AMMSE_BLOCK) nn += nrm2(Lq[i]);
+    for (int i = tid; i < M; i += AMMSE_BLOCK) nn += nrm2(qv[i]);
     nn = block_sum(nn, sm.red);
-    {
-      const double inv = 1.0 / sqrt(nn);
-      for (int i = tid; i < M; i += AMMSE_BLOCK) Lq[i] = scal(inv, Lq[i]);
-    }
+    for (int i = tid; i < M; i += AMMSE_BLOCK) qv[i] = scal(1.0 / sqrt(nn), qv[i]);
     __syncthreads();
-    // plain three-term Lanczos: the largest Ritz value converges to
-    // lambda_max without re-orthogonalisation (lost orthogonality only adds
-    // copies of converged eigenvalues); convergence is tested every 8 steps
-    const double ltol = (sizeof(R) == 8) ? 1e-14 : 1e-10;
-    zd* qa = Lq;            // q_{j-1}
-    zd* qb = Lq + M;        // q_j
-    zd* qc = Lq + 2 * M;    // w
-    for (int i = tid; i < M; i += AMMSE_BLOCK) {
-      qb[i] = Lq[i];
-      qa[i] = {0.0, 0.0};
-    }
-    __syncthreads();
-    int msz = 0;
+    const int m = min(p.lanczos_steps, M);
+    constexpr bool exact_beta = sizeof(R) == 8;
+    const double ltol = exact_beta ? 1e-14 : 1e-8;
+    const double rtol = exact_beta ? 1e-16 : 1e-10;
+    const int first = exact_beta ? 8 : 12, every = exact_beta ? 8 : 4;
     double beta_prev = 0.0, tmax = 0.0, theta = 0.0;
-    const int wv = tid >> 6, ln = tid & 63;
     for (int j = 0; j < m; ++j) {
-      // y1 = S H q
-      for (int r = wv; r < un; r += AMMSE_BLOCK / 64) {
-        zd acc = {0.0, 0.0};
-        for (int i = ln; i < M; i += 64) acc = acc + to_d(Hc[(long)r * M + i]) * qb[i];
-        acc.x = wave_sum(acc.x);
-        acc.y = wave_sum(acc.y);
-        if (ln == 0) Ly1[r] = scal(sm.invsig[r / N], acc);
+      {  // y1 = S H q
+        const int part = tid & (tpr - 1);
+        for (int r = tid / tpr; r < un; r += AMMSE_BLOCK / tpr) {
+          const cx<R>* __restrict__ hr = Hc + (long)r * M;
+          zd acc = {0.0, 0.0};
+#pragma unroll 4
+          for (int i = part; i < M; i += tpr) acc = acc + to_d(hr[i]) * qv[i];
+          for (int o = 1; o < tpr; o <<= 1) {
+            acc.x += __shfl_xor(acc.x, o, 64);
+            acc.y += __shfl_xor(acc.y, o, 64);
+          }
+          if (part == 0) Ly1[r] = scal(sm.invsig[r / N], acc);
+        }
       }
       __syncthreads();
-      // y2 = S D y1
-      for (int r = tid; r < un; r += AMMSE_BLOCK) {
-        const int u = r / N, n = r % N;
+      for (int r = tid; r < un; r += AMMSE_BLOCK) {   // y2 = S D y1
+        const int u = r / N, n = r - u * N;
         zd acc = {0.0, 0.0};
         for (int k = 0; k < N; ++k) acc = acc + Dm[u * 16 + n * 4 + k] * Ly1[u * N + k];
         Ly2[r] = scal(sm.invsig[u], acc);
       }
       __syncthreads();
-      // w = H^H y2 ; alpha_j = Re q^H w
-      double al = 0.0;
-      for (int i = tid; i < M; i += AMMSE_BLOCK) {
-        zd acc = {0.0, 0.0};
-#pragma unroll 8
-        for (int r = 0; r < un; ++r) acc = acc + cj(to_d(Hc[(long)r * M + i])) * Ly2[r];
-        qc[i] = acc;
-        al += qb[i].x * acc.x + qb[i].y * acc.y;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+      {  // w = H^H y2 and the inner products
+        const int part = tid & (tpc - 1);
+        for (int i = tid / tpc; i < M; i += AMMSE_BLOCK / tpc) {
+          zd acc = {0.0, 0.0};
+#pragma unroll 4
+          for (int r = part; r < un; r += tpc) acc = acc + cj(to_d(Hc[(long)r * M + i])) * Ly2[r];
+          for (int o = 1; o < tpc; o <<= 1) {
+            acc.x += __shfl_xor(acc.x, o, 64);
+            acc.y += __shfl_xor(acc.y, o, 64);
+          }
+          if (part == 0) {
+            wv[i] = acc;
+            const zd q = qv[i], pp = pv[i];
+            s0 += nrm2(acc);
+            s1 += q.x * acc.x + q.y * acc.y;
+            s2 += pp.x * acc.x + pp.y * acc.y;
+          }
+        }
       }
-      al = block_sum(al, sm.red);
-      double bb = 0.0;
-      for (int i = tid; i < M; i += AMMSE_BLOCK) {
-        const zd w = qc[i] - scal(al, qb[i]) - scal(beta_prev, qa[i]);
-        qc[i] = w;
-        bb += nrm2(w);
+      s0 = wave_sum(s0);
+      s1 = wave_sum(s1);
+      s2 = wave_sum(s2);
+      __syncthreads();
+      if ((tid & 63) == 0) {
+        sm.red[(tid >> 6)] = s0;
+        sm.red[4 + (tid >> 6)] = s1;
+        sm.red[8 + (tid >> 6)] = s2;
       }
-      bb = sqrt(block_sum(bb, sm.red));
+      __syncthreads();
+      const double ww = (sm.red[0] + sm.red[1]) + (sm.red[2] + sm.red[3]);
+      const double al = (sm.red[4] + sm.red[5]) + (sm.red[6] + sm.red[7]);
+      const double pw = (sm.red[8] + sm.red[9]) + (sm.red[10] + sm.red[11]);
+      double bb;
+      if (exact_beta) {
+        double nr = 0.0;
+        for (int i = tid; i < M; i += AMMSE_BLOCK) {
+          const zd w = wv[i] - scal(al, qv[i]) - scal(beta_prev, pv[i]);
+          wv[i] = w;
+          nr += nrm2(w);
+        }
+        bb = sqrt(block_sum(nr, sm.red));
+      } else {
+        bb = sqrt(fmax(ww - al * al - 2.0 * beta_prev * pw + beta_prev * beta_prev, 0.0));
+      }
       if (tid == 0) {
         sm.la[j] = al;
         sm.lb[j] = bb;
       }
-      msz = j + 1;
+      const int msz = j + 1;
       tmax = fmax(tmax, fabs(al) + bb);
       const bool breakdown = !(bb > 1e-13 * tmax);
-      if (breakdown || (msz % 8) == 0 || msz == m) {
+      bool stop = breakdown;
+      if (breakdown || (msz >= first && (msz % every) == 0) || msz == m) {
         __syncthreads();
-        const double th = (tmax > 0.0) ? tridiag_lmax(sm.la, sm.lb, msz, &sm.imin) : 0.0;
-        const bool conv = fabs(th - theta) <= ltol * fabs(th);
+        const double th = (tmax > 0.0) ? tridiag_lmax(sm.la, sm.lb, msz, &sm.imin, rtol) : 0.0;
+        stop = stop || fabs(th - theta) <= ltol * fabs(th);
         theta = th;
-        if (breakdown || conv) break;
       }
+      if (stop) break;
+      __syncthreads();
       const double ib = 1.0 / bb;
       for (int i = tid; i < M; i += AMMSE_BLOCK) {
-        qa[i] = qb[i];
-        qb[i] = scal(ib, qc[i]);
+        const zd w = exact_beta ? wv[i] : wv[i] - scal(al, qv[i]) - scal(beta_prev, pv[i]);
+        pv[i] = qv[i];
+        qv[i] = scal(ib, w);
       }
       beta_prev = bb;
       __syncthreads();
@@ -459,8 +494,11 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
   __syncthreads();
   const int T = p.wsr_only ? 0 : p.max_iters;
   if (!p.wsr_only) {
-    for (long e = tid; e < Vtot; e += AMMSE_BLOCK) Vq[e] = V[e];
-    for (long e = tid; e < (long)un * D.ud; e += AMMSE_BLOCK) Gq[e] = Gp[e];
+    const int nv = (int)Vtot, ng = un * D.ud;
+#pragma unroll 4
+    for (int e = tid; e < nv; e += AMMSE_BLOCK) Vq[e] = V[e];
+#pragma unroll 4
+    for (int e = tid; e < ng; e += AMMSE_BLOCK) Gq[e] = Gp[e];
   }
   __syncthreads();
 
@@ -523,17 +561,24 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
     for (int c = 0; c < C; ++c) {
       const int nc = sm.cu[c] * d;
       const long base = (long)un * sm.colOff[c];
-      for (long e = tid; e < (long)un * nc; e += AMMSE_BLOCK) {
-        const int r = (int)(e / nc), j = (int)(e % nc);
-        const int u = r / N, n = r % N;
+      // flat element loop (consecutive threads along a row, rows wrap)
+      const int ne = un * nc;
+      for (int e = tid; e < ne; e += AMMSE_BLOCK) {
+        const int r = e / nc, j = e - r * nc;
+        const int u = r / N, n = r - u * N;
         zd acc = {0.0, 0.0};
-        for (int k = 0; k < N; ++k) {
-          const long idx = base + (long)(u * N + k) * nc + j;
-          const zd gh = {(1.0 + om) * (double)Gp[idx].x - om * (double)Gq[idx].x,
-                         (1.0 + om) * (double)Gp[idx].y - om * (double)Gq[idx].y};
-          acc = acc + Dm[u * 16 + n * 4 + k] * gh;
+        const long g0 = base + (long)(u * N) * nc + j;
+#pragma unroll
+        for (int k = 0; k < AMMSE_MAX_RX; ++k) {
+          if (k < N) {
+            const cx<R> a = Gp[g0 + (long)k * nc], q = Gq[g0 + (long)k * nc];
+            const zd gh = {(1.0 + om) * (double)a.x - om * (double)q.x,
+                           (1.0 + om) * (double)a.y - om * (double)q.y};
+            acc = acc + Dm[u * 16 + n * 4 + k] * gh;
+          }
         }
-        if (sm.cellOf[u] == c && j / d == sm.local[u]) acc = acc - Ym[u * 16 + n * 4 + (j % d)];
+        const int j0 = sm.local[u] * d;
+        if (sm.cellOf[u] == c && j >= j0 && j < j0 + d) acc = acc - Ym[u * 16 + n * 4 + (j - j0)];
         Z[base + e] = from_d<R>(scal(sm.invsig[u], acc));
       }
     }
@@ -555,18 +600,24 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
       const long n = (long)M * nc;
       const double g = sm.gamma[c];
       double pw = 0.0;
-      for (long e = tid; e < n; e += AMMSE_BLOCK) {
-        const zd v = to_d(V[base + e]), vq = to_d(Vq[base + e]), gr = to_d(Gr[base + e]);
+      const int ni = (int)n;
+      cx<R>* __restrict__ Vb = V + base;
+      cx<R>* __restrict__ Vqb = Vq + base;
+      cx<R>* __restrict__ Grb = Gr + base;
+#pragma unroll 4
+      for (int e = tid; e < ni; e += AMMSE_BLOCK) {
+        const zd v = to_d(Vb[e]), vq = to_d(Vqb[e]), gr = to_d(Grb[e]);
         const zd x = {(1.0 + om) * v.x - om * vq.x - g * gr.x, (1.0 + om) * v.y - om * vq.y - g * gr.y};
         const cx<R> xs = from_d<R>(x);
-        Gr[base + e] = xs;
+        Grb[e] = xs;
         pw += nrm2(to_d(xs));
       }
       pw = block_sum(pw, sm.red);
       const double s = (pw > sm.Pc[c]) ? sqrt(sm.Pc[c] / pw) : 1.0;
-      for (long e = tid; e < n; e += AMMSE_BLOCK) {
-        Vq[base + e] = V[base + e];
-        V[base + e] = from_d<R>(scal(s, to_d(Gr[base + e])));
+#pragma unroll 4
+      for (int e = tid; e < ni; e += AMMSE_BLOCK) {
+        Vqb[e] = Vb[e];
+        Vb[e] = from_d<R>(scal(s, to_d(Grb[e])));
       }
     }
     __syncthreads();
@@ -601,7 +652,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
     const long base = (long)M * sm.colOff[c];
     const long n = (long)M * sm.cu[c] * d;
     double pw = 0.0;
-    for (long e = tid; e < n; e += AMMSE_BLOCK) pw += nrm2(to_d(V[base + e]));
+    for (int e = tid; e < (int)n; e += AMMSE_BLOCK) pw += nrm2(to_d(V[base + e]));
     pw = block_sum(pw, sm.red);
     if (n > 0 && pw == 0.0) status |= AMMSE_INST_ZERO_POWER;
   }
