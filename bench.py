@@ -34,6 +34,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 REF_FILE = os.path.join(ROOT, "tests", "golden", "wmmse_ref_rayleigh_sweep4x256.json")
+LARGE_REF_FILE = os.path.join(ROOT, "tests", "golden", "oracle_ref_rayleigh_m256u64n2d2_b512.json")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ammse_solve_fp32_rayleigh_sweep1024_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2510_20507_amd", "csrc", f)
                   for f in ("ammse_fast.hip", "ammse_kernels.hip", "ammse_device.h",
@@ -118,6 +119,95 @@ def plain_per_instance(batch, ref, opts, per_p: int = 8, reps: int = 2):
             "ms_per_instance": dt / len(idx) * 1e3, "reached_99": ok}
 
 
+def mixed_precision(reps: int = 2):
+    """The M=256 workload (512 instances, 64 users, N=d=2, P=20 dB) solved in
+    float, in bfloat16 with the float refinement pass (last 10 of 100
+    iterations) and in bfloat16 throughout: kernel time (HIP events on the
+    launch stream), instances/s reaching 99 % of the stored FP64 WMMSE WSR,
+    and the reported WSR's relative error against the stored FP64 oracle
+    A-MMMSE WSR (first 16 instances)."""
+    import torch
+    from paper_2510_20507_amd import ammse, synth
+    if not os.path.exists(LARGE_REF_FILE):
+        return None
+    with open(LARGE_REF_FILE) as f:
+        refj = json.load(f)
+    batch = synth.rayleigh_large(512)
+    assert refj["workload"] == batch.name
+    wm = np.asarray(refj["wmmse"]["wsr"])
+    am_idx = np.asarray(refj["ammmse"]["index"])
+    am = np.asarray(refj["ammmse"]["wsr"])
+    flops = float(batch.total_flops_per_iter().sum()) * ITERS
+    out = {"workload": batch.name, "instances": batch.batch, "M": 256, "users": 64, "N": 2,
+           "d": 2, "snr_db": 20, "iters": ITERS}
+    modes = [("fp32", ammse.Options(precision=ammse.PREC_FP32, max_iters=ITERS)),
+             ("bf16_refined", ammse.Options(precision=ammse.PREC_BF16, max_iters=ITERS,
+                                            refine_iters=10)),
+             ("bf16", ammse.Options(precision=ammse.PREC_BF16, max_iters=ITERS, refine_iters=0))]
+    db = ammse.to_device(batch, ammse.PREC_FP32)
+    for name, opts in modes:
+        plan = ammse.Plan(db.table, db.cell_users, opts)
+        ws = plan.workspace()
+        V = torch.empty_like(db.V0)
+        wsr = torch.empty(batch.batch, dtype=torch.float64, device="cuda")
+        st = torch.empty(batch.batch, dtype=torch.int32, device="cuda")
+        V.copy_(db.V0)
+        plan.solve(db.H, db.sigma2, db.alpha, db.P, V, wsr, None, None, st, workspace=ws)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            V.copy_(db.V0)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.solve(db.H, db.sigma2, db.alpha, db.P, V, wsr, None, None, st, workspace=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        w = wsr.cpu().numpy()
+        ok = int(((w >= 0.99 * wm) & (st.cpu().numpy() == 0)).sum())
+        t = float(np.mean(ms))
+        err = np.abs(w[am_idx] - am) / am
+        out[name] = {"kernel_ms": t, "instances_per_s_reached_99": ok / (t / 1e3),
+                     "reached_99": ok, "achieved_tflops": flops / (t / 1e3) / 1e12,
+                     "wsr_rel_err_vs_fp64_oracle_max": float(err.max()),
+                     "wsr_rel_err_vs_fp64_oracle_mean": float(err.mean())}
+        plan.close()
+    out["speedup_bf16_refined_vs_fp32"] = out["fp32"]["kernel_ms"] / out["bf16_refined"]["kernel_ms"]
+    return out
+
+
+def gpu_wmmse(batch, ref, max_iters: int = 500, eps: float = 1e-6):
+    """The comparator on the same GPU: WMMSE (Algorithm 2, FP32 channel
+    products, double M x M solves) on the whole benchmark batch with the
+    reference stop rule (relative WSR change <= 1e-6 or 500 iterations), one
+    launch; instances/s reaching 99 % of the FP64 WMMSE reference."""
+    import torch
+    from paper_2510_20507_amd import ammse
+    opts = ammse.Options(precision=ammse.PREC_FP32, algorithm=ammse.ALGO_WMMSE,
+                         max_iters=max_iters, eps2=eps)
+    db = ammse.to_device(batch, opts.precision)
+    plan = ammse.Plan(db.table, db.cell_users, opts)
+    ws = plan.workspace()
+    V = db.V0.clone()
+    wsr = torch.empty(batch.batch, dtype=torch.float64, device="cuda")
+    it = torch.empty(batch.batch, dtype=torch.int32, device="cuda")
+    st = torch.empty(batch.batch, dtype=torch.int32, device="cuda")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    plan.solve(db.H, db.sigma2, db.alpha, db.P, V, wsr, it, None, st, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1)
+    w = wsr.cpu().numpy()
+    ok = int(((w >= 0.99 * ref) & (st.cpu().numpy() == 0)).sum())
+    plan.close()
+    return {"kernel_ms": t, "instances_per_s_reached_99": ok / (t / 1e3), "reached_99": ok,
+            "mean_iters": float(it.cpu().numpy().mean()), "max_iters": max_iters, "eps": eps,
+            "precision": "fp32 products, fp64 M x M solves"}
+
+
 def parse_pmc(dirs):
     """Sum FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the solve kernel and of
     the calibration copy from rocprofv3 --pmc CSV output directories."""
@@ -165,6 +255,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-wmmse", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help=f"also run a {CALIB_COPY_MIB} MiB device copy (counter calibration)")
     ap.add_argument("--parse-pmc", nargs="+", metavar="DIR")
@@ -263,6 +355,10 @@ def main():
     }
     if not a.no_plain:
         line["plain_per_instance"] = plain_per_instance(batch, ref, opts)
+    if not a.no_mixed:
+        line["mixed_precision"] = mixed_precision()
+    if not a.no_wmmse:
+        line["gpu_wmmse"] = gpu_wmmse(batch, ref)
     if a.calib_copy:
         n = CALIB_COPY_MIB * (1 << 20) // 4
         x = torch.ones(n, dtype=torch.float32, device="cuda")

@@ -63,6 +63,13 @@ typedef int32_t ammse_status_t;
 #define AMMSE_PREC_FP64 0       /* everything in double */
 #define AMMSE_PREC_FP32 1       /* channel products in float; N x N, d x d work,
                                    step size and projection in double */
+#define AMMSE_PREC_BF16 2       /* mixed: H and V stored as float; the two channel
+                                   products of an iteration run in bfloat16 with float
+                                   accumulation, except in the last refine_iters
+                                   iterations (the refinement pass), which start by
+                                   recomputing G^{t-1} and G^{t-2} in float and then
+                                   run as AMMSE_PREC_FP32; the step size, the N x N /
+                                   d x d algebra and the projection are as in FP32 */
 
 /* Kernel selection (ammse_options_t.path). */
 #define AMMSE_PATH_AUTO 0
@@ -98,6 +105,20 @@ typedef struct ammse_instance_t {
   int64_t bs_off;   /* entries of P[] */
 } ammse_instance_t;
 
+/* Algorithms (ammse_options_t.algorithm). */
+#define AMMSE_ALGO_AMMMSE 0  /* Algorithm 3 (A-MMMSE; A-WMMSE with warm_start = 0) */
+#define AMMSE_ALGO_WMMSE 1   /* Algorithm 2 (WMMSE, Section IV): U and W as in
+                                Algorithm 3's second stage, V per BS by the exact
+                                minimiser (A_c + mu_c I)^{-1} B_c with the dual
+                                mu_c >= 0 of the power budget (mu_c = 0 when the
+                                unconstrained minimiser meets it).  The comparator
+                                of Section VII.  max_iters caps the iterations,
+                                eps2 > 0 stops once the relative WSR change of an
+                                iteration is <= eps2; T_c, eps1, warm_start,
+                                extrapolate, gamma_c are ignored.  FP64 and FP32
+                                storage (the M x M solve runs in double); the
+                                general kernel only. */
+
 /* Solver options (Algorithm 3 inputs). */
 typedef struct ammse_options_t {
   int32_t precision;         /* AMMSE_PREC_* */
@@ -113,6 +134,9 @@ typedef struct ammse_options_t {
   int32_t path;              /* AMMSE_PATH_AUTO: LDS-resident MFMA kernel when every
                                 instance fits it, else the general kernel;
                                 AMMSE_PATH_GENERAL: always the general kernel */
+  int32_t refine_iters;      /* AMMSE_PREC_BF16: final iterations with float products
+                                (the refinement pass); ignored otherwise */
+  int32_t algorithm;         /* AMMSE_ALGO_AMMMSE (Algorithm 3) or AMMSE_ALGO_WMMSE */
   int32_t reserved;          /* must be 0 */
   double eps1;               /* stage-switch tolerance (paper: 0.1) */
   double eps2;               /* stop tolerance (0: run exactly max_iters) */
@@ -134,7 +158,8 @@ int32_t ammse_version(void);
 const char* ammse_status_string(ammse_status_t s);
 
 /* Fill *opt with the paper's defaults: FP32, T = 100, T_c = 3, warm start,
- * extrapolation, re-armed step, eps1 = 0.1, eps2 = 0, gamma_c = 0 (keep). */
+ * extrapolation, re-armed step, eps1 = 0.1, eps2 = 0, gamma_c = 0 (keep),
+ * refine_iters = 10, algorithm = AMMSE_ALGO_AMMMSE. */
 void ammse_default_options(ammse_options_t* opt);
 
 /*

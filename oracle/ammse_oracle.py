@@ -410,9 +410,11 @@ def wmmse_precoder(prob: Problem, Uu: np.ndarray, Wu: np.ndarray, mode: str = "r
 
 
 def wmmse(prob: Problem, V0u: np.ndarray, max_iters: int = 500, eps: float = 1e-6,
-          mode: str = "reference") -> dict:
+          mode: str = "reference", perturb=None) -> dict:
     """WMMSE (Algorithm 2): U by the receiver equation, W = E^{-1}, V by the
-    dual-bisection solve, until the relative WSR change is <= eps."""
+    dual-bisection solve, until the relative WSR change is <= eps.
+    ``perturb(t, V)``, if given, replaces every new iterate (a test hook that
+    measures how strongly a trajectory amplifies rounding-sized changes)."""
     V = V0u.copy()
     trace = [wsr_bits(prob, V)]
     it = 0
@@ -420,6 +422,8 @@ def wmmse(prob: Problem, V0u: np.ndarray, max_iters: int = 500, eps: float = 1e-
         Uu = mmse_receivers(prob, V)
         Wu = _inv_hermitian(mse_at_mmse(prob, Uu, V))
         V, _ = wmmse_precoder(prob, Uu, Wu, mode)
+        if perturb is not None:
+            V = perturb(t, V)
         trace.append(wsr_bits(prob, V))
         it = t
         if rel_change(trace[-1], trace[-2]) <= eps:

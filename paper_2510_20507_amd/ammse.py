@@ -22,8 +22,11 @@ STATUS_NAMES = {0: "OK", 1: "ERR_NULL", 2: "ERR_SHAPE", 3: "ERR_OPTION", 4: "ERR
                 5: "ERR_HIP", 6: "ERR_UNSUPPORTED", 7: "ERR_ALLOC"}
 PREC_FP64 = 0
 PREC_FP32 = 1
+PREC_BF16 = 2
 PATH_AUTO = 0
 PATH_GENERAL = 1
+ALGO_AMMMSE = 0
+ALGO_WMMSE = 1
 INST_NONFINITE = 1
 INST_CHOLESKY = 2
 INST_ZERO_POWER = 4
@@ -47,8 +50,9 @@ class AmmseOptions(ctypes.Structure):
                 ("T_c", ctypes.c_int32), ("warm_start", ctypes.c_int32),
                 ("extrapolate", ctypes.c_int32), ("rearm_at_switch", ctypes.c_int32),
                 ("force_switch_iter", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32),
-                ("path", ctypes.c_int32), ("reserved", ctypes.c_int32), ("eps1", ctypes.c_double), ("eps2", ctypes.c_double),
-                ("gamma_c", ctypes.c_double)]
+                ("path", ctypes.c_int32), ("refine_iters", ctypes.c_int32),
+                ("algorithm", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("eps1", ctypes.c_double), ("eps2", ctypes.c_double), ("gamma_c", ctypes.c_double)]
 
 
 class AmmseError(RuntimeError):
@@ -119,6 +123,8 @@ class Options:
     force_switch_iter: int = -1
     lanczos_steps: int = 0
     path: int = 0
+    refine_iters: int = 10
+    algorithm: int = ALGO_AMMMSE
     reserved: int = 0
     eps1: float = 0.1
     eps2: float = 0.0
@@ -248,7 +254,7 @@ class DeviceBatch:
 
 def to_device(batch, precision: int = PREC_FP32, device: int = 0) -> DeviceBatch:
     import torch
-    cdt = torch.complex128 if precision == PREC_FP64 else torch.complex64
+    cdt = torch.complex128 if precision == PREC_FP64 else torch.complex64   # BF16 mode: float I/O
     dev = f"cuda:{device}"
     table, cu = make_table(batch)
     return DeviceBatch(
@@ -305,7 +311,7 @@ def wsr(batch, V: Optional[np.ndarray] = None, precision: int = PREC_FP32,
     opt = Options(precision=precision, max_iters=0)
     plan = Plan(db.table, db.cell_users, opt, device)
     dev = f"cuda:{device}"
-    cdt = torch.complex128 if precision == PREC_FP64 else torch.complex64
+    cdt = torch.complex128 if precision == PREC_FP64 else torch.complex64   # BF16 mode: float I/O
     Vt = db.V0 if V is None else torch.from_numpy(np.asarray(V)).to(dev, cdt).contiguous()
     out = torch.empty(batch.batch, dtype=torch.float64, device=dev)
     plan.wsr(db.H, db.sigma2, db.alpha, Vt, out)

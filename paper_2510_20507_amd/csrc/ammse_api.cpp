@@ -26,7 +26,9 @@ int resolved_lanczos(const ammse_options_t& o) {
 }
 
 ammse_status_t check_options(const ammse_options_t& o) {
-  if (o.precision != AMMSE_PREC_FP64 && o.precision != AMMSE_PREC_FP32) return AMMSE_ERR_OPTION;
+  if (o.precision != AMMSE_PREC_FP64 && o.precision != AMMSE_PREC_FP32 &&
+      o.precision != AMMSE_PREC_BF16)
+    return AMMSE_ERR_OPTION;
   if (o.max_iters < 0 || o.max_iters > 1000000) return AMMSE_ERR_OPTION;
   if (o.T_c < 0) return AMMSE_ERR_OPTION;
   if (o.warm_start != 0 && o.warm_start != 1) return AMMSE_ERR_OPTION;
@@ -35,7 +37,11 @@ ammse_status_t check_options(const ammse_options_t& o) {
   if (o.force_switch_iter != -1 && o.force_switch_iter < 1) return AMMSE_ERR_OPTION;
   if (o.lanczos_steps < 0 || o.lanczos_steps > AMMSE_MAX_LANCZOS) return AMMSE_ERR_OPTION;
   if (o.path != AMMSE_PATH_AUTO && o.path != AMMSE_PATH_GENERAL) return AMMSE_ERR_OPTION;
+  if (o.refine_iters < 0) return AMMSE_ERR_OPTION;
+  if (o.algorithm != AMMSE_ALGO_AMMMSE && o.algorithm != AMMSE_ALGO_WMMSE) return AMMSE_ERR_OPTION;
   if (o.reserved != 0) return AMMSE_ERR_OPTION;
+  if (o.algorithm == AMMSE_ALGO_WMMSE && o.precision == AMMSE_PREC_BF16)
+    return AMMSE_ERR_UNSUPPORTED;
   if (!(o.eps1 >= 0.0) || !(o.eps2 >= 0.0)) return AMMSE_ERR_OPTION;
   if (o.T_c == 0 && !(o.gamma_c > 0.0)) return AMMSE_ERR_OPTION;
   if (o.gamma_c != o.gamma_c) return AMMSE_ERR_OPTION;
@@ -74,6 +80,8 @@ void ammse_default_options(ammse_options_t* opt) {
   opt->force_switch_iter = -1;
   opt->lanczos_steps = 0;
   opt->path = AMMSE_PATH_AUTO;
+  opt->refine_iters = 10;
+  opt->algorithm = AMMSE_ALGO_AMMMSE;
   opt->reserved = 0;
   opt->eps1 = 0.1;
   opt->eps2 = 0.0;
@@ -146,7 +154,7 @@ ammse_status_t ammse_plan_create(ammse_plan_t* plan, int32_t device,
   if (batch < 1) return AMMSE_ERR_SHAPE;
   if (hipSetDevice(device) != hipSuccess) return AMMSE_ERR_HIP;
 
-  const int rb = (o.precision == AMMSE_PREC_FP64) ? 8 : 4;
+  const int rb = (o.precision == AMMSE_PREC_FP64) ? 8 : 4;   // BF16 mode stores float
   const int ls = resolved_lanczos(o);
   // launch order: decreasing work, so the dispatcher balances uneven batches
   std::vector<int32_t> order(batch);
@@ -159,7 +167,8 @@ ammse_status_t ammse_plan_create(ammse_plan_t* plan, int32_t device,
   std::stable_sort(order.begin(), order.end(),
                    [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
 
-  bool fast = (o.precision == AMMSE_PREC_FP32) && (o.path == AMMSE_PATH_AUTO);
+  bool fast = (o.precision == AMMSE_PREC_FP32) && (o.path == AMMSE_PATH_AUTO) &&
+              (o.algorithm == AMMSE_ALGO_AMMMSE);
   for (int32_t i = 0; fast && i < batch; ++i) {
     const ammse_instance_t& t = table[i];
     fast = ammse_fast_eligible(t.C, t.U, t.M, t.N, t.d);
@@ -187,7 +196,8 @@ ammse_status_t ammse_plan_create(ammse_plan_t* plan, int32_t device,
     d.user_off = t.user_off;
     d.bs_off = t.bs_off;
     d.ws_off = (int64_t)off;
-    if (!fast) off += ammse_ws_layout(rb, t.U, t.M, t.N, t.d, ls).total;
+    if (!fast)
+      off += ammse_ws_layout(rb, t.U, t.M, t.N, t.d, ls, o.algorithm == AMMSE_ALGO_WMMSE).total;
   }
 
   ammse_plan_s* P = new (std::nothrow) ammse_plan_s();
@@ -264,6 +274,8 @@ static void fill_common(ammse_plan_t plan, ammse_kparams_t& k) {
   k.eps1 = o.eps1;
   k.eps2 = o.eps2;
   k.gamma_c = o.gamma_c;
+  k.lowp_iters = (o.precision == AMMSE_PREC_BF16) ? std::max(0, o.max_iters - o.refine_iters) : -1;
+  k.algorithm = o.algorithm;
 }
 
 ammse_status_t ammse_solve(ammse_plan_t plan, const void* H, const double* sigma2,
@@ -310,6 +322,7 @@ ammse_status_t ammse_wsr(ammse_plan_t plan, const void* H, const double* sigma2,
   k.wsr_only = 1;
   k.max_iters = 0;
   k.trace_len = 1;
+  k.lowp_iters = -1;   // the WSR of V is evaluated with float products
   return launch(plan, k, (hipStream_t)stream);
 }
 

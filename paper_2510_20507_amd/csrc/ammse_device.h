@@ -247,6 +247,80 @@ __device__ __forceinline__ void user_weights(const zd* UW, const zd* E, bool sta
   }
 }
 
+// complex double from lane `src` (every lane of the wave must execute it)
+__device__ __forceinline__ zd shz(zd v, int src) {
+  return {__shfl(v.x, src, 64), __shfl(v.y, src, 64)};
+}
+
+// ---------------------------------------------------------------------------
+// 4 x 4 complex double matrices spread over a 16-lane group: lane base + 4a + b
+// holds entry (a, b).  All functions must be executed by the whole wave.
+// ---------------------------------------------------------------------------
+struct Lane4 {
+  int base, a, b;
+  __device__ __forceinline__ zd at(zd v, int r, int c) const { return shz(v, base + 4 * r + c); }
+};
+
+// In place Cholesky (lower); ok is cleared when a pivot is not positive/finite.
+__device__ __forceinline__ zd chol16(const Lane4& L, zd A, bool& ok) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double dkk = L.at(A, k, k).x;
+    ok = ok && (dkk > 0.0) && isfinite(dkk);
+    const double l = sqrt(fmax(dkk, 1e-300));
+    if (L.b == k && L.a > k) A = scal(1.0 / l, A);
+    if (L.a == k && L.b == k) A = {l, 0.0};
+    const zd lak = L.at(A, L.a, k), lbk = L.at(A, L.b, k);
+    if (L.a > k && L.b > k) A = A - mulc(lak, lbk);
+  }
+  if (L.b > L.a) A = {0.0, 0.0};
+  return A;
+}
+
+// X <- Lo^{-1} X (forward substitution, Lo lower with real diagonal)
+__device__ __forceinline__ zd trsm16(const Lane4& L, zd Lo, zd X) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double lkk = L.at(Lo, k, k).x;
+    if (L.a == k) X = scal(1.0 / lkk, X);
+    const zd xkb = L.at(X, k, L.b), lak = L.at(Lo, L.a, k);
+    if (L.a > k) X = X - lak * xkb;
+  }
+  return X;
+}
+
+// X <- Lo^{-H} X (back substitution with the conjugate transpose)
+__device__ __forceinline__ zd trsm16h(const Lane4& L, zd Lo, zd X) {
+#pragma unroll
+  for (int k = 3; k >= 0; --k) {
+    const double lkk = L.at(Lo, k, k).x;
+    if (L.a == k) X = scal(1.0 / lkk, X);
+    const zd xkb = L.at(X, k, L.b), lka = L.at(Lo, k, L.a);
+    if (L.a < k) X = X - cj(lka) * xkb;
+  }
+  return X;
+}
+
+// A^H B, A B, A B^H
+__device__ __forceinline__ zd mm_hn(const Lane4& L, zd A, zd B) {
+  zd c = {0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) c = c + cj(L.at(A, k, L.a)) * L.at(B, k, L.b);
+  return c;
+}
+__device__ __forceinline__ zd mm_nn(const Lane4& L, zd A, zd B) {
+  zd c = {0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) c = c + L.at(A, L.a, k) * L.at(B, k, L.b);
+  return c;
+}
+__device__ __forceinline__ zd mm_nh(const Lane4& L, zd A, zd B) {
+  zd c = {0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) c = c + mulc(L.at(A, L.a, k), L.at(B, L.b, k));
+  return c;
+}
+
 __device__ __forceinline__ double rel_change(double a, double b) {
   if (b > 0) return fabs(a - b) / b;
   return (a == b) ? 0.0 : INFINITY;

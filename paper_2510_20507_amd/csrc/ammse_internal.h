@@ -20,9 +20,15 @@ struct ammse_desc_t {
 
 // Byte offsets of the sub-buffers inside one instance workspace.
 struct ammse_ws_layout_t {
-  size_t Gp, Gq, Z, Vq, Gr;   // storage-precision complex matrices
-  size_t Jm, Dm, Ym;          // double complex per-user blocks
+  size_t Gp, Gq, Z, Vq;       // storage-precision complex matrices
+  size_t UWm, Em, Dm, Ym;     // double complex per-user 4 x 4 blocks
   size_t Lq, Lw, Ly1, Ly2;    // Lanczos basis and work vectors (double complex)
+  size_t Am, Lm, Bm, Xm;      // WMMSE: matrix and its Cholesky factor (M x M at most),
+                              // right-hand sides and solution (M x (U d) at most),
+                              // double complex; empty for Algorithm 3
+  size_t Tm;                  // WMMSE: S D S H_{:,c} or R = C^H S H_{:,c} ((U N) x M,
+                              // double complex)
+  size_t Lwm, Lim, Cm;        // WMMSE: per-user Lw, Lw^{-1}, C (double complex 4 x 4)
   size_t total;
 };
 
@@ -52,6 +58,9 @@ struct ammse_kparams_t {
   int32_t lanczos_steps;
   int32_t wsr_only;      // 1: evaluate WSR(V) and return (no iteration, V not written)
   int32_t trace_len;     // max_iters + 1
+  int32_t algorithm;     // AMMSE_ALGO_*
+  int32_t lowp_iters;    // BF16 mode: iterations 1..lowp_iters use bfloat16 products
+                         // (and G^0 when lowp_iters >= 1); -1: float products only
   double eps1, eps2, gamma_c;
 };
 
@@ -64,7 +73,8 @@ struct ammse_kparams_t {
 __host__ __device__ inline size_t ammse_align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int U, int M, int N,
-                                                             int d, int lanczos_steps) {
+                                                             int d, int lanczos_steps,
+                                                             bool wmmse) {
   const size_t cs = 2 * (size_t)real_bytes;      // storage complex
   const size_t zs = 16;                          // double complex
   const size_t un = (size_t)U * N, ud = (size_t)U * d;
@@ -74,14 +84,23 @@ __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int
   L.Gq = o;  o += ammse_align256(un * ud * cs);
   L.Z = o;   o += ammse_align256(un * ud * cs);
   L.Vq = o;  o += ammse_align256((size_t)M * ud * cs);
-  L.Gr = o;  o += ammse_align256((size_t)M * ud * cs);
-  L.Jm = o;  o += ammse_align256((size_t)U * 16 * zs);
+  L.UWm = o; o += ammse_align256((size_t)U * 16 * zs);
+  L.Em = o;  o += ammse_align256((size_t)U * 16 * zs);
   L.Dm = o;  o += ammse_align256((size_t)U * 16 * zs);
   L.Ym = o;  o += ammse_align256((size_t)U * 16 * zs);
   L.Lq = o;  o += ammse_align256((size_t)3 * M * zs);   // three Lanczos vectors
   L.Lw = o;  o += ammse_align256((size_t)M * zs);
   L.Ly1 = o; o += ammse_align256(un * zs);
   L.Ly2 = o; o += ammse_align256(un * zs);
+  const size_t w = wmmse ? 1 : 0;
+  L.Am = o;  o += ammse_align256(w * (size_t)M * M * zs);
+  L.Lm = o;  o += ammse_align256(w * (size_t)M * M * zs);
+  L.Bm = o;  o += ammse_align256(w * (size_t)M * ud * zs);
+  L.Xm = o;  o += ammse_align256(w * (size_t)M * ud * zs);
+  L.Tm = o;  o += ammse_align256(w * un * (size_t)M * zs);
+  L.Lwm = o; o += ammse_align256(w * (size_t)U * 16 * zs);
+  L.Lim = o; o += ammse_align256(w * (size_t)U * 16 * zs);
+  L.Cm = o;  o += ammse_align256(w * (size_t)U * 16 * zs);
   L.total = o;
   return L;
 }

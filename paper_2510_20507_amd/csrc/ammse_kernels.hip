@@ -30,23 +30,58 @@
 namespace {
 using namespace ammse_dev;
 
+// Thread index hidden from loop-invariant code motion: each phase of the
+// fused kernel re-derives its lane indices instead of the compiler keeping
+// every phase's index arithmetic live across the whole iteration loop, which
+// would cost occupancy.
+__device__ __forceinline__ int phase_tid() {
+  int x = threadIdx.x;
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 constexpr int KC = 16;   // k-chunk of the channel products
 constexpr int TM = 64;   // output tile rows
 constexpr int TN = 64;   // output tile columns
 
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+template <class T>
+struct MfmaTile {
+  static constexpr bool LOW = sizeof(T) == 2;
+  static constexpr int KC = LOW ? 32 : 16;          // k-chunk
+  static constexpr int LD = LOW ? KC + 8 : KC + 1;  // padded k stride (elements)
+  static constexpr int NA = TM * KC / AMMSE_BLOCK;  // staged A elements per thread
+  static constexpr int NB = KC * TN / AMMSE_BLOCK;
+  static constexpr size_t bytes = sizeof(T) * 2 * (TM + TN) * LD;
+};
+
+
+template <class R>
+constexpr size_t tile_bytes() {
+  if constexpr (sizeof(R) == 8) {
+    return sizeof(cx<R>) * KC * (TM + 1 + TN + 1);
+  } else {
+    return MfmaTile<float>::bytes > MfmaTile<__bf16>::bytes ? MfmaTile<float>::bytes
+                                                             : MfmaTile<__bf16>::bytes;
+  }
+}
+
 template <class R>
 struct Smem {
-  cx<R> As[KC * (TM + 1)];
-  cx<R> Bs[KC * (TN + 1)];
+  alignas(16) char tiles[tile_bytes<R>()];
   double invsig[AMMSE_MAX_USERS];
   double alpha[AMMSE_MAX_USERS];
-  double rate[AMMSE_MAX_USERS];
   int cellOf[AMMSE_MAX_USERS];
   int local[AMMSE_MAX_USERS];
   int cu[AMMSE_MAX_CELLS];
   int colOff[AMMSE_MAX_CELLS + 1];
   double Pc[AMMSE_MAX_CELLS];
   double gamma[AMMSE_MAX_CELLS];
+  double scur[AMMSE_MAX_CELLS];    // projection factor of the current iterate per BS
+  double sprev[AMMSE_MAX_CELLS];   // and of the previous one
+  double mu[AMMSE_MAX_CELLS];      // WMMSE: dual variable of each BS (warm start)
   double la[AMMSE_MAX_LANCZOS];
   double lb[AMMSE_MAX_LANCZOS];
   zd h[AMMSE_MAX_LANCZOS];
@@ -55,15 +90,14 @@ struct Smem {
   int imin;
 };
 
-// C (m x n) = alpha * op(A) * B, row i of C further scaled by rowscale[i / rs_div]
-// when rowscale != nullptr.  op(A) = A (m x k, row-major, lda) or, with CONJA,
+// P (m x n) = op(A) * B handed element by element to the epilogue
+// epi(i, j, P[i][j]).  op(A) = A (m x k, row-major, lda) or, with CONJA,
 // A^H where A is stored k x m row-major (lda).  B is k x n row-major (ldb).
 // All operands in global memory, staged through LDS tiles of 64 x 16.
-template <class R, bool CONJA>
+template <class R, bool CONJA, class Epi>
 __device__ void block_gemm(int m, int n, int k, const cx<R>* __restrict__ A, long lda,
-                           const cx<R>* __restrict__ B, long ldb, cx<R>* __restrict__ Cm,
-                           long ldc, R alpha, const double* rowscale, int rs_div, cx<R>* As,
-                           cx<R>* Bs) {
+                           const cx<R>* __restrict__ B, long ldb, cx<R>* As, cx<R>* Bs,
+                           Epi&& epi) {
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
   for (int i0 = 0; i0 < m; i0 += TM) {
@@ -117,108 +151,164 @@ __device__ void block_gemm(int m, int n, int k, const cx<R>* __restrict__ A, lon
       for (int i = 0; i < 4; ++i) {
         const int gi = i0 + ty + 16 * i;
         if (gi >= m) continue;
-        R s = alpha;
-        if (rowscale) s *= (R)rowscale[gi / rs_div];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int gj = j0 + tx + 16 * j;
-          if (gj < n) Cm[(long)gi * ldc + gj] = scal(s, acc[i][j]);
+          if (gj < n) epi(gi, gj, acc[i][j]);
         }
       }
     }
   }
 }
 
-typedef float floatx4_t __attribute__((ext_vector_type(4)));
-
-// FP32 variant on MFMA (v_mfma_f32_16x16x4f32): same LDS staging, each wave
-// computes a 16 x 64 strip of the 64 x 64 output tile; a complex product is
-// three real accumulators (Re*Re, Im*Im, Re*Im + Im*Re).
-template <bool CONJA>
+// MFMA channel products (FP32 storage): P = op(A) B into the epilogue as in
+// block_gemm, products in T = float (v_mfma_f32_16x16x4f32)
+// or T = bfloat16 (v_mfma_f32_16x16x32_bf16), float accumulation either way.
+// Operand tiles are staged through LDS in planar form (real and imaginary
+// planes, k contiguous per row / column, converted to T on the way in); the
+// global loads of the next k-chunk are issued before the current chunk's
+// products so that their latency overlaps the MFMA work.  Each of the four
+// waves owns a 16-row strip of the 64 x 64 output tile; a complex product is
+// three real accumulators (Re Re, Im Im, Re Im + Im Re).
+template <class T, bool CONJA, class Epi>
 __device__ void block_gemm_mfma(int m, int n, int k, const cx<float>* __restrict__ A, long lda,
-                                const cx<float>* __restrict__ B, long ldb,
-                                cx<float>* __restrict__ Cm, long ldc, float alpha,
-                                const double* rowscale, int rs_div, cx<float>* As,
-                                cx<float>* Bs) {
-  const int tid = threadIdx.x;
+                                const cx<float>* __restrict__ B, long ldb, char* lds, Epi&& epi) {
+  using Tl = MfmaTile<T>;
+  constexpr int KC = Tl::KC, LD = Tl::LD, NA = Tl::NA, NB = Tl::NB;
+  T* AsR = (T*)lds;
+  T* AsI = AsR + TM * LD;
+  T* BsR = AsI + TM * LD;
+  T* BsI = BsR + TN * LD;
+  const int tid = phase_tid();
   const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
-  for (int i0 = 0; i0 < m; i0 += TM) {
-    for (int j0 = 0; j0 < n; j0 += TN) {
-      floatx4_t P[4][3];
+  const int ntn = (n + TN - 1) / TN, nk = (k + KC - 1) / KC;
+  const int steps = ((m + TM - 1) / TM) * ntn * nk;
+  // staging coordinates: A along the contiguous global index, B along columns
+  auto a_rk = [&](int q, int& row, int& kk) {
+    const int e = tid + AMMSE_BLOCK * q;
+    if (CONJA) {
+      row = e % TM;
+      kk = e / TM;
+    } else {
+      kk = e % KC;
+      row = e / KC;
+    }
+  };
+  cx<float> ra[NA], rb[NB];
+  auto fetch = [&](int s) {
+    const int tile = s / nk, k0 = (s - tile * nk) * KC;
+    const int i0 = (tile / ntn) * TM, j0 = (tile % ntn) * TN;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      int row, kk;
+      a_rk(q, row, kk);
+      const int gi = i0 + row, gk = k0 + kk;
+      ra[q] = {0.f, 0.f};
+      if (gi < m && gk < k) ra[q] = CONJA ? A[(long)gk * lda + gi] : A[(long)gi * lda + gk];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + AMMSE_BLOCK * q, col = e % TN, kk = e / TN;
+      const int gj = j0 + col, gk = k0 + kk;
+      rb[q] = {0.f, 0.f};
+      if (gj < n && gk < k) rb[q] = B[(long)gk * ldb + gj];
+    }
+  };
+  floatx4_t P[4][3];
+  fetch(0);
+  for (int s = 0; s < steps; ++s) {
+    const int tile = s / nk, kc = s - tile * nk;
+    if (kc == 0) {
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int q = 0; q < 3; ++q) P[j][q] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-      for (int k0 = 0; k0 < k; k0 += KC) {
-        for (int e = tid; e < TM * KC; e += AMMSE_BLOCK) {
-          int row, kk;
-          if (CONJA) {
-            row = e % TM;
-            kk = e / TM;
-          } else {
-            kk = e % KC;
-            row = e / KC;
-          }
-          const int gi = i0 + row, gk = k0 + kk;
-          cx<float> v = {0.f, 0.f};
-          if (gi < m && gk < k) v = CONJA ? cj(A[(long)gk * lda + gi]) : A[(long)gi * lda + gk];
-          As[kk * (TM + 1) + row] = v;
-        }
-        for (int e = tid; e < KC * TN; e += AMMSE_BLOCK) {
-          const int col = e % TN, kk = e / TN;
-          const int gj = j0 + col, gk = k0 + kk;
-          cx<float> v = {0.f, 0.f};
-          if (gj < n && gk < k) v = B[(long)gk * ldb + gj];
-          Bs[kk * (TN + 1) + col] = v;
-        }
-        __syncthreads();
+    }
+    __syncthreads();   // the previous chunk's products are done with the tiles
 #pragma unroll
-        for (int kk = 0; kk < KC; kk += 4) {
-          const cx<float> a = As[(kk + lk) * (TM + 1) + 16 * wave + li];
-          cx<float> b[4];
+    for (int q = 0; q < NA; ++q) {
+      int row, kk;
+      a_rk(q, row, kk);
+      AsR[row * LD + kk] = (T)ra[q].x;
+      AsI[row * LD + kk] = (T)(CONJA ? -ra[q].y : ra[q].y);
+    }
 #pragma unroll
-          for (int j = 0; j < 4; ++j) b[j] = Bs[(kk + lk) * (TN + 1) + 16 * j + li];
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + AMMSE_BLOCK * q, col = e % TN, kk = e / TN;
+      BsR[col * LD + kk] = (T)rb[q].x;
+      BsI[col * LD + kk] = (T)rb[q].y;
+    }
+    __syncthreads();
+    if (s + 1 < steps) fetch(s + 1);
+    if constexpr (Tl::LOW) {
+      const int ar = (16 * wave + li) * LD + 8 * lk;
+      const bf16x8_t axr = *(const bf16x8_t*)(AsR + ar), axi = *(const bf16x8_t*)(AsI + ar);
+      bf16x8_t bxr[4], bxi[4];
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
-            P[j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b[j].x, P[j][0], 0, 0, 0);
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            P[j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b[j].y, P[j][1], 0, 0, 0);
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            P[j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b[j].y, P[j][2], 0, 0, 0);
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            P[j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b[j].x, P[j][2], 0, 0, 0);
-        }
-        __syncthreads();
+      for (int j = 0; j < 4; ++j) {
+        const int br = (16 * j + li) * LD + 8 * lk;
+        bxr[j] = *(const bf16x8_t*)(BsR + br);
+        bxi[j] = *(const bf16x8_t*)(BsI + br);
       }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        P[j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(axr, bxr[j], P[j][0], 0, 0, 0);
+        P[j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(axi, bxi[j], P[j][1], 0, 0, 0);
+        P[j][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(axr, bxi[j], P[j][2], 0, 0, 0);
+        P[j][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(axi, bxr[j], P[j][2], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < KC; kk += 4) {
+        const int ar = (16 * wave + li) * LD + kk + lk;
+        const float axr = AsR[ar], axi = AsI[ar];
+        float bxr[4], bxi[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int br = (16 * j + li) * LD + kk + lk;
+          bxr[j] = BsR[br];
+          bxi[j] = BsI[br];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          P[j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(axr, bxr[j], P[j][0], 0, 0, 0);
+          P[j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(axi, bxi[j], P[j][1], 0, 0, 0);
+          P[j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(axr, bxi[j], P[j][2], 0, 0, 0);
+          P[j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(axi, bxr[j], P[j][2], 0, 0, 0);
+        }
+      }
+    }
+    if (kc == nk - 1) {
+      const int i0 = (tile / ntn) * TM, j0 = (tile % ntn) * TN;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gi = i0 + 16 * wave + 4 * lk + r;
         if (gi >= m) continue;
-        float s = alpha;
-        if (rowscale) s *= (float)rowscale[gi / rs_div];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int gj = j0 + 16 * j + li;
-          if (gj < n) Cm[(long)gi * ldc + gj] = {s * (P[j][0][r] - P[j][1][r]), s * P[j][2][r]};
+          if (gj < n) epi(gi, gj, cx<float>{P[j][0][r] - P[j][1][r], P[j][2][r]});
         }
       }
     }
   }
+  __syncthreads();
 }
 
-// Channel product dispatch: MFMA for FP32 storage, LDS-tiled FMA for FP64.
-template <class R, bool CONJA>
+// Channel product dispatch: MFMA for FP32 storage (bfloat16 products when
+// lowp), LDS-tiled FMA for FP64.
+template <class R, bool CONJA, class Epi>
 __device__ __forceinline__ void channel_gemm(int m, int n, int k, const cx<R>* A, long lda,
-                                             const cx<R>* B, long ldb, cx<R>* Cm, long ldc,
-                                             R alpha, const double* rowscale, int rs_div,
-                                             cx<R>* As, cx<R>* Bs) {
+                                             const cx<R>* B, long ldb, char* tiles, bool lowp,
+                                             Epi&& epi) {
   if constexpr (sizeof(R) == 4) {
-    block_gemm_mfma<CONJA>(m, n, k, A, lda, B, ldb, Cm, ldc, alpha, rowscale, rs_div, As, Bs);
+    if (lowp)
+      block_gemm_mfma<__bf16, CONJA>(m, n, k, A, lda, B, ldb, tiles, epi);
+    else
+      block_gemm_mfma<float, CONJA>(m, n, k, A, lda, B, ldb, tiles, epi);
   } else {
-    block_gemm<R, CONJA>(m, n, k, A, lda, B, ldb, Cm, ldc, alpha, rowscale, rs_div, As, Bs);
+    cx<R>* As = (cx<R>*)tiles;
+    block_gemm<R, CONJA>(m, n, k, A, lda, B, ldb, As, As + KC * (TM + 1), epi);
   }
 }
 
@@ -226,7 +316,8 @@ __device__ __forceinline__ void channel_gemm(int m, int n, int k, const cx<R>* A
 // The fused kernel
 // ---------------------------------------------------------------------------
 template <class R>
-__global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_t p) {
+__global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_solve_kernel(
+    ammse_kparams_t p) {
   __shared__ Smem<R> sm;
   const ammse_desc_t D = p.desc[blockIdx.x];
   const int tid = threadIdx.x;
@@ -257,106 +348,161 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
   }
   __syncthreads();
 
-  const ammse_ws_layout_t L = ammse_ws_layout((int)sizeof(R), U, M, N, d, p.lanczos_steps);
+  const bool wm = p.algorithm == AMMSE_ALGO_WMMSE;
+  const ammse_ws_layout_t L = ammse_ws_layout((int)sizeof(R), U, M, N, d, p.lanczos_steps, wm);
   char* ws = p.ws + D.ws_off;
   cx<R>* Gp = (cx<R>*)(ws + L.Gp);
   cx<R>* Gq = (cx<R>*)(ws + L.Gq);
   cx<R>* Z = (cx<R>*)(ws + L.Z);
   cx<R>* Vq = (cx<R>*)(ws + L.Vq);
-  cx<R>* Gr = (cx<R>*)(ws + L.Gr);
-  zd* Jm = (zd*)(ws + L.Jm);
+  zd* UWm = (zd*)(ws + L.UWm);
+  zd* Em = (zd*)(ws + L.Em);
   zd* Dm = (zd*)(ws + L.Dm);
   zd* Ym = (zd*)(ws + L.Ym);
   zd* Lq = (zd*)(ws + L.Lq);
   zd* Lw = (zd*)(ws + L.Lw);
   zd* Ly1 = (zd*)(ws + L.Ly1);
   zd* Ly2 = (zd*)(ws + L.Ly2);
+  zd* Am = (zd*)(ws + L.Am);
+  zd* Lm = (zd*)(ws + L.Lm);
+  zd* Bm = (zd*)(ws + L.Bm);
+  zd* Xm = (zd*)(ws + L.Xm);
+  zd* Tm = (zd*)(ws + L.Tm);
+  zd* Lwm = (zd*)(ws + L.Lwm);
+  zd* Lim = (zd*)(ws + L.Lim);
+  zd* Cm = (zd*)(ws + L.Cm);
   const cx<R>* H = (const cx<R>*)p.H + D.h_off;
   cx<R>* V = (cx<R>*)p.V + D.v_off;
   const long Vtot = (long)M * D.ud;
 
-  auto channel_product = [&](cx<R>* G, const cx<R>* Vsrc) {
+  // G_c = S H_{:,c} (scale_c X_c) for every BS c: X holds the precoders up
+  // to the per-BS factor of the sum-power projection, which is applied here
+  // (by linearity) instead of rewriting X.
+  auto channel_product = [&](cx<R>* G, const cx<R>* X, const double* scale, bool lowp) {
     for (int c = 0; c < C; ++c) {
       const int nc = sm.cu[c] * d;
       if (nc == 0) continue;
-      channel_gemm<R, false>(un, nc, M, H + (long)c * un * M, M, Vsrc + (long)M * sm.colOff[c], nc,
-                           G + (long)un * sm.colOff[c], nc, R(1), sm.invsig, N, sm.As, sm.Bs);
+      cx<R>* __restrict__ Gc = G + (long)un * sm.colOff[c];
+      const double sc = scale[c];
+      channel_gemm<R, false>(un, nc, M, H + (long)c * un * M, M, X + (long)M * sm.colOff[c], nc,
+                             sm.tiles, lowp, [&](int i, int j, cx<R> v) {
+                               const R f = (R)(sc * sm.invsig[i / N]);
+                               Gc[(long)i * nc + j] = {f * v.x, f * v.y};
+                             });
     }
   };
 
-  // Per-user receiver algebra on G (normalised products of the current V).
-  // Writes alpha_u R_u into sm.rate; keeps UW and E in the caller's registers.
-  auto interference_cov = [&](const cx<R>* G) {
-    const int np = N * (N + 1) / 2;
-    for (int e = tid; e < U * np; e += AMMSE_BLOCK) {
-      const int u = e / np;
-      int q = e % np, n1 = 0;
-      while (q >= N - n1) {
-        q -= N - n1;
-        ++n1;
-      }
-      const int n2 = n1 + q;
-      const int cown = sm.cellOf[u], j0 = sm.local[u] * d;
-      zd acc = {0.0, 0.0};
+  // Per-user receiver algebra on G (normalised products of the current V):
+  // one user per 16-lane group, lane 4a + b holding entry (a, b) of the
+  // user's N x N and d x d matrices zero/identity-padded to 4 x 4.
+  //   J- = I + sum of G G^H over the columns of the other streams
+  //   F = L^{-1} G_own (J- = L L^H), W = E^{-1} = I + F^H F, R = log det W,
+  //   UW = J-^{-1} G_own, E = Lw^{-H} Lw^{-1}
+  // UW and E go to the workspace; returns the sum of alpha_u R_u (nats) over
+  // the block.
+  auto receivers = [&](const cx<R>* G) -> double {
+    const int tid = phase_tid();
+    const int lane = tid & 63, li = lane & 15;
+    const Lane4 L4{lane & ~15, li >> 2, li & 3};
+    const int ea = L4.a, eb = L4.b;
+    double rsum = 0.0;
+    bool ok = true;
+    for (int u0 = 0; u0 < U; u0 += AMMSE_BLOCK / 16) {
+      const int u = u0 + (tid >> 4);
+      const bool act = u < U;
+      const int uu = act ? u : U - 1;
+      const int cown = sm.cellOf[uu], j0 = sm.local[uu] * d;
+      // J-: lane li accumulates all N x N entries over the columns
+      // j = li (mod 16) of the other streams, then a reduce-scatter over the
+      // 16 lanes leaves entry (a, b) on lane 4a + b.
+      zd sj[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) sj[q] = {0.0, 0.0};
       for (int c = 0; c < C; ++c) {
         const int nc = sm.cu[c] * d;
-        const cx<R>* Gc = G + (long)un * sm.colOff[c];
-        const cx<R>* r1 = Gc + (long)(u * N + n1) * nc;
-        const cx<R>* r2 = Gc + (long)(u * N + n2) * nc;
-        for (int j = 0; j < nc; ++j) {
-          if (c == cown && j >= j0 && j < j0 + d) continue;
-          acc = acc + mulc(to_d(r1[j]), to_d(r2[j]));
+        const cx<R>* __restrict__ r0 = G + (long)un * sm.colOff[c] + (long)(uu * N) * nc;
+        const bool oc = c == cown;
+        for (int j = li; j < nc; j += 16) {
+          if (oc && j >= j0 && j < j0 + d) continue;
+          zd g[AMMSE_MAX_RX];
+#pragma unroll
+          for (int k = 0; k < AMMSE_MAX_RX; ++k)
+            g[k] = (k < N) ? to_d(r0[(long)k * nc + j]) : zd{0.0, 0.0};
+#pragma unroll
+          for (int x = 0; x < AMMSE_MAX_RX; ++x)
+#pragma unroll
+            for (int y = 0; y < AMMSE_MAX_RX; ++y)
+              if (x < N && y < N) sj[x * 4 + y] = sj[x * 4 + y] + mulc(g[x], g[y]);
         }
       }
-      if (n1 == n2) acc = {acc.x + 1.0, 0.0};
-      Jm[u * 16 + n1 * 4 + n2] = acc;
-      Jm[u * 16 + n2 * 4 + n1] = cj(acc);
-    }
-    __syncthreads();
-  };
-
-  auto user_rates = [&](const cx<R>* G, zd* UW, zd* E) {
-    if (tid < U) {
-      const int u = tid;
-      zd J[16], F[16];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int step = 0; step < 4; ++step) {
+        const int bit = 8 >> step;                 // 8, 4, 2, 1 entries exchanged
+        const bool hi = (li & bit) != 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          J[i * 4 + j] = (i < N && j < N) ? Jm[u * 16 + i * 4 + j]
-                                          : zd{(i == j) ? 1.0 : 0.0, 0.0};
-          F[i * 4 + j] = {0.0, 0.0};
+        for (int q = 0; q < bit; ++q) {
+          const zd send = hi ? sj[q] : sj[q + bit];
+          const zd keep = hi ? sj[q + bit] : sj[q];
+          sj[q] = keep + zd{__shfl_xor(send.x, bit, 64), __shfl_xor(send.y, bit, 64)};
         }
-      const int c = sm.cellOf[u], nc = sm.cu[c] * d, j0 = sm.local[u] * d;
-      const cx<R>* Gc = G + (long)un * sm.colOff[c];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-          if (i < N && s < d) F[i * 4 + s] = to_d(Gc[(long)(u * N + i) * nc + j0 + s]);
-      double r;
-      const bool ok = user_receiver(J, F, UW, E, &r);
-      sm.rate[u] = sm.alpha[u] * r;
-      if (!ok) atomicOr(&sm.fail, AMMSE_INST_CHOLESKY);
+      }
+      zd J = {(ea == eb) ? 1.0 : 0.0, 0.0}, F = {0.0, 0.0};
+      if (ea < N && eb < N) J = J + sj[0];
+      if (ea < N && eb < d) {
+        const int c = cown, nc = sm.cu[c] * d;
+        F = to_d(G[(long)un * sm.colOff[c] + (long)(uu * N + ea) * nc + j0 + eb]);
+      }
+      bool oku = true;
+      const zd Lo = chol16(L4, J, oku);
+      F = trsm16(L4, Lo, F);                      // L^{-1} G_own
+      zd X = mm_hn(L4, F, F);                     // I + F^H F
+      if (ea == eb) X = {X.x + 1.0, 0.0};
+      const zd UWv = trsm16h(L4, Lo, F);          // J-^{-1} G_own
+      const zd Lw = chol16(L4, X, oku);
+      const zd Li = trsm16(L4, Lw, zd{(ea == eb) ? 1.0 : 0.0, 0.0});
+      const zd Ev = mm_hn(L4, Li, Li);            // E = Lw^{-H} Lw^{-1}
+      if (act) {
+        if (ea == eb) rsum += sm.alpha[u] * 2.0 * log(Lw.x);
+        UWm[u * 16 + li] = UWv;
+        Em[u * 16 + li] = Ev;
+        if (wm) {
+          Lwm[u * 16 + li] = Lw;
+          Lim[u * 16 + li] = Li;
+        }
+        ok = ok && oku;
+      }
     }
+    if (!ok) atomicOr(&sm.fail, AMMSE_INST_CHOLESKY);
+    return rsum;
   };
 
-  // WSR in bits of the rates in sm.rate (all threads get the value).
-  auto wsr_sum = [&]() {
-    double v = 0.0;
-    for (int u = tid; u < U; u += AMMSE_BLOCK) v += sm.rate[u];
-    return block_sum(v, sm.red) * (1.0 / M_LN2);
-  };
+  // WSR in bits from the per-thread rate sums (all threads get the value).
+  auto wsr_sum = [&](double rs) { return block_sum(rs, sm.red) * (1.0 / M_LN2); };
 
-  // D_u = alpha U W U^H, Y_u = alpha U W into the workspace (padded 4 x 4).
-  auto user_weights_ws = [&](const zd* UW, const zd* E, bool stage2) {
-    if (tid < U) {
-      zd Dl[16], Yl[16];
-      user_weights(UW, E, stage2, sm.alpha[tid], Dl, Yl);
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        Dm[tid * 16 + i] = Dl[i];
-        Ym[tid * 16 + i] = Yl[i];
+  // D_u = alpha U W U^H and Y_u = alpha U W into the workspace (padded 4 x 4):
+  // stage I uses W = I (U = UW E), stage II W = E^{-1} (U W = UW).
+  auto weights = [&](bool stage2) {
+    const int tid = phase_tid();
+    const int lane = tid & 63, li = lane & 15;
+    const Lane4 L4{lane & ~15, li >> 2, li & 3};
+    for (int u0 = 0; u0 < U; u0 += AMMSE_BLOCK / 16) {
+      const int u = u0 + (tid >> 4);
+      const bool act = u < U;
+      const int uu = act ? u : U - 1;
+      const zd UWv = UWm[uu * 16 + li], Ev = Em[uu * 16 + li];
+      const zd T = mm_nn(L4, UWv, Ev);            // U
+      const zd Ur = stage2 ? UWv : T;
+      zd Dv = mm_nh(L4, T, Ur);
+      const zd Dt = L4.at(Dv, L4.b, L4.a);
+      Dv = {0.5 * (Dv.x + Dt.x), 0.5 * (Dv.y - Dt.y)};   // exactly Hermitian
+      const double al = sm.alpha[uu];
+      if (act) {
+        Dm[u * 16 + li] = scal(al, Dv);
+        Ym[u * 16 + li] = scal(al, Ur);
+      }
+      if (wm) {   // D = C C^H with C = sqrt(alpha) UW Lw^{-H} (second stage)
+        const zd Cv = scal(sqrt(al), mm_nh(L4, UWv, Lim[uu * 16 + li]));
+        if (act) Cm[u * 16 + li] = Cv;
       }
     }
     __syncthreads();
@@ -369,12 +515,14 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
   // reduced together.  FP64 forms ||w - alpha q - beta p|| explicitly, FP32
   // uses beta^2 = ||w||^2 - alpha^2 - 2 beta_prev Re(p^H w) + beta_prev^2.
   auto lanczos_lmax = [&](int c) {
+    const int tid = phase_tid();
     const cx<R>* __restrict__ Hc = H + (long)c * un * M;
     zd* qv = Lq;
     zd* pv = Lq + M;
     zd* wv = Lq + 2 * M;
-    int tpr = 1;
-    while (tpr < 64 && tpr * 2 * un <= AMMSE_BLOCK) tpr *= 2;
+    // 16 consecutive threads per row of H (coalesced), fewer for short rows
+    int tpr = 16;
+    while (tpr > 1 && tpr > M) tpr >>= 1;
     int tpc = 1;
     while (tpc < 64 && tpc * 2 * M <= AMMSE_BLOCK) tpc *= 2;
     for (int i = tid; i < M; i += AMMSE_BLOCK) {
@@ -489,14 +637,290 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
     return theta;
   };
 
-  // ---- initial state: G^0, copies for the t = 1 extrapolation
-  channel_product(Gp, V);
+  // The iterate V^t is kept as scur_c * Xc (per BS c) and V^{t-1} as
+  // sprev_c * Xp; Xc and Xp rotate between the caller's V and the workspace
+  // copy Vq.
+  cx<R>* Xc = V;
+  cx<R>* Xp = Vq;
+
+  // ---- WMMSE V step (Algorithm 2, Section IV): per BS c,
+  //   A_c = H_c^H S D S H_c over all users, B_c = H_c^H S Y on the columns of
+  //   the BS's own users (D, Y of the second stage: W = E^{-1}),
+  //   V_c = (A_c + mu I)^{-1} B_c with mu = 0 if the minimum-norm minimiser
+  //   meets the budget, else the root of ||V_c(mu)||^2 = P_c.
+  // With D = C C^H per user, A_c = R^H R and B_c = R^H Z for R = C^H S H_c
+  // ((U d) x M) and Z = sqrt(alpha) Lw^H on the own users' blocks, so
+  //   V_c(mu) = R^H (K + mu I)^{-1} Z,  K = R R^H  ((U d) x (U d)).
+  // When U d <= M this stream-space form is used: K is then generically
+  // nonsingular, mu = 0 gives the minimum-norm (pseudo-inverse) minimiser
+  // even though A_c is singular, and the factorised matrix is the smaller
+  // one.  Otherwise A_c (M x M, generically nonsingular) is factorised.
+  // The root is found by safeguarded Newton steps on 1/||V_c(mu)|| inside a
+  // bisection bracket; the factorisations and solves are in double.
+  // Lm = Cholesky factor (lower) of Am + mu I (n x n); false when not positive definite.
+  auto wm_chol = [&](int n, double mu_) -> bool {
+    const int tid = phase_tid();
+    for (int e = tid; e < n * n; e += AMMSE_BLOCK) {
+      const int i = e / n, j = e - i * n;
+      if (j <= i) {
+        zd a = Am[e];
+        if (i == j) a = {a.x + mu_, 0.0};
+        Lm[e] = a;
+      }
+    }
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+      const double dkk = Lm[k * n + k].x;
+      if (!(dkk > 0.0) || !isfinite(dkk)) {
+        __syncthreads();
+        return false;
+      }
+      const double lkk = sqrt(dkk), il = 1.0 / lkk;
+      for (int i = k + 1 + tid; i < n; i += AMMSE_BLOCK) Lm[i * n + k] = scal(il, Lm[i * n + k]);
+      __syncthreads();
+      if (tid == 0) Lm[k * n + k] = {lkk, 0.0};
+      const int w = n - k - 1;
+      for (int e = tid; e < w * w; e += AMMSE_BLOCK) {
+        const int i = k + 1 + e / w, j = k + 1 + (e - (e / w) * w);
+        if (j <= i) Lm[i * n + j] = Lm[i * n + j] - mulc(Lm[i * n + k], Lm[j * n + k]);
+      }
+      __syncthreads();
+    }
+    return true;
+  };
+  // Triangular solves on the nc columns of a row-major n x nc block: four
+  // threads per column, thread q of a column owning the rows i = q (mod 4);
+  // the partial sums meet by shuffles, so no barrier is needed inside.
+  // Y <- L^{-1} Y (conjT = false) or L^{-H} Y (conjT = true), in place.
+  auto wm_trsm = [&](zd* Y, int n, int nc, bool conjT) {
+    const int tid = phase_tid();
+    const int q = tid & 3;
+    for (int j0 = 0; j0 < nc; j0 += AMMSE_BLOCK / 4) {
+      const int j = j0 + (tid >> 2);
+      const bool act = j < nc;
+      const int jj = act ? j : nc - 1;
+      for (int s = 0; s < n; ++s) {
+        const int k = conjT ? n - 1 - s : s;
+        zd part = {0.0, 0.0};
+        if (!conjT) {
+          for (int i = q; i < k; i += 4) part = part + Lm[k * n + i] * Y[i * nc + jj];
+        } else {
+          for (int i = k + 1 + ((q - (k + 1)) & 3); i < n; i += 4)
+            part = part + cj(Lm[i * n + k]) * Y[i * nc + jj];
+        }
+        part.x += __shfl_xor(part.x, 1, 64);
+        part.y += __shfl_xor(part.y, 1, 64);
+        part.x += __shfl_xor(part.x, 2, 64);
+        part.y += __shfl_xor(part.y, 2, 64);
+        const zd yk = scal(1.0 / Lm[k * n + k].x, Y[k * nc + jj] - part);
+        if (act && q == (k & 3)) Y[k * nc + jj] = yk;
+      }
+    }
+    __syncthreads();
+  };
+  auto wm_norm2 = [&](const zd* Y, int n) {
+    const int tid = phase_tid();
+    double v = 0.0;
+    for (int e = tid; e < n; e += AMMSE_BLOCK) v += nrm2(Y[e]);
+    return block_sum(v, sm.red);
+  };
+  // Probe mu: X = (Am + mu I)^{-1} Bm (n x nc) and q = ||V(mu)||^2 with
+  // V = X (antenna space) or V = R^H X (stream space; formed explicitly, as
+  // shorter expressions cancel catastrophically once a stream is switched off
+  // and K is singular).  Returns false if Am + mu I is not positive definite.
+  auto wm_probe = [&](int n, int nc, bool sspace, double mu_, double& q) -> bool {
+    const int tid = phase_tid();
+    if (!wm_chol(n, mu_)) return false;
+    for (int e = tid; e < n * nc; e += AMMSE_BLOCK) Xm[e] = Bm[e];
+    __syncthreads();
+    wm_trsm(Xm, n, nc, false);
+    wm_trsm(Xm, n, nc, true);
+    if (sspace) {
+      double v = 0.0;
+      for (int e = tid; e < M * nc; e += AMMSE_BLOCK) {
+        const int m = e / nc, j = e - m * nc;
+        zd acc = {0.0, 0.0};
+        for (int k = 0; k < n; ++k) acc = acc + cj(Tm[(long)k * M + m]) * Xm[k * nc + j];
+        v += nrm2(acc);
+      }
+      q = block_sum(v, sm.red);
+    } else {
+      q = wm_norm2(Xm, n * nc);
+    }
+    return true;
+  };
+  auto wmmse_step = [&]() {
+    const int tid = phase_tid();
+    const int nsd = U * d;
+    const bool sspace = nsd <= M;
+    const int n = sspace ? nsd : M;
+    for (int c = 0; c < C; ++c) {
+      const int nc = sm.cu[c] * d;
+      if (nc == 0) continue;
+      const cx<R>* Hc = H + (long)c * un * M;
+      int u0 = 0;
+      while (u0 < U && sm.cellOf[u0] != c) ++u0;
+      if (sspace) {
+        // R = C^H S H_c, one thread per (user, antenna)
+        for (int e = tid; e < U * M; e += AMMSE_BLOCK) {
+          const int u = e / M, m = e - u * M;
+          zd h[AMMSE_MAX_RX];
+#pragma unroll
+          for (int k = 0; k < AMMSE_MAX_RX; ++k)
+            h[k] = (k < N) ? scal(sm.invsig[u], to_d(Hc[(long)(u * N + k) * M + m]))
+                           : zd{0.0, 0.0};
+          for (int s_ = 0; s_ < d; ++s_) {
+            zd r = {0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < AMMSE_MAX_RX; ++k)
+              if (k < N) r = r + cj(Cm[u * 16 + k * 4 + s_]) * h[k];
+            Tm[(long)(u * d + s_) * M + m] = r;
+          }
+        }
+        // Z: sqrt(alpha_u) Lw_u^H on the own users' diagonal blocks
+        for (int e = tid; e < nsd * nc; e += AMMSE_BLOCK) {
+          const int i = e / nc, j = e - (e / nc) * nc;
+          const int u = i / d, s_ = i - u * d, ul = u - u0, t_ = j - (j / d) * d;
+          zd z = {0.0, 0.0};
+          if (ul >= 0 && ul < sm.cu[c] && j / d == ul)
+            z = scal(sqrt(sm.alpha[u]), cj(Lwm[u * 16 + t_ * 4 + s_]));
+          Bm[e] = z;
+        }
+        __syncthreads();
+        // K = R R^H
+        for (int e = tid; e < nsd * nsd; e += AMMSE_BLOCK) {
+          const int i = e / nsd, j = e - i * nsd;
+          const zd* ri = Tm + (long)i * M;
+          const zd* rj = Tm + (long)j * M;
+          zd acc = {0.0, 0.0};
+          for (int m = 0; m < M; ++m) acc = acc + mulc(ri[m], rj[m]);
+          Am[e] = acc;
+        }
+      } else {
+        // T = S D S H_c: one thread per (user, antenna), N rows each
+        for (int e = tid; e < U * M; e += AMMSE_BLOCK) {
+          const int u = e / M, m = e - u * M;
+          const double s2 = sm.invsig[u] * sm.invsig[u];
+          zd h[AMMSE_MAX_RX];
+#pragma unroll
+          for (int k = 0; k < AMMSE_MAX_RX; ++k)
+            h[k] = (k < N) ? to_d(Hc[(long)(u * N + k) * M + m]) : zd{0.0, 0.0};
+#pragma unroll
+          for (int nn = 0; nn < AMMSE_MAX_RX; ++nn) {
+            if (nn < N) {
+              zd acc = {0.0, 0.0};
+#pragma unroll
+              for (int k = 0; k < AMMSE_MAX_RX; ++k)
+                if (k < N) acc = acc + Dm[u * 16 + nn * 4 + k] * h[k];
+              Tm[(long)(u * N + nn) * M + m] = scal(s2, acc);
+            }
+          }
+        }
+        // B_c[m][j] = sum_n conj(H[uN+n][m]) (1/sigma_u) Y_u[n][s], j = local user * d + s
+        for (int e = tid; e < M * nc; e += AMMSE_BLOCK) {
+          const int m = e / nc, j = e - m * nc;
+          const int u = u0 + j / d, s_ = j - (j / d) * d;
+          zd acc = {0.0, 0.0};
+          for (int nn = 0; nn < N; ++nn)
+            acc = acc + cj(to_d(Hc[(long)(u * N + nn) * M + m])) * Ym[u * 16 + nn * 4 + s_];
+          Bm[e] = scal(sm.invsig[u], acc);
+        }
+        __syncthreads();
+        // A_c = H_c^H T
+        for (int e = tid; e < M * M; e += AMMSE_BLOCK) {
+          const int i = e / M, j = e - i * M;
+          zd acc = {0.0, 0.0};
+          for (int r = 0; r < un; ++r)
+            acc = acc + cj(to_d(Hc[(long)r * M + i])) * Tm[(long)r * M + j];
+          Am[e] = acc;
+        }
+      }
+      __syncthreads();
+      const double Pc = sm.Pc[c];
+      double q = 0.0;
+      if (!(Pc > 0.0)) {
+        for (int e = tid; e < n * nc; e += AMMSE_BLOCK) Xm[e] = {0.0, 0.0};
+        __syncthreads();
+      } else {
+        // Root of phi(mu) = 1/||V(mu)|| - 1/sqrt(P) (increasing, nearly linear
+        // in mu) by secant steps through the last two probes, kept inside the
+        // bracket [lo, hi]; bisection (geometric once lo > 0) when a step
+        // leaves the bracket or the bracket stops halving.
+        const double sP = sqrt(Pc);
+        bool ok = wm_probe(n, nc, sspace, 0.0, q);
+        double mu_ = 0.0;
+        if (!ok || q > Pc) {
+          double lo = 0.0, hi;
+          if (sspace) {
+            // ||B_c||^2 = ||R^H Z||^2 <= ||K||_F ||Z||_F^2 and ||V(mu)|| <= ||B_c|| / mu
+            hi = sqrt(sqrt(wm_norm2(Am, n * n)) * wm_norm2(Bm, n * nc) / Pc);
+          } else {
+            hi = sqrt(wm_norm2(Bm, n * nc) / Pc);
+          }
+          bool have_a = ok && q > 0.0;
+          double mu_a = 0.0, ph_a = have_a ? 1.0 / sqrt(q) - 1.0 / sP : 0.0;
+          double next = (sm.mu[c] > 0.0 && sm.mu[c] < hi) ? sm.mu[c] : 0.5 * hi;
+          double wref = hi - lo;
+          int since = 0;
+          for (int probe = 0; probe < 100; ++probe) {
+            double mid = (lo > 0.0) ? sqrt(lo * hi) : 0.5 * (lo + hi);
+            if (!(next > lo && next < hi)) next = mid;
+            mu_ = next;
+            ok = wm_probe(n, nc, sspace, mu_, q);
+            if (!ok) {
+              lo = mu_;
+              next = sqrt(lo * hi);
+              have_a = false;
+              continue;
+            }
+            if (q > Pc) lo = mu_;
+            else hi = mu_;
+            if (fabs(sqrt(q) - sP) <= 1e-13 * sP || hi - lo <= 1e-13 * hi) break;
+            const double ph = (q > 0.0) ? 1.0 / sqrt(q) - 1.0 / sP : 1e300;
+            mid = (lo > 0.0) ? sqrt(lo * hi) : 0.5 * (lo + hi);
+            next = (have_a && ph != ph_a) ? mu_ - ph * (mu_ - mu_a) / (ph - ph_a) : mid;
+            have_a = true;
+            mu_a = mu_;
+            ph_a = ph;
+            if (++since >= 3) {
+              if (hi - lo > 0.5 * wref) next = mid;
+              wref = hi - lo;
+              since = 0;
+            }
+          }
+          if (!ok) atomicOr(&sm.fail, AMMSE_INST_CHOLESKY);
+        }
+        if (tid == 0) sm.mu[c] = mu_;
+      }
+      cx<R>* Vc = Xc + (long)M * sm.colOff[c];
+      if (sspace) {   // V_c = R^H X
+        for (int e = tid; e < M * nc; e += AMMSE_BLOCK) {
+          const int m = e / nc, j = e - m * nc;
+          zd acc = {0.0, 0.0};
+          for (int k = 0; k < nsd; ++k) acc = acc + cj(Tm[(long)k * M + m]) * Xm[k * nc + j];
+          Vc[e] = from_d<R>(acc);
+        }
+      } else {
+        for (int e = tid; e < M * nc; e += AMMSE_BLOCK) Vc[e] = from_d<R>(Xm[e]);
+      }
+      __syncthreads();
+    }
+  };
+
+  // ---- initial state.
+  for (int c = tid; c < C; c += AMMSE_BLOCK) {
+    sm.scur[c] = 1.0;
+    sm.sprev[c] = 1.0;
+    sm.mu[c] = 0.0;
+  }
+  __syncthreads();
+  channel_product(Gp, Xc, sm.scur, p.lowp_iters >= 1);
   __syncthreads();
   const int T = p.wsr_only ? 0 : p.max_iters;
   if (!p.wsr_only) {
     const int nv = (int)Vtot, ng = un * D.ud;
 #pragma unroll 4
-    for (int e = tid; e < nv; e += AMMSE_BLOCK) Vq[e] = V[e];
+    for (int e = tid; e < nv; e += AMMSE_BLOCK) Xp[e] = Xc[e];
 #pragma unroll 4
     for (int e = tid; e < ng; e += AMMSE_BLOCK) Gq[e] = Gp[e];
   }
@@ -504,21 +928,25 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
 
   int fsw = p.force_switch_iter;
   if (p.force_switch && p.force_switch[b] > 0) fsw = p.force_switch[b];
-  bool stage2 = (fsw >= 1) ? (fsw <= 1) : (p.warm_start == 0);
+  bool stage2 = wm || ((fsw >= 1) ? (fsw <= 1) : (p.warm_start == 0));
   int switch_iter = stage2 ? 1 : -1;
   bool prev_step_stage2 = false;
   double wsr_prev = 0.0, wsr_prev2 = 0.0;   // WSR(V^{t-1}), WSR(V^{t-2})
   int iters_run = 0;
   int status = 0;
-  zd UW[16], E[16];
 
   for (int t = 1; t <= T; ++t) {
+    const bool lowp = t <= p.lowp_iters;   // bfloat16 products in this iteration
+    if (p.lowp_iters >= 1 && t == p.lowp_iters + 1) {
+      // refinement pass: G^{t-1} and G^{t-2} again with float products
+      channel_product(Gp, Xc, sm.scur, false);
+      channel_product(Gq, Xp, sm.sprev, false);
+      __syncthreads();
+    }
     // receivers and rate of V^{t-1}
-    interference_cov(Gp);
-    user_rates(Gp, UW, E);
-    __syncthreads();
+    const double rs = receivers(Gp);
     wsr_prev2 = wsr_prev;
-    wsr_prev = wsr_sum();
+    wsr_prev = wsr_sum(rs);
     if (p.trace) {
       if (tid == 0) p.trace[(long)b * p.trace_len + (t - 1)] = wsr_prev;
     }
@@ -540,7 +968,21 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
         switch_iter = t;
       }
     }
-    user_weights_ws(UW, E, stage2);
+    weights(stage2);
+
+    if (wm) {   // Algorithm 2: exact V minimiser, then G^t
+      wmmse_step();
+      {
+        cx<R>* tmp = Gq;
+        Gq = Gp;
+        Gp = tmp;
+      }
+      channel_product(Gp, Xc, sm.scur, false);
+      __syncthreads();
+      prev_step_stage2 = true;
+      iters_run = t;
+      continue;
+    }
 
     // step size
     const bool adaptive = t <= p.T_c || (p.rearm && switch_iter >= 1 && t >= switch_iter &&
@@ -556,69 +998,76 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
       __syncthreads();
     }
 
-    // Z = S (D G^ - Y), G^ = (1+w) G^{t-1} - w G^{t-2}
+    // Z = S (D G^ - Y), G^ = (1+w) G^{t-1} - w G^{t-2}: one thread per
+    // (user, column), consecutive threads along the columns; the N rows of
+    // the user's block of G^ are read once and give the N rows of Z.
     const double om = p.extrapolate ? fmax((t - 2.0) / (t + 1.0), 0.0) : 0.0;
     for (int c = 0; c < C; ++c) {
       const int nc = sm.cu[c] * d;
       const long base = (long)un * sm.colOff[c];
-      // flat element loop (consecutive threads along a row, rows wrap)
-      const int ne = un * nc;
+      const int ne = U * nc;
+#pragma unroll 2
       for (int e = tid; e < ne; e += AMMSE_BLOCK) {
-        const int r = e / nc, j = e - r * nc;
-        const int u = r / N, n = r - u * N;
-        zd acc = {0.0, 0.0};
+        const int u = e / nc, j = e - u * nc;
         const long g0 = base + (long)(u * N) * nc + j;
+        zd gh[AMMSE_MAX_RX];
 #pragma unroll
         for (int k = 0; k < AMMSE_MAX_RX; ++k) {
+          gh[k] = {0.0, 0.0};
           if (k < N) {
             const cx<R> a = Gp[g0 + (long)k * nc], q = Gq[g0 + (long)k * nc];
-            const zd gh = {(1.0 + om) * (double)a.x - om * (double)q.x,
-                           (1.0 + om) * (double)a.y - om * (double)q.y};
-            acc = acc + Dm[u * 16 + n * 4 + k] * gh;
+            gh[k] = {(1.0 + om) * (double)a.x - om * (double)q.x,
+                     (1.0 + om) * (double)a.y - om * (double)q.y};
           }
         }
         const int j0 = sm.local[u] * d;
-        if (sm.cellOf[u] == c && j >= j0 && j < j0 + d) acc = acc - Ym[u * 16 + n * 4 + (j - j0)];
-        Z[base + e] = from_d<R>(scal(sm.invsig[u], acc));
+        const bool own = sm.cellOf[u] == c && j >= j0 && j < j0 + d;
+        const double is = sm.invsig[u];
+#pragma unroll
+        for (int n = 0; n < AMMSE_MAX_RX; ++n) {
+          if (n < N) {
+            zd acc = {0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < AMMSE_MAX_RX; ++k)
+              if (k < N) acc = acc + Dm[u * 16 + n * 4 + k] * gh[k];
+            if (own) acc = acc - Ym[u * 16 + n * 4 + (j - j0)];
+            Z[g0 + (long)n * nc] = from_d<R>(scal(is, acc));
+          }
+        }
       }
     }
     __syncthreads();
 
-    // gradient: Gr_c = 2 H_c^H Z_c
+    // gradient 2 H_c^H Z_c and, in the product's epilogue, the extrapolated
+    // step X~ = (1+w) V^{t-1} - w V^{t-2} - gamma Grad written over V^{t-2};
+    // then the projection factor of each BS from ||X~||^2.
     for (int c = 0; c < C; ++c) {
       const int nc = sm.cu[c] * d;
       if (nc == 0) continue;
-      channel_gemm<R, true>(M, nc, un, H + (long)c * un * M, M, Z + (long)un * sm.colOff[c], nc,
-                          Gr + (long)M * sm.colOff[c], nc, R(2), nullptr, 1, sm.As, sm.Bs);
-    }
-    __syncthreads();
-
-    // extrapolated projected step per BS
-    for (int c = 0; c < C; ++c) {
-      const int nc = sm.cu[c] * d;
       const long base = (long)M * sm.colOff[c];
-      const long n = (long)M * nc;
-      const double g = sm.gamma[c];
+      const cx<R>* __restrict__ xc = Xc + base;
+      cx<R>* __restrict__ xp = Xp + base;
+      const double a1 = (1.0 + om) * sm.scur[c], a2 = om * sm.sprev[c], g2 = 2.0 * sm.gamma[c];
       double pw = 0.0;
-      const int ni = (int)n;
-      cx<R>* __restrict__ Vb = V + base;
-      cx<R>* __restrict__ Vqb = Vq + base;
-      cx<R>* __restrict__ Grb = Gr + base;
-#pragma unroll 4
-      for (int e = tid; e < ni; e += AMMSE_BLOCK) {
-        const zd v = to_d(Vb[e]), vq = to_d(Vqb[e]), gr = to_d(Grb[e]);
-        const zd x = {(1.0 + om) * v.x - om * vq.x - g * gr.x, (1.0 + om) * v.y - om * vq.y - g * gr.y};
-        const cx<R> xs = from_d<R>(x);
-        Grb[e] = xs;
-        pw += nrm2(to_d(xs));
-      }
+      channel_gemm<R, true>(M, nc, un, H + (long)c * un * M, M, Z + (long)un * sm.colOff[c], nc,
+                            sm.tiles, lowp, [&](int i, int j, cx<R> g) {
+                              const long e = (long)i * nc + j;
+                              const zd v = to_d(xc[e]), q = to_d(xp[e]);
+                              const cx<R> xs = from_d<R>(zd{a1 * v.x - a2 * q.x - g2 * (double)g.x,
+                                                            a1 * v.y - a2 * q.y - g2 * (double)g.y});
+                              xp[e] = xs;
+                              pw += nrm2(to_d(xs));
+                            });
       pw = block_sum(pw, sm.red);
-      const double s = (pw > sm.Pc[c]) ? sqrt(sm.Pc[c] / pw) : 1.0;
-#pragma unroll 4
-      for (int e = tid; e < ni; e += AMMSE_BLOCK) {
-        Vqb[e] = Vb[e];
-        Vb[e] = from_d<R>(scal(s, to_d(Grb[e])));
+      if (tid == 0) {
+        sm.sprev[c] = sm.scur[c];
+        sm.scur[c] = (pw > sm.Pc[c]) ? sqrt(sm.Pc[c] / pw) : 1.0;
       }
+    }
+    {
+      cx<R>* tmp = Xc;
+      Xc = Xp;
+      Xp = tmp;
     }
     __syncthreads();
 
@@ -628,7 +1077,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
       Gq = Gp;
       Gp = tmp;
     }
-    channel_product(Gp, V);
+    channel_product(Gp, Xc, sm.scur, lowp);
     __syncthreads();
     prev_step_stage2 = stage2;
     iters_run = t;
@@ -637,22 +1086,30 @@ __global__ __launch_bounds__(AMMSE_BLOCK) void ammse_solve_kernel(ammse_kparams_
   // ---- WSR of the returned precoders
   double wsr_final;
   if (iters_run == T && !status) {
-    interference_cov(Gp);
-    user_rates(Gp, UW, E);
-    __syncthreads();
-    wsr_final = wsr_sum();
+    const double rs = receivers(Gp);
+    wsr_final = wsr_sum(rs);
     if (sm.fail) status |= sm.fail;
     if (!isfinite(wsr_final)) status |= AMMSE_INST_NONFINITE;
     if (p.trace && tid == 0) p.trace[(long)b * p.trace_len + T] = wsr_final;
   } else {
-    wsr_final = wsr_prev;   // stopped early: V holds V^{iters_run}, WSR already known
+    wsr_final = wsr_prev;   // stopped early: V^{iters_run} is the iterate, WSR already known
   }
-  // zero-power check
+  // V = scur X into the caller's buffer; zero-power check
   for (int c = 0; c < C; ++c) {
     const long base = (long)M * sm.colOff[c];
-    const long n = (long)M * sm.cu[c] * d;
+    const int n = M * sm.cu[c] * d;
+    const double sc = sm.scur[c];
     double pw = 0.0;
-    for (int e = tid; e < (int)n; e += AMMSE_BLOCK) pw += nrm2(to_d(V[base + e]));
+    for (int e = tid; e < n; e += AMMSE_BLOCK) {
+      const cx<R> v = Xc[base + e];
+      if (!p.wsr_only) {
+        const cx<R> o = from_d<R>(scal(sc, to_d(v)));
+        V[base + e] = o;
+        pw += nrm2(to_d(o));
+      } else {
+        pw += nrm2(to_d(v));
+      }
+    }
     pw = block_sum(pw, sm.red);
     if (n > 0 && pw == 0.0) status |= AMMSE_INST_ZERO_POWER;
   }

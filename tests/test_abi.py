@@ -44,8 +44,9 @@ def test_version_and_status_strings(L):
 def test_struct_layout_matches_header():
     assert ctypes.sizeof(ammse.AmmseInstance) == 56
     assert ammse.AmmseInstance.h_off.offset == 24
-    assert ctypes.sizeof(ammse.AmmseOptions) == 64
-    assert ammse.AmmseOptions.eps1.offset == 40
+    assert ctypes.sizeof(ammse.AmmseOptions) == 72
+    assert ammse.AmmseOptions.algorithm.offset == 40
+    assert ammse.AmmseOptions.eps1.offset == 48
 
 
 def test_default_options_match_paper(L):
@@ -53,6 +54,7 @@ def test_default_options_match_paper(L):
     L.ammse_default_options(ctypes.byref(o))
     assert (o.precision, o.max_iters, o.T_c, o.warm_start, o.extrapolate) == (1, 100, 3, 1, 1)
     assert o.eps1 == pytest.approx(0.1) and o.eps2 == 0.0 and o.force_switch_iter == -1
+    assert o.refine_iters == 10 and o.algorithm == ammse.ALGO_AMMMSE and o.reserved == 0
 
 
 def test_validate_reports_buffer_lengths(L):
@@ -94,13 +96,22 @@ def test_validate_rejects_overlapping_precoders(L):
 @pytest.mark.parametrize("opt", [
     dict(precision=7), dict(max_iters=-1), dict(T_c=-1), dict(lanczos_steps=65),
     dict(force_switch_iter=0), dict(eps1=-0.1), dict(T_c=0), dict(eps2=float("nan")),
-    dict(path=2), dict(reserved=1),
+    dict(path=2), dict(refine_iters=-1), dict(precision=3), dict(algorithm=2),
+    dict(reserved=1),
 ])
 def test_validate_rejects_bad_options(L, opt):
     table, cu = _one()
     with pytest.raises(ammse.AmmseError) as e:
         ammse.validate(table, cu, ammse.Options(**opt))
     assert e.value.code == 3
+
+
+def test_wmmse_in_bfloat16_is_unsupported(L):
+    table, cu = _one()
+    with pytest.raises(ammse.AmmseError) as e:
+        ammse.validate(table, cu, ammse.Options(algorithm=ammse.ALGO_WMMSE,
+                                                precision=ammse.PREC_BF16))
+    assert e.value.code == 6
 
 
 def test_empty_batch_is_valid_but_cannot_be_planned(L):
