@@ -229,6 +229,61 @@ ammse_status_t ammse_wsr(ammse_plan_t plan, const void* H, const double* sigma2,
                          const double* alpha, const void* V, double* wsr, void* workspace,
                          size_t workspace_bytes, ammse_stream_t stream);
 
+/*
+ * Unrolled (differentiable) A-MMMSE.  T = opt.max_iters iterations of
+ * Algorithm 3 in which the step size of iteration t is an input,
+ * gamma[b * T + t - 1] (the learnable step sizes of an unrolled solver; the
+ * adaptive rule of Section V-A and T_c, gamma_c are not used), with the stage
+ * switch by the eps1 rule or forced, extrapolation and projection as in
+ * ammse_solve; output WSR(V^T).  ammse_unrolled_backward returns the
+ * derivatives of sum_b dwsr[b] * WSR_b(V^T) with respect to the step sizes
+ * and the channels, the stage switch and the projection branch (active or
+ * not) of the forward held fixed.  Supported: plans whose instances are all
+ * single-cell (C = 1), algorithm AMMSE_ALGO_AMMMSE, precision FP64 or FP32
+ * (else AMMSE_ERR_UNSUPPORTED).
+ *
+ * Checkpoints: the forward stores (V^t, V^{t-1}) for t = 0, K, 2K, ... (K =
+ * ckpt_every >= 1) in `ckpt`; the backward recomputes each segment of K
+ * iterations from its checkpoint with the same kernel code and propagates the
+ * adjoints backwards through it, so its memory is O(K) iterations.
+ */
+
+/* Device bytes of the workspace (shared by forward and backward) and of the
+ * checkpoint buffer for this plan and K. */
+ammse_status_t ammse_unrolled_workspace_size(ammse_plan_t plan, int32_t ckpt_every,
+                                             size_t* ws_bytes, size_t* ckpt_bytes);
+
+/*
+ *   H, sigma2, alpha, P, V, wsr, switch_iter, status, wsr_trace, force_switch:
+ *            as for ammse_solve (V: in V^0, out V^T; switch_iter is required)
+ *   gamma    device double [batch][T], step sizes in the caller's instance order
+ *   ckpt     device, ckpt_bytes from ammse_unrolled_workspace_size
+ *   workspace device, ws_bytes, 256-byte aligned
+ */
+ammse_status_t ammse_unrolled_forward(ammse_plan_t plan, const void* H, const double* sigma2,
+                                      const double* alpha, const double* P, void* V,
+                                      const double* gamma, int32_t ckpt_every, double* wsr,
+                                      int32_t* switch_iter, int32_t* status, double* wsr_trace,
+                                      const int32_t* force_switch, void* ckpt, void* workspace,
+                                      size_t workspace_bytes, ammse_stream_t stream);
+
+/*
+ *   gamma, ckpt_every, ckpt: as passed to (and written by) the forward
+ *   switch_iter device int32 [batch], the forward's output
+ *   dwsr     device double [batch], upstream weight of WSR_b
+ *   dH       device, layout of H (complex, storage precision), overwritten with
+ *            dL/dRe(H) + i dL/dIm(H), L = sum_b dwsr[b] WSR_b, so that
+ *            dL = Re sum(conj(dH) * delta H); channel blocks must not overlap
+ *            (else AMMSE_ERR_SHAPE)
+ *   dgamma   device double [batch][T], dL/dgamma
+ */
+ammse_status_t ammse_unrolled_backward(ammse_plan_t plan, const void* H, const double* sigma2,
+                                       const double* alpha, const double* P, const double* gamma,
+                                       int32_t ckpt_every, const int32_t* switch_iter,
+                                       const void* ckpt, const double* dwsr, void* dH,
+                                       double* dgamma, void* workspace, size_t workspace_bytes,
+                                       ammse_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

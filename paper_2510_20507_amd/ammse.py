@@ -33,7 +33,8 @@ INST_ZERO_POWER = 4
 
 EXPORTED = ("ammse_version", "ammse_status_string", "ammse_default_options", "ammse_validate",
             "ammse_plan_create", "ammse_plan_workspace_size", "ammse_plan_destroy",
-            "ammse_solve", "ammse_wsr", "ammse_plan_info")
+            "ammse_solve", "ammse_wsr", "ammse_plan_info", "ammse_unrolled_workspace_size",
+            "ammse_unrolled_forward", "ammse_unrolled_backward")
 KERNEL_LDS_MFMA = 0
 KERNEL_GENERAL = 1
 
@@ -95,6 +96,14 @@ def lib() -> ctypes.CDLL:
     L.ammse_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.ammse_wsr.restype = i32
     L.ammse_wsr.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.ammse_unrolled_workspace_size.restype = i32
+    L.ammse_unrolled_workspace_size.argtypes = [vp, i32, P(sz), P(sz)]
+    L.ammse_unrolled_forward.restype = i32
+    L.ammse_unrolled_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp,
+                                         vp, sz, vp]
+    L.ammse_unrolled_backward.restype = i32
+    L.ammse_unrolled_backward.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp,
+                                          sz, vp]
     _lib = L
     return L
 
@@ -225,6 +234,39 @@ class Plan:
                                  _ptr(status), _ptr(trace), _ptr(force_switch), _ptr(workspace),
                                  workspace.numel() * workspace.element_size(), stream)
         _check(code, "ammse_solve")
+
+    def unrolled_sizes(self, ckpt_every: int) -> tuple:
+        """(workspace bytes, checkpoint bytes) of the unrolled solver."""
+        ws, ck = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().ammse_unrolled_workspace_size(self._handle, int(ckpt_every), ctypes.byref(ws),
+                                                   ctypes.byref(ck)),
+               "ammse_unrolled_workspace_size")
+        return int(ws.value), int(ck.value)
+
+    def unrolled_forward(self, H, sigma2, alpha, P, V, gamma, ckpt_every, wsr, switch_iter, ckpt,
+                         workspace, status=None, trace=None, force_switch=None, stream=None):
+        """ammse_unrolled_forward on device tensors (V: in V^0, out V^T)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        code = lib().ammse_unrolled_forward(
+            self._handle, _ptr(H), _ptr(sigma2), _ptr(alpha), _ptr(P), _ptr(V), _ptr(gamma),
+            int(ckpt_every), _ptr(wsr), _ptr(switch_iter), _ptr(status), _ptr(trace),
+            _ptr(force_switch), _ptr(ckpt), _ptr(workspace),
+            workspace.numel() * workspace.element_size(), stream)
+        _check(code, "ammse_unrolled_forward")
+
+    def unrolled_backward(self, H, sigma2, alpha, P, gamma, ckpt_every, switch_iter, ckpt, dwsr,
+                          dH, dgamma, workspace, stream=None):
+        """ammse_unrolled_backward on device tensors."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        code = lib().ammse_unrolled_backward(
+            self._handle, _ptr(H), _ptr(sigma2), _ptr(alpha), _ptr(P), _ptr(gamma),
+            int(ckpt_every), _ptr(switch_iter), _ptr(ckpt), _ptr(dwsr), _ptr(dH), _ptr(dgamma),
+            _ptr(workspace), workspace.numel() * workspace.element_size(), stream)
+        _check(code, "ammse_unrolled_backward")
 
     def wsr(self, H, sigma2, alpha, V, wsr, workspace=None, stream=None):
         """ammse_wsr on device tensors."""

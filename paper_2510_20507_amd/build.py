@@ -7,7 +7,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libammse.so")
-SOURCES = ["ammse_api.cpp", "ammse_kernels.hip", "ammse_fast.hip"]
+SOURCES = ["ammse_api.cpp", "ammse_kernels.hip", "ammse_fast.hip", "ammse_unroll.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

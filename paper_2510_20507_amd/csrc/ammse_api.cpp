@@ -5,6 +5,7 @@
 #include <cstring>
 #include <new>
 #include <numeric>
+#include <array>
 #include <vector>
 
 #include "ammse_internal.h"
@@ -17,6 +18,11 @@ struct ammse_plan_s {
   size_t ws_bytes = 0;
   ammse_desc_t* d_desc = nullptr;
   int32_t* d_cell_users = nullptr;
+  // for the unrolled solver
+  bool single_cell = true;     // every instance has C == 1
+  bool h_disjoint = true;      // channel blocks do not overlap (dH is written)
+  int64_t v_elems = 0;         // minimum length of V (complex elements)
+  std::vector<std::array<int32_t, 4>> shapes;   // (U, M, N, d) per instance
 };
 
 namespace {
@@ -202,6 +208,22 @@ ammse_status_t ammse_plan_create(ammse_plan_t* plan, int32_t device,
 
   ammse_plan_s* P = new (std::nothrow) ammse_plan_s();
   if (!P) return AMMSE_ERR_ALLOC;
+  {
+    std::vector<std::pair<int64_t, int64_t>> hspans;
+    int64_t vmax = 0;
+    P->shapes.resize(batch);
+    for (int32_t i = 0; i < batch; ++i) {
+      const ammse_instance_t& t = table[i];
+      P->single_cell = P->single_cell && t.C == 1;
+      hspans.emplace_back(t.h_off, (int64_t)t.C * t.U * t.N * t.M);
+      vmax = std::max(vmax, t.v_off + (int64_t)t.M * t.U * t.d);
+      P->shapes[i] = {t.U, t.M, t.N, t.d};
+    }
+    std::sort(hspans.begin(), hspans.end());
+    for (size_t i = 1; i < hspans.size(); ++i)
+      if (hspans[i - 1].first + hspans[i - 1].second > hspans[i].first) P->h_disjoint = false;
+    P->v_elems = vmax;
+  }
   P->device = device;
   P->batch = batch;
   P->use_fast = fast ? 1 : 0;
@@ -324,6 +346,116 @@ ammse_status_t ammse_wsr(ammse_plan_t plan, const void* H, const double* sigma2,
   k.trace_len = 1;
   k.lowp_iters = -1;   // the WSR of V is evaluated with float products
   return launch(plan, k, (hipStream_t)stream);
+}
+
+static ammse_status_t unroll_check(ammse_plan_t plan, int32_t ckpt_every) {
+  if (!plan) return AMMSE_ERR_NULL;
+  if (ckpt_every < 1) return AMMSE_ERR_OPTION;
+  if (!plan->single_cell || plan->opt.algorithm != AMMSE_ALGO_AMMMSE ||
+      plan->opt.precision == AMMSE_PREC_BF16)
+    return AMMSE_ERR_UNSUPPORTED;
+  return AMMSE_OK;
+}
+
+static size_t unroll_stride(ammse_plan_t plan, int32_t K) {
+  const int rb = (plan->opt.precision == AMMSE_PREC_FP64) ? 8 : 4;
+  size_t m = 256;
+  for (const auto& s : plan->shapes)
+    m = std::max(m, ammse_unroll_layout(rb, s[0], s[1], s[2], s[3], K).total);
+  return m;
+}
+
+ammse_status_t ammse_unrolled_workspace_size(ammse_plan_t plan, int32_t ckpt_every,
+                                             size_t* ws_bytes, size_t* ckpt_bytes) {
+  const ammse_status_t st = unroll_check(plan, ckpt_every);
+  if (st != AMMSE_OK) return st;
+  if (!ws_bytes || !ckpt_bytes) return AMMSE_ERR_NULL;
+  const int rb = (plan->opt.precision == AMMSE_PREC_FP64) ? 8 : 4;
+  const int64_t T = plan->opt.max_iters;
+  const int64_t nck = std::max<int64_t>(1, (T + ckpt_every - 1) / ckpt_every);
+  *ws_bytes = unroll_stride(plan, ckpt_every) * (size_t)plan->batch;
+  *ckpt_bytes = (size_t)(2 * nck * plan->v_elems) * 2 * rb;
+  return AMMSE_OK;
+}
+
+static void fill_unroll(ammse_plan_t plan, int32_t K, ammse_unroll_params_t& q) {
+  std::memset(&q, 0, sizeof(q));
+  const int64_t T = plan->opt.max_iters;
+  q.ckpt_every = K;
+  q.nck = (int32_t)std::max<int64_t>(1, (T + K - 1) / K);
+  q.ws_stride = unroll_stride(plan, K);
+  q.fp64 = plan->opt.precision == AMMSE_PREC_FP64;
+}
+
+ammse_status_t ammse_unrolled_forward(ammse_plan_t plan, const void* H, const double* sigma2,
+                                      const double* alpha, const double* P, void* V,
+                                      const double* gamma, int32_t ckpt_every, double* wsr,
+                                      int32_t* switch_iter, int32_t* status, double* wsr_trace,
+                                      const int32_t* force_switch, void* ckpt, void* workspace,
+                                      size_t workspace_bytes, ammse_stream_t stream) {
+  const ammse_status_t st = unroll_check(plan, ckpt_every);
+  if (st != AMMSE_OK) return st;
+  if (!H || !sigma2 || !alpha || !P || !V || !gamma || !wsr || !switch_iter || !ckpt ||
+      !workspace)
+    return AMMSE_ERR_NULL;
+  size_t need = 0, cneed = 0;
+  (void)ammse_unrolled_workspace_size(plan, ckpt_every, &need, &cneed);
+  if (workspace_bytes < need || ((uintptr_t)workspace & 255) != 0) return AMMSE_ERR_WORKSPACE;
+  ammse_kparams_t k;
+  fill_common(plan, k);
+  k.H = H;
+  k.sigma2 = sigma2;
+  k.alpha = alpha;
+  k.P = P;
+  k.V = V;
+  k.wsr = wsr;
+  k.switch_iter = switch_iter;
+  k.status = status;
+  k.trace = wsr_trace;
+  k.force_switch = force_switch;
+  k.ws = (char*)workspace;
+  ammse_unroll_params_t q;
+  fill_unroll(plan, ckpt_every, q);
+  q.gamma = gamma;
+  q.ckpt = ckpt;
+  if (hipSetDevice(plan->device) != hipSuccess) return AMMSE_ERR_HIP;
+  return ammse_launch_unroll(k, q, false, (hipStream_t)stream) == hipSuccess ? AMMSE_OK
+                                                                               : AMMSE_ERR_HIP;
+}
+
+ammse_status_t ammse_unrolled_backward(ammse_plan_t plan, const void* H, const double* sigma2,
+                                       const double* alpha, const double* P, const double* gamma,
+                                       int32_t ckpt_every, const int32_t* switch_iter,
+                                       const void* ckpt, const double* dwsr, void* dH,
+                                       double* dgamma, void* workspace, size_t workspace_bytes,
+                                       ammse_stream_t stream) {
+  const ammse_status_t st = unroll_check(plan, ckpt_every);
+  if (st != AMMSE_OK) return st;
+  if (!H || !sigma2 || !alpha || !P || !gamma || !switch_iter || !ckpt || !dwsr || !dH ||
+      !dgamma || !workspace)
+    return AMMSE_ERR_NULL;
+  if (!plan->h_disjoint) return AMMSE_ERR_SHAPE;
+  size_t need = 0, cneed = 0;
+  (void)ammse_unrolled_workspace_size(plan, ckpt_every, &need, &cneed);
+  if (workspace_bytes < need || ((uintptr_t)workspace & 255) != 0) return AMMSE_ERR_WORKSPACE;
+  ammse_kparams_t k;
+  fill_common(plan, k);
+  k.H = H;
+  k.sigma2 = sigma2;
+  k.alpha = alpha;
+  k.P = P;
+  k.ws = (char*)workspace;
+  ammse_unroll_params_t q;
+  fill_unroll(plan, ckpt_every, q);
+  q.gamma = gamma;
+  q.ckpt = const_cast<void*>(ckpt);
+  q.dH = dH;
+  q.dgamma = dgamma;
+  q.switch_iter = switch_iter;
+  q.dwsr = dwsr;
+  if (hipSetDevice(plan->device) != hipSuccess) return AMMSE_ERR_HIP;
+  return ammse_launch_unroll(k, q, true, (hipStream_t)stream) == hipSuccess ? AMMSE_OK
+                                                                              : AMMSE_ERR_HIP;
 }
 
 }  // extern "C"

@@ -1,0 +1,284 @@
+// Channel products shared by the solve kernels (gfx950): complex GEMMs
+// staged through LDS with an element-wise epilogue functor, FP64 on FMA and
+// FP32 storage on MFMA (float or bfloat16 products, float accumulation).
+#pragma once
+
+#include "ammse_device.h"
+#include "ammse_internal.h"
+
+namespace ammse_dev {
+
+// Thread index hidden from loop-invariant code motion: each phase of the
+// fused kernel re-derives its lane indices instead of the compiler keeping
+// every phase's index arithmetic live across the whole iteration loop, which
+// would cost occupancy.
+__device__ __forceinline__ int phase_tid() {
+  int x = threadIdx.x;
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+constexpr int KC = 16;   // k-chunk of the channel products
+constexpr int TM = 64;   // output tile rows
+constexpr int TN = 64;   // output tile columns
+
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+template <class T>
+struct MfmaTile {
+  static constexpr bool LOW = sizeof(T) == 2;
+  static constexpr int KC = LOW ? 32 : 16;          // k-chunk
+  static constexpr int LD = LOW ? KC + 8 : KC + 1;  // padded k stride (elements)
+  static constexpr int NA = TM * KC / AMMSE_BLOCK;  // staged A elements per thread
+  static constexpr int NB = KC * TN / AMMSE_BLOCK;
+  static constexpr size_t bytes = sizeof(T) * 2 * (TM + TN) * LD;
+};
+
+
+template <class R>
+constexpr size_t tile_bytes() {
+  if constexpr (sizeof(R) == 8) {
+    return sizeof(cx<R>) * KC * (TM + 1 + TN + 1);
+  } else {
+    return MfmaTile<float>::bytes > MfmaTile<__bf16>::bytes ? MfmaTile<float>::bytes
+                                                             : MfmaTile<__bf16>::bytes;
+  }
+}
+
+// P (m x n) = op(A) * op(B) handed element by element to the epilogue
+// epi(i, j, P[i][j]).  op(A) = A (m x k, row-major, lda) or, with CONJA,
+// A^H where A is stored k x m row-major (lda).  op(B) = B (k x n, row-major,
+// ldb) or, with CONJB, B^H where B is stored n x k row-major (ldb).
+// All operands in global memory, staged through LDS tiles of 64 x 16.
+template <class R, bool CONJA, bool CONJB, class Epi>
+__device__ void block_gemm(int m, int n, int k, const cx<R>* __restrict__ A, long lda,
+                           const cx<R>* __restrict__ B, long ldb, cx<R>* As, cx<R>* Bs,
+                           Epi&& epi) {
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  for (int i0 = 0; i0 < m; i0 += TM) {
+    for (int j0 = 0; j0 < n; j0 += TN) {
+      cx<R> acc[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = {R(0), R(0)};
+      for (int k0 = 0; k0 < k; k0 += KC) {
+        for (int e = tid; e < TM * KC; e += AMMSE_BLOCK) {
+          int row, kk;
+          if (CONJA) {
+            row = e % TM;
+            kk = e / TM;
+          } else {
+            kk = e % KC;
+            row = e / KC;
+          }
+          const int gi = i0 + row, gk = k0 + kk;
+          cx<R> v = {R(0), R(0)};
+          if (gi < m && gk < k) v = CONJA ? cj(A[(long)gk * lda + gi]) : A[(long)gi * lda + gk];
+          As[kk * (TM + 1) + row] = v;
+        }
+        for (int e = tid; e < KC * TN; e += AMMSE_BLOCK) {
+          const int col = CONJB ? e / KC : e % TN, kk = CONJB ? e % KC : e / TN;
+          const int gj = j0 + col, gk = k0 + kk;
+          cx<R> v = {R(0), R(0)};
+          if (gj < n && gk < k) v = CONJB ? cj(B[(long)gj * ldb + gk]) : B[(long)gk * ldb + gj];
+          Bs[kk * (TN + 1) + col] = v;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < KC; ++kk) {
+          cx<R> a[4], b[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) a[i] = As[kk * (TM + 1) + ty + 16 * i];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) b[j] = Bs[kk * (TN + 1) + tx + 16 * j];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              acc[i][j].x += a[i].x * b[j].x - a[i].y * b[j].y;
+              acc[i][j].y += a[i].x * b[j].y + a[i].y * b[j].x;
+            }
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gi = i0 + ty + 16 * i;
+        if (gi >= m) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int gj = j0 + tx + 16 * j;
+          if (gj < n) epi(gi, gj, acc[i][j]);
+        }
+      }
+    }
+  }
+}
+
+// MFMA channel products (FP32 storage): P = op(A) B into the epilogue as in
+// block_gemm, products in T = float (v_mfma_f32_16x16x4f32)
+// or T = bfloat16 (v_mfma_f32_16x16x32_bf16), float accumulation either way.
+// Operand tiles are staged through LDS in planar form (real and imaginary
+// planes, k contiguous per row / column, converted to T on the way in); the
+// global loads of the next k-chunk are issued before the current chunk's
+// products so that their latency overlaps the MFMA work.  Each of the four
+// waves owns a 16-row strip of the 64 x 64 output tile; a complex product is
+// three real accumulators (Re Re, Im Im, Re Im + Im Re).
+template <class T, bool CONJA, bool CONJB, class Epi>
+__device__ void block_gemm_mfma(int m, int n, int k, const cx<float>* __restrict__ A, long lda,
+                                const cx<float>* __restrict__ B, long ldb, char* lds, Epi&& epi) {
+  using Tl = MfmaTile<T>;
+  constexpr int KC = Tl::KC, LD = Tl::LD, NA = Tl::NA, NB = Tl::NB;
+  T* AsR = (T*)lds;
+  T* AsI = AsR + TM * LD;
+  T* BsR = AsI + TM * LD;
+  T* BsI = BsR + TN * LD;
+  const int tid = phase_tid();
+  const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  const int ntn = (n + TN - 1) / TN, nk = (k + KC - 1) / KC;
+  const int steps = ((m + TM - 1) / TM) * ntn * nk;
+  // staging coordinates: A along the contiguous global index, B along columns
+  auto a_rk = [&](int q, int& row, int& kk) {
+    const int e = tid + AMMSE_BLOCK * q;
+    if (CONJA) {
+      row = e % TM;
+      kk = e / TM;
+    } else {
+      kk = e % KC;
+      row = e / KC;
+    }
+  };
+  auto b_ck = [&](int q, int& col, int& kk) {
+    const int e = tid + AMMSE_BLOCK * q;
+    if (CONJB) {
+      kk = e % KC;
+      col = e / KC;
+    } else {
+      col = e % TN;
+      kk = e / TN;
+    }
+  };
+  cx<float> ra[NA], rb[NB];
+  auto fetch = [&](int s) {
+    const int tile = s / nk, k0 = (s - tile * nk) * KC;
+    const int i0 = (tile / ntn) * TM, j0 = (tile % ntn) * TN;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      int row, kk;
+      a_rk(q, row, kk);
+      const int gi = i0 + row, gk = k0 + kk;
+      ra[q] = {0.f, 0.f};
+      if (gi < m && gk < k) ra[q] = CONJA ? A[(long)gk * lda + gi] : A[(long)gi * lda + gk];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      int col, kk;
+      b_ck(q, col, kk);
+      const int gj = j0 + col, gk = k0 + kk;
+      rb[q] = {0.f, 0.f};
+      if (gj < n && gk < k) rb[q] = CONJB ? cj(B[(long)gj * ldb + gk]) : B[(long)gk * ldb + gj];
+    }
+  };
+  floatx4_t P[4][3];
+  fetch(0);
+  for (int s = 0; s < steps; ++s) {
+    const int tile = s / nk, kc = s - tile * nk;
+    if (kc == 0) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) P[j][q] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    }
+    __syncthreads();   // the previous chunk's products are done with the tiles
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      int row, kk;
+      a_rk(q, row, kk);
+      AsR[row * LD + kk] = (T)ra[q].x;
+      AsI[row * LD + kk] = (T)(CONJA ? -ra[q].y : ra[q].y);
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      int col, kk;
+      b_ck(q, col, kk);
+      BsR[col * LD + kk] = (T)rb[q].x;
+      BsI[col * LD + kk] = (T)rb[q].y;
+    }
+    __syncthreads();
+    if (s + 1 < steps) fetch(s + 1);
+    if constexpr (Tl::LOW) {
+      const int ar = (16 * wave + li) * LD + 8 * lk;
+      const bf16x8_t axr = *(const bf16x8_t*)(AsR + ar), axi = *(const bf16x8_t*)(AsI + ar);
+      bf16x8_t bxr[4], bxi[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int br = (16 * j + li) * LD + 8 * lk;
+        bxr[j] = *(const bf16x8_t*)(BsR + br);
+        bxi[j] = *(const bf16x8_t*)(BsI + br);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        P[j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(axr, bxr[j], P[j][0], 0, 0, 0);
+        P[j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(axi, bxi[j], P[j][1], 0, 0, 0);
+        P[j][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(axr, bxi[j], P[j][2], 0, 0, 0);
+        P[j][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(axi, bxr[j], P[j][2], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < KC; kk += 4) {
+        const int ar = (16 * wave + li) * LD + kk + lk;
+        const float axr = AsR[ar], axi = AsI[ar];
+        float bxr[4], bxi[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int br = (16 * j + li) * LD + kk + lk;
+          bxr[j] = BsR[br];
+          bxi[j] = BsI[br];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          P[j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(axr, bxr[j], P[j][0], 0, 0, 0);
+          P[j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(axi, bxi[j], P[j][1], 0, 0, 0);
+          P[j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(axr, bxi[j], P[j][2], 0, 0, 0);
+          P[j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(axi, bxr[j], P[j][2], 0, 0, 0);
+        }
+      }
+    }
+    if (kc == nk - 1) {
+      const int i0 = (tile / ntn) * TM, j0 = (tile % ntn) * TN;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = i0 + 16 * wave + 4 * lk + r;
+        if (gi >= m) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int gj = j0 + 16 * j + li;
+          if (gj < n) epi(gi, gj, cx<float>{P[j][0][r] - P[j][1][r], P[j][2][r]});
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Channel product dispatch: MFMA for FP32 storage (bfloat16 products when
+// lowp), LDS-tiled FMA for FP64.
+template <class R, bool CONJA, bool CONJB = false, class Epi>
+__device__ __forceinline__ void channel_gemm(int m, int n, int k, const cx<R>* A, long lda,
+                                             const cx<R>* B, long ldb, char* tiles, bool lowp,
+                                             Epi&& epi) {
+  if constexpr (sizeof(R) == 4) {
+    if (lowp)
+      block_gemm_mfma<__bf16, CONJA, CONJB>(m, n, k, A, lda, B, ldb, tiles, epi);
+    else
+      block_gemm_mfma<float, CONJA, CONJB>(m, n, k, A, lda, B, ldb, tiles, epi);
+  } else {
+    cx<R>* As = (cx<R>*)tiles;
+    block_gemm<R, CONJA, CONJB>(m, n, k, A, lda, B, ldb, As, As + KC * (TM + 1), epi);
+  }
+}
+
+}  // namespace ammse_dev

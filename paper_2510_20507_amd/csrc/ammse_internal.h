@@ -105,6 +105,59 @@ __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int
   return L;
 }
 
+// Workspace of one instance of the unrolled solver (forward and adjoint), K
+// iterations per checkpoint segment; every sub-buffer 256-byte aligned.
+struct ammse_unroll_layout_t {
+  size_t Vs, Gs, Zs, Grs, Vts, sp;           // segment storage
+  size_t UWs, Es, Los, Ds, Ys;               // per-user blocks, K + 1 slots
+  size_t Vb, Gb, Zb, Tb, Pa, Pb;             // adjoints
+  size_t total;
+};
+
+__host__ __device__ inline ammse_unroll_layout_t ammse_unroll_layout(int real_bytes, int U, int M,
+                                                                     int N, int d, int K) {
+  const size_t cs = 2 * (size_t)real_bytes, zs = 16;
+  const size_t v = (size_t)M * U * d * cs, g = (size_t)U * N * U * d * cs;
+  const size_t ub = (size_t)U * 16 * zs;
+  ammse_unroll_layout_t L;
+  size_t o = 0;
+  L.Vs = o;  o += ammse_align256((size_t)(K + 2) * v);
+  L.Gs = o;  o += ammse_align256((size_t)(K + 2) * g);
+  L.Zs = o;  o += ammse_align256((size_t)K * g);
+  L.Grs = o; o += ammse_align256((size_t)K * v);
+  L.Vts = o; o += ammse_align256((size_t)K * v);
+  L.sp = o;  o += ammse_align256((size_t)K * 2 * sizeof(double));
+  L.UWs = o; o += ammse_align256((size_t)(K + 1) * ub);
+  L.Es = o;  o += ammse_align256((size_t)(K + 1) * ub);
+  L.Los = o; o += ammse_align256((size_t)(K + 1) * ub);
+  L.Ds = o;  o += ammse_align256((size_t)(K + 1) * ub);
+  L.Ys = o;  o += ammse_align256((size_t)(K + 1) * ub);
+  L.Vb = o;  o += ammse_align256(3 * v);
+  L.Gb = o;  o += ammse_align256(3 * g);
+  L.Zb = o;  o += ammse_align256(g);
+  L.Tb = o;  o += ammse_align256(v);
+  L.Pa = o;  o += ammse_align256(ub);
+  L.Pb = o;  o += ammse_align256(ub);
+  L.total = o;
+  return L;
+}
+
+// Extra launch parameters of the unrolled solver.
+struct ammse_unroll_params_t {
+  const double* gamma;        // [batch][T] step sizes (caller's instance order)
+  void* ckpt;                 // checkpoints: instance b at element 2 * nck * v_off
+  void* dH;                   // adjoint only: dWSR/dH, layout of H
+  double* dgamma;             // adjoint only: [batch][T]
+  const int32_t* switch_iter; // adjoint only: stage-switch iteration of the forward
+  const double* dwsr;         // adjoint only: upstream weight per instance
+  size_t ws_stride;           // workspace bytes per launched workgroup
+  int32_t ckpt_every;         // K
+  int32_t nck;                // checkpoints per instance, ceil(T / K)
+  int32_t fp64;
+};
+
+hipError_t ammse_launch_unroll(const ammse_kparams_t& p, const ammse_unroll_params_t& q,
+                               bool backward, hipStream_t s);
 hipError_t ammse_launch_fp64(const ammse_kparams_t& p, hipStream_t s);
 size_t ammse_general_lds_bytes(int precision);
 // LDS-resident MFMA kernel (FP32): shapes it serves, its LDS use, launch.

@@ -28,7 +28,7 @@ def L():
 
 def test_every_declared_symbol_is_exported(L):
     names = _declared_functions()
-    assert len(names) == 10
+    assert len(names) == 13
     assert set(names) == set(ammse.EXPORTED)
     for n in names:
         assert hasattr(L, n), n
