@@ -38,7 +38,7 @@ LARGE_REF_FILE = os.path.join(ROOT, "tests", "golden", "oracle_ref_rayleigh_m256
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ammse_solve_fp32_rayleigh_sweep1024_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2510_20507_amd", "csrc", f)
                   for f in ("ammse_fast.hip", "ammse_kernels.hip", "ammse_device.h",
-                            "ammse_internal.h")]
+                            "ammse_internal.h", "ammse_gemm.h")]
 PEAK_FP32_MFMA_TFLOPS = 157.3
 ITERS = 100
 CALIB_COPY_MIB = 1024
@@ -208,6 +208,87 @@ def gpu_wmmse(batch, ref, max_iters: int = 500, eps: float = 1e-6):
             "precision": "fp32 products, fp64 M x M solves"}
 
 
+def unrolled_leg(B: int = 1024, T: int = 20, K: int = 5, reps: int = 3):
+    """Differentiable unrolled A-MMMSE on the 1024-instance 64-antenna batch
+    (16 users, N=d=4, P=20 dB): forward with checkpoints every K iterations
+    and the adjoint (dWSR/dgamma, dWSR/dH), FP32, constant step 0.004 (the
+    order of the paper's stage-II step at this shape), timed with HIP events."""
+    import torch
+    from paper_2510_20507_amd import ammse, synth
+    batch = synth.unrolled_batch(B)
+    opts = ammse.Options(precision=ammse.PREC_FP32, max_iters=T)
+    db = ammse.to_device(batch, opts.precision)
+    plan = ammse.Plan(db.table, db.cell_users, opts)
+    ws_b, ck_b = plan.unrolled_sizes(K)
+    ws = torch.empty(ws_b, dtype=torch.uint8, device="cuda")
+    ck = torch.empty(ck_b, dtype=torch.uint8, device="cuda")
+    g = torch.full((B, T), 0.004, dtype=torch.float64, device="cuda")
+    V = torch.empty_like(db.V0)
+    wsr = torch.empty(B, dtype=torch.float64, device="cuda")
+    sw = torch.empty(B, dtype=torch.int32, device="cuda")
+    dw = torch.ones(B, dtype=torch.float64, device="cuda")
+    dH = torch.empty_like(db.H)
+    dg = torch.empty_like(g)
+    fw, bw = [], []
+    for r in range(reps + 1):
+        V.copy_(db.V0)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        plan.unrolled_forward(db.H, db.sigma2, db.alpha, db.P, V, g, K, wsr, sw, ck, ws)
+        e[1].record()
+        plan.unrolled_backward(db.H, db.sigma2, db.alpha, db.P, g, K, sw, ck, dw, dH, dg, ws)
+        e[2].record()
+        torch.cuda.synchronize()
+        if r > 0:
+            fw.append(e[0].elapsed_time(e[1]))
+            bw.append(e[1].elapsed_time(e[2]))
+    plan.close()
+    f, b_ = float(np.mean(fw)), float(np.mean(bw))
+    ok = bool(torch.isfinite(dg).all()) and bool(torch.isfinite(wsr).all())
+    return {"workload": batch.name, "instances": B, "T": T, "ckpt_every": K,
+            "precision": "fp32", "forward_ms": f, "backward_ms": b_,
+            "instances_per_s_fwd_bwd": B / ((f + b_) / 1e3), "finite": ok,
+            "workspace_bytes": ws_b, "checkpoint_bytes": ck_b}
+
+
+def early_exit(batch, ref, eps_list=(1e-3, 1e-4, 1e-5)):
+    """eps2 stop (Algorithm 3's second tolerance) with per-instance retirement:
+    each workgroup leaves its loop once the relative WSR change of a stage-II
+    step is <= eps2 (at most 100 iterations); time of the whole batch and
+    instances reaching 99 % of the FP64 WMMSE reference."""
+    import torch
+    from paper_2510_20507_amd import ammse
+    out = []
+    db = ammse.to_device(batch, ammse.PREC_FP32)
+    for eps in eps_list:
+        opts = ammse.Options(precision=ammse.PREC_FP32, max_iters=ITERS, eps2=eps)
+        plan = ammse.Plan(db.table, db.cell_users, opts)
+        ws = plan.workspace()
+        V = torch.empty_like(db.V0)
+        wsr = torch.empty(batch.batch, dtype=torch.float64, device="cuda")
+        it = torch.empty(batch.batch, dtype=torch.int32, device="cuda")
+        st = torch.empty(batch.batch, dtype=torch.int32, device="cuda")
+        ms = []
+        for r in range(3):
+            V.copy_(db.V0)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.solve(db.H, db.sigma2, db.alpha, db.P, V, wsr, it, None, st, workspace=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            if r:
+                ms.append(e0.elapsed_time(e1))
+        w = wsr.cpu().numpy()
+        ok = int(((w >= 0.99 * ref) & (st.cpu().numpy() == 0)).sum())
+        t = float(np.mean(ms))
+        out.append({"eps2": eps, "kernel_ms": t, "reached_99": ok,
+                    "instances_per_s_reached_99": ok / (t / 1e3),
+                    "mean_iters": float(it.cpu().numpy().mean())})
+        plan.close()
+    return out
+
+
 def parse_pmc(dirs):
     """Sum FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the solve kernel and of
     the calibration copy from rocprofv3 --pmc CSV output directories."""
@@ -257,6 +338,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-wmmse", action="store_true")
+    ap.add_argument("--no-unrolled", action="store_true")
+    ap.add_argument("--no-early-exit", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help=f"also run a {CALIB_COPY_MIB} MiB device copy (counter calibration)")
     ap.add_argument("--parse-pmc", nargs="+", metavar="DIR")
@@ -359,6 +442,10 @@ def main():
         line["mixed_precision"] = mixed_precision()
     if not a.no_wmmse:
         line["gpu_wmmse"] = gpu_wmmse(batch, ref)
+    if not a.no_unrolled:
+        line["unrolled"] = unrolled_leg()
+    if not a.no_early_exit:
+        line["early_exit"] = early_exit(batch, ref)
     if a.calib_copy:
         n = CALIB_COPY_MIB * (1 << 20) // 4
         x = torch.ones(n, dtype=torch.float32, device="cuda")

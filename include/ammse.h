@@ -118,6 +118,13 @@ typedef struct ammse_instance_t {
                                 extrapolate, gamma_c are ignored.  FP64 and FP32
                                 storage (the M x M solve runs in double); the
                                 general kernel only. */
+#define AMMSE_ALGO_MMMSE 2   /* Section V-B (mixed weighted-unweighted sum-MSE):
+                                WMMSE iterations with W = I (sum-MSE block
+                                coordinate descent, V by the same exact minimiser)
+                                until the eps1 rule of Algorithm 3 switches to W =
+                                E^{-1}; eps2 stops after a second-stage iteration.
+                                warm_start = 0 or force_switch_iter as for
+                                Algorithm 3; otherwise as AMMSE_ALGO_WMMSE. */
 
 /* Solver options (Algorithm 3 inputs). */
 typedef struct ammse_options_t {
@@ -136,7 +143,7 @@ typedef struct ammse_options_t {
                                 AMMSE_PATH_GENERAL: always the general kernel */
   int32_t refine_iters;      /* AMMSE_PREC_BF16: final iterations with float products
                                 (the refinement pass); ignored otherwise */
-  int32_t algorithm;         /* AMMSE_ALGO_AMMMSE (Algorithm 3) or AMMSE_ALGO_WMMSE */
+  int32_t algorithm;         /* AMMSE_ALGO_AMMMSE (Algorithm 3), _WMMSE or _MMMSE */
   int32_t reserved;          /* must be 0 */
   double eps1;               /* stage-switch tolerance (paper: 0.1) */
   double eps2;               /* stop tolerance (0: run exactly max_iters) */

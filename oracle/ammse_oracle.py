@@ -55,7 +55,7 @@ __all__ = [
     "Problem", "from_instance", "split_v", "join_v", "cross_terms", "user_rates", "wsr_bits",
     "mmse_receivers", "mse_matrices", "mse_at_mmse", "objective_f", "transmit_hessians",
     "gradient_v", "step_sizes", "project_spc", "omega_schedule", "rel_change", "ammmse",
-    "wmmse", "wmmse_precoder", "kkt_residual", "kappa", "solve_batch",
+    "wmmse", "wmmse_precoder", "mmmse", "kkt_residual", "kappa", "solve_batch",
 ]
 
 
@@ -431,6 +431,42 @@ def wmmse(prob: Problem, V0u: np.ndarray, max_iters: int = 500, eps: float = 1e-
     return dict(V=V, wsr=trace[-1], trace=np.array(trace), iters=it)
 
 
+def mmmse(prob: Problem, V0u: np.ndarray, max_iters: int = 500, eps1: float = 0.1,
+          eps2: float = 1e-6, mode: str = "reference", force_switch_iter: Optional[int] = None
+          ) -> dict:
+    """MMMSE (Section V-B, mixed weighted-unweighted sum-MSE): stage I is BCD on
+    the sum-MSE problem (W = I: U by the receiver equation, V by the
+    eq:mmse_Vk solve with its dual mu found by bisection, i.e. the WMMSE V step
+    with W = I); once the relative WSR change between V^{t-1} and V^{t-2} is
+    <= eps1 (tested at the start of iteration t, as in Algorithm 3) iteration t
+    and the later ones are WMMSE iterations (W = E^{-1}); stop once a stage-II
+    step changes the WSR by <= eps2 (relative) or after max_iters."""
+    V = V0u.copy()
+    trace = [wsr_bits(prob, V)]
+    stage2 = force_switch_iter is not None and force_switch_iter <= 1
+    switch = 1 if stage2 else -1
+    prev_stage2 = False
+    it = 0
+    for t in range(1, max_iters + 1):
+        if prev_stage2 and t >= 2 and rel_change(trace[-1], trace[-2]) <= eps2:
+            break
+        if not stage2:
+            trig = (t >= force_switch_iter) if force_switch_iter is not None else \
+                (t >= 2 and rel_change(trace[-1], trace[-2]) <= eps1)
+            if trig:
+                stage2, switch = True, t
+        Uu = mmse_receivers(prob, V)
+        if stage2:
+            Wu = _inv_hermitian(mse_at_mmse(prob, Uu, V))
+        else:
+            Wu = np.stack([np.eye(prob.d, dtype=np.complex128)] * prob.U)
+        V, _ = wmmse_precoder(prob, Uu, Wu, mode)
+        trace.append(wsr_bits(prob, V))
+        prev_stage2 = stage2
+        it = t
+    return dict(V=V, wsr=trace[-1], trace=np.array(trace), iters=it, switch_iter=switch)
+
+
 # ---------------------------------------------------------------------------
 # Stationarity and constants (Section VI)
 # ---------------------------------------------------------------------------
@@ -486,6 +522,8 @@ def _solve_one(args):
         r = ammmse(prob, V0, **kw)
     elif algo == "wmmse":
         r = wmmse(prob, V0, **kw)
+    elif algo == "mmmse":
+        r = mmmse(prob, V0, **kw)
     elif algo == "wsr":
         r = dict(wsr=wsr_bits(prob, V0), V=V0)
     else:

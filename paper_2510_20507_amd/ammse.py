@@ -27,6 +27,7 @@ PATH_AUTO = 0
 PATH_GENERAL = 1
 ALGO_AMMMSE = 0
 ALGO_WMMSE = 1
+ALGO_MMMSE = 2
 INST_NONFINITE = 1
 INST_CHOLESKY = 2
 INST_ZERO_POWER = 4

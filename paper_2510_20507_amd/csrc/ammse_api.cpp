@@ -44,9 +44,11 @@ ammse_status_t check_options(const ammse_options_t& o) {
   if (o.lanczos_steps < 0 || o.lanczos_steps > AMMSE_MAX_LANCZOS) return AMMSE_ERR_OPTION;
   if (o.path != AMMSE_PATH_AUTO && o.path != AMMSE_PATH_GENERAL) return AMMSE_ERR_OPTION;
   if (o.refine_iters < 0) return AMMSE_ERR_OPTION;
-  if (o.algorithm != AMMSE_ALGO_AMMMSE && o.algorithm != AMMSE_ALGO_WMMSE) return AMMSE_ERR_OPTION;
+  if (o.algorithm != AMMSE_ALGO_AMMMSE && o.algorithm != AMMSE_ALGO_WMMSE &&
+      o.algorithm != AMMSE_ALGO_MMMSE)
+    return AMMSE_ERR_OPTION;
   if (o.reserved != 0) return AMMSE_ERR_OPTION;
-  if (o.algorithm == AMMSE_ALGO_WMMSE && o.precision == AMMSE_PREC_BF16)
+  if (o.algorithm != AMMSE_ALGO_AMMMSE && o.precision == AMMSE_PREC_BF16)
     return AMMSE_ERR_UNSUPPORTED;
   if (!(o.eps1 >= 0.0) || !(o.eps2 >= 0.0)) return AMMSE_ERR_OPTION;
   if (o.T_c == 0 && !(o.gamma_c > 0.0)) return AMMSE_ERR_OPTION;
@@ -203,7 +205,7 @@ ammse_status_t ammse_plan_create(ammse_plan_t* plan, int32_t device,
     d.bs_off = t.bs_off;
     d.ws_off = (int64_t)off;
     if (!fast)
-      off += ammse_ws_layout(rb, t.U, t.M, t.N, t.d, ls, o.algorithm == AMMSE_ALGO_WMMSE).total;
+      off += ammse_ws_layout(rb, t.U, t.M, t.N, t.d, ls, o.algorithm != AMMSE_ALGO_AMMMSE).total;
   }
 
   ammse_plan_s* P = new (std::nothrow) ammse_plan_s();

@@ -89,7 +89,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   }
   __syncthreads();
 
-  const bool wm = p.algorithm == AMMSE_ALGO_WMMSE;
+  const bool wm = p.algorithm != AMMSE_ALGO_AMMMSE;   // exact V step (Algorithm 2 / MMMSE)
   const ammse_ws_layout_t L = ammse_ws_layout((int)sizeof(R), U, M, N, d, p.lanczos_steps, wm);
   char* ws = p.ws + D.ws_off;
   cx<R>* Gp = (cx<R>*)(ws + L.Gp);
@@ -241,8 +241,8 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
         Dm[u * 16 + li] = scal(al, Dv);
         Ym[u * 16 + li] = scal(al, Ur);
       }
-      if (wm) {   // D = C C^H with C = sqrt(alpha) UW Lw^{-H} (second stage)
-        const zd Cv = scal(sqrt(al), mm_nh(L4, UWv, Lim[uu * 16 + li]));
+      if (wm) {   // D = C C^H: C = sqrt(alpha) UW Lw^{-H} (stage II) or sqrt(alpha) U (stage I)
+        const zd Cv = scal(sqrt(al), stage2 ? mm_nh(L4, UWv, Lim[uu * 16 + li]) : T);
         if (act) Cm[u * 16 + li] = Cv;
       }
     }
@@ -490,7 +490,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     }
     return true;
   };
-  auto wmmse_step = [&]() {
+  auto wmmse_step = [&](bool stage2) {
     const int tid = phase_tid();
     const int nsd = U * d;
     const bool sspace = nsd <= M;
@@ -518,13 +518,15 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
             Tm[(long)(u * d + s_) * M + m] = r;
           }
         }
-        // Z: sqrt(alpha_u) Lw_u^H on the own users' diagonal blocks
+        // Z: sqrt(alpha_u) Lw_u^H (stage II) or sqrt(alpha_u) I (stage I) on the
+        // own users' diagonal blocks
         for (int e = tid; e < nsd * nc; e += AMMSE_BLOCK) {
           const int i = e / nc, j = e - (e / nc) * nc;
           const int u = i / d, s_ = i - u * d, ul = u - u0, t_ = j - (j / d) * d;
           zd z = {0.0, 0.0};
           if (ul >= 0 && ul < sm.cu[c] && j / d == ul)
-            z = scal(sqrt(sm.alpha[u]), cj(Lwm[u * 16 + t_ * 4 + s_]));
+            z = stage2 ? scal(sqrt(sm.alpha[u]), cj(Lwm[u * 16 + t_ * 4 + s_]))
+                       : zd{(s_ == t_) ? sqrt(sm.alpha[u]) : 0.0, 0.0};
           Bm[e] = z;
         }
         __syncthreads();
@@ -669,7 +671,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
 
   int fsw = p.force_switch_iter;
   if (p.force_switch && p.force_switch[b] > 0) fsw = p.force_switch[b];
-  bool stage2 = wm || ((fsw >= 1) ? (fsw <= 1) : (p.warm_start == 0));
+  bool stage2 = p.algorithm == AMMSE_ALGO_WMMSE || ((fsw >= 1) ? (fsw <= 1) : (p.warm_start == 0));
   int switch_iter = stage2 ? 1 : -1;
   bool prev_step_stage2 = false;
   double wsr_prev = 0.0, wsr_prev2 = 0.0;   // WSR(V^{t-1}), WSR(V^{t-2})
@@ -711,8 +713,8 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     }
     weights(stage2);
 
-    if (wm) {   // Algorithm 2: exact V minimiser, then G^t
-      wmmse_step();
+    if (wm) {   // Algorithm 2 / MMMSE: exact V minimiser, then G^t
+      wmmse_step(stage2);
       {
         cx<R>* tmp = Gq;
         Gq = Gp;
@@ -720,7 +722,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       }
       channel_product(Gp, Xc, sm.scur, false);
       __syncthreads();
-      prev_step_stage2 = true;
+      prev_step_stage2 = stage2;
       iters_run = t;
       continue;
     }

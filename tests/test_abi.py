@@ -96,7 +96,7 @@ def test_validate_rejects_overlapping_precoders(L):
 @pytest.mark.parametrize("opt", [
     dict(precision=7), dict(max_iters=-1), dict(T_c=-1), dict(lanczos_steps=65),
     dict(force_switch_iter=0), dict(eps1=-0.1), dict(T_c=0), dict(eps2=float("nan")),
-    dict(path=2), dict(refine_iters=-1), dict(precision=3), dict(algorithm=2),
+    dict(path=2), dict(refine_iters=-1), dict(precision=3), dict(algorithm=3),
     dict(reserved=1),
 ])
 def test_validate_rejects_bad_options(L, opt):

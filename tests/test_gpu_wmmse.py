@@ -160,3 +160,44 @@ def test_fp32_rayleigh_sweep_subset_vs_oracle():
         np.testing.assert_allclose(g[:m + 1], ref["trace"][:m + 1], rtol=1e-4, err_msg=str(i))
         if over.size == 0:
             assert abs(res.wsr[k] - ref["wsr"]) <= 1e-4 * ref["wsr"], i
+
+
+# ---------------------------------------------------------------------------
+# MMMSE (Section V-B): sum-MSE stage (W = I) then WMMSE, same V solver
+# ---------------------------------------------------------------------------
+
+def mm_opts(**kw):
+    base = dict(algorithm=ammse.ALGO_MMMSE, precision=ammse.PREC_FP64, max_iters=500, eps1=0.1,
+                eps2=1e-6)
+    base.update(kw)
+    return ammse.Options(**base)
+
+
+def test_fp64_mmmse_single_small_matches_oracle():
+    b = synth.single_small()
+    inst = b.instance(0)
+    prob = O.from_instance(inst)
+    ref = O.mmmse(prob, O.split_v(prob, inst["V0"]), max_iters=200, eps1=0.1, eps2=1e-6)
+    res = ammse.solve(b, mm_opts(max_iters=200), want_trace=True)
+    say("mmmse single small: oracle switch", ref["switch_iter"], "iters", ref["iters"],
+        "gpu", res.switch_iter[0], res.iters[0])
+    assert res.status[0] == 0
+    assert res.switch_iter[0] == ref["switch_iter"] and res.iters[0] == ref["iters"]
+    np.testing.assert_allclose(res.trace[0][:ref["iters"] + 1], ref["trace"], rtol=1e-9)
+
+
+def test_fp64_mmmse_ragged_multicell():
+    b = _ragged()
+    T = 25
+    for i in range(b.batch):
+        if b.P[b.bs_off[i]:b.bs_off[i] + b.instance(i)["C"]].sum() == 0.0:
+            continue
+        inst = b.instance(i)
+        prob = O.from_instance(inst)
+        ref = O.mmmse(prob, O.split_v(prob, inst["V0"]), max_iters=T, eps1=0.1, eps2=0.0)
+        fs = np.array([ref["switch_iter"] if ref["switch_iter"] >= 1 else T + 1], np.int32)
+        res = ammse.solve(b.subset([i]), mm_opts(max_iters=T, eps2=0.0), want_trace=True,
+                          force_switch=fs)
+        say("mmmse ragged", i, "switch", ref["switch_iter"], "final", ref["wsr"], res.wsr[0])
+        assert res.status[0] == 0
+        np.testing.assert_allclose(res.trace[0], ref["trace"], rtol=1e-9, err_msg=str(i))

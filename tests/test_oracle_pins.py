@@ -469,3 +469,50 @@ def test_wmmse_subproblem_optimality():
         Y = Vn + 0.05 * (rng.standard_normal(Vn.shape) + 1j * rng.standard_normal(Vn.shape))
         Y = O.project_spc(prob, Y)
         assert O.objective_f(prob, Uu, Wu, Y) >= f0 - 1e-9
+
+
+# ---------------------------------------------------------------------------
+# MMMSE (Section V-B)
+# ---------------------------------------------------------------------------
+
+def _sum_mse(prob, V):
+    """sum_u alpha_u Tr(E_u) at the MMSE receivers of V (the stage-I objective),
+    E_u from the general MSE definition."""
+    Uu = O.mmse_receivers(prob, V)
+    E = O.mse_matrices(prob, Uu, V)
+    return float(sum(prob.alpha[u] * np.trace(E[u]).real for u in range(prob.U)))
+
+
+@pytest.mark.parametrize("cells", [[4], [2, 3]])
+def test_mmmse_stage1_is_descent_on_sum_mse(cells):
+    """Block coordinate descent on the sum-MSE problem: with the switch never
+    taken, sum alpha Tr(E) at the MMSE receivers does not increase."""
+    inst = random_instance(51, M=8, cell_users=cells, N=2, d=2, P=10.0, alpha_range=(0.5, 1.5))
+    prob, V0 = _prob(inst)
+    vals = [_sum_mse(prob, V0)]
+    for t in range(1, 9):
+        r = O.mmmse(prob, V0, max_iters=t, eps1=-1.0, eps2=0.0)
+        assert r["switch_iter"] == -1
+        vals.append(_sum_mse(prob, r["V"]))
+    assert np.all(np.diff(vals) <= 1e-10 * np.abs(vals[1:]))
+    assert vals[-1] < vals[0]
+
+
+def test_mmmse_with_immediate_switch_is_wmmse():
+    inst = random_instance(52, M=8, cell_users=[2, 2], N=2, d=2, P=10.0, alpha_range=(0.5, 1.5))
+    prob, V0 = _prob(inst)
+    a = O.mmmse(prob, V0, max_iters=30, eps2=0.0, force_switch_iter=1)
+    b = O.wmmse(prob, V0, max_iters=30, eps=-1.0)
+    np.testing.assert_allclose(a["trace"], b["trace"], rtol=1e-13)
+
+
+def test_mmmse_switch_rule_and_stage2_monotone():
+    inst = random_instance(53, M=8, cell_users=[4], N=2, d=2, P=30.0, alpha_range=(0.5, 1.5))
+    prob, V0 = _prob(inst)
+    r = O.mmmse(prob, V0, max_iters=80, eps1=0.1, eps2=0.0)
+    s, tr = r["switch_iter"], r["trace"]
+    assert s >= 2
+    rel = lambda a, b: abs(a - b) / b
+    assert rel(tr[s - 1], tr[s - 2]) <= 0.1
+    assert all(rel(tr[t - 1], tr[t - 2]) > 0.1 for t in range(2, s))
+    assert np.all(np.diff(tr[s:]) >= -1e-9 * tr[s + 1:])
