@@ -289,6 +289,48 @@ def early_exit(batch, ref, eps_list=(1e-3, 1e-4, 1e-5)):
     return out
 
 
+def profile_leg(name: str, reps: int) -> int:
+    """Launch one workload `reps` times and print its kernel times: the
+    seven-cell uneven batch (4096 instances, FP32, 100 iterations), the M=256
+    batch in float or bfloat16 mode, GPU WMMSE on the benchmark batch, or the
+    unrolled forward + adjoint."""
+    import torch
+    from paper_2510_20507_amd import ammse, synth
+    if name == "unrolled":
+        print(json.dumps(unrolled_leg(reps=reps)), flush=True)
+        return 0
+    if name == "hexcell":
+        batch = synth.hexcell_batch(4096)
+        opts = ammse.Options(precision=ammse.PREC_FP32, max_iters=ITERS)
+    elif name.startswith("large"):
+        batch = synth.rayleigh_large(512)
+        opts = ammse.Options(precision=ammse.PREC_BF16 if name == "large_bf16" else
+                             ammse.PREC_FP32, max_iters=ITERS)
+    else:
+        batch = synth.rayleigh_sweep(B_per_p=256)
+        opts = ammse.Options(precision=ammse.PREC_FP32, algorithm=ammse.ALGO_WMMSE,
+                             max_iters=500, eps2=1e-6)
+    db = ammse.to_device(batch, opts.precision)
+    plan = ammse.Plan(db.table, db.cell_users, opts)
+    ws = plan.workspace()
+    V = torch.empty_like(db.V0)
+    wsr = torch.empty(batch.batch, dtype=torch.float64, device="cuda")
+    flops = float(batch.total_flops_per_iter().sum()) * opts.max_iters
+    for r in range(reps):
+        V.copy_(db.V0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.solve(db.H, db.sigma2, db.alpha, db.P, V, wsr, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        print(json.dumps({"leg": name, "workload": batch.name, "rep": r, "kernel_ms": ms,
+                          "algorithmic_tflops": flops / (ms / 1e3) / 1e12}), flush=True)
+    plan.close()
+    return 0
+
+
 def parse_pmc(dirs):
     """Sum FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the solve kernel and of
     the calibration copy from rocprofv3 --pmc CSV output directories."""
@@ -343,11 +385,16 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help=f"also run a {CALIB_COPY_MIB} MiB device copy (counter calibration)")
     ap.add_argument("--parse-pmc", nargs="+", metavar="DIR")
+    ap.add_argument("--profile-leg", choices=["hexcell", "large_fp32", "large_bf16", "wmmse",
+                                              "unrolled"],
+                    help="run only one other workload's launches (for rocprofv3) and exit")
     a = ap.parse_args()
 
     if a.parse_pmc:
         print(json.dumps(parse_pmc(a.parse_pmc), indent=1))
         return 0
+    if a.profile_leg:
+        return profile_leg(a.profile_leg, a.steps)
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); instances "
               "are independent, so a multi-GPU run would shard the batch with no communication.",

@@ -59,6 +59,8 @@ struct ammse_kparams_t {
   int32_t wsr_only;      // 1: evaluate WSR(V) and return (no iteration, V not written)
   int32_t trace_len;     // max_iters + 1
   int32_t algorithm;     // AMMSE_ALGO_*
+  int32_t lds_factor;    // exact V step: dynamic LDS holds a <= 64 x 64 Cholesky factor
+                         // (1) and also the solution block (2)
   int32_t lowp_iters;    // BF16 mode: iterations 1..lowp_iters use bfloat16 products
                          // (and G^0 when lowp_iters >= 1); -1: float products only
   double eps1, eps2, gamma_c;

@@ -23,6 +23,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 #include "ammse_internal.h"
 
 #include "ammse_device.h"
@@ -60,6 +62,7 @@ template <class R>
 __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_solve_kernel(
     ammse_kparams_t p) {
   __shared__ Smem<R> sm;
+  extern __shared__ __align__(16) char dyn_lds[];   // WMMSE / MMMSE: Cholesky factor
   const ammse_desc_t D = p.desc[blockIdx.x];
   const int tid = threadIdx.x;
   const int C = D.C, U = D.U, M = D.M, N = D.N, d = D.d, un = D.un;
@@ -398,17 +401,19 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   // one.  Otherwise A_c (M x M, generically nonsingular) is factorised.
   // The root is found by safeguarded Newton steps on 1/||V_c(mu)|| inside a
   // bisection bracket; the factorisations and solves are in double.
-  // Lm = Cholesky factor (lower) of Am + mu I (n x n); false when not positive definite.
-  auto wm_chol = [&](int n, double mu_) -> bool {
+  // Lm = Cholesky factor (lower) of Am + mu I (n x n); false when not positive
+  // definite.  Lm and the solution block Y below live in LDS or in global
+  // memory; the helpers are inlined into one copy of the solve per case, so
+  // each access uses its own address space.
+  auto wm_chol = [&](int n, double mu_, auto* Lm) __attribute__((always_inline)) -> bool {
     const int tid = phase_tid();
-    for (int e = tid; e < n * n; e += AMMSE_BLOCK) {
-      const int i = e / n, j = e - i * n;
-      if (j <= i) {
-        zd a = Am[e];
+    const int tx = tid & 15, ty = tid >> 4;
+    for (int i = ty; i < n; i += 16)
+      for (int j = tx; j <= i; j += 16) {
+        zd a = Am[i * n + j];
         if (i == j) a = {a.x + mu_, 0.0};
-        Lm[e] = a;
+        Lm[i * n + j] = a;
       }
-    }
     __syncthreads();
     for (int k = 0; k < n; ++k) {
       const double dkk = Lm[k * n + k].x;
@@ -420,10 +425,10 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       for (int i = k + 1 + tid; i < n; i += AMMSE_BLOCK) Lm[i * n + k] = scal(il, Lm[i * n + k]);
       __syncthreads();
       if (tid == 0) Lm[k * n + k] = {lkk, 0.0};
-      const int w = n - k - 1;
-      for (int e = tid; e < w * w; e += AMMSE_BLOCK) {
-        const int i = k + 1 + e / w, j = k + 1 + (e - (e / w) * w);
-        if (j <= i) Lm[i * n + j] = Lm[i * n + j] - mulc(Lm[i * n + k], Lm[j * n + k]);
+      for (int i = k + 1 + ty; i < n; i += 16) {
+        const zd lik = Lm[i * n + k];
+        for (int j = k + 1 + tx; j <= i; j += 16)
+          Lm[i * n + j] = Lm[i * n + j] - mulc(lik, Lm[j * n + k]);
       }
       __syncthreads();
     }
@@ -433,7 +438,8 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   // threads per column, thread q of a column owning the rows i = q (mod 4);
   // the partial sums meet by shuffles, so no barrier is needed inside.
   // Y <- L^{-1} Y (conjT = false) or L^{-H} Y (conjT = true), in place.
-  auto wm_trsm = [&](zd* Y, int n, int nc, bool conjT) {
+  auto wm_trsm = [&](auto* Y, int n, int nc, bool conjT, const auto* Lm)
+      __attribute__((always_inline)) {
     const int tid = phase_tid();
     const int q = tid & 3;
     for (int j0 = 0; j0 < nc; j0 += AMMSE_BLOCK / 4) {
@@ -444,8 +450,10 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
         const int k = conjT ? n - 1 - s : s;
         zd part = {0.0, 0.0};
         if (!conjT) {
+#pragma unroll 4
           for (int i = q; i < k; i += 4) part = part + Lm[k * n + i] * Y[i * nc + jj];
         } else {
+#pragma unroll 4
           for (int i = k + 1 + ((q - (k + 1)) & 3); i < n; i += 4)
             part = part + cj(Lm[i * n + k]) * Y[i * nc + jj];
         }
@@ -459,34 +467,42 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     }
     __syncthreads();
   };
-  auto wm_norm2 = [&](const zd* Y, int n) {
+  auto wm_norm2 = [&](const auto* Y, int n) __attribute__((always_inline)) {
     const int tid = phase_tid();
     double v = 0.0;
     for (int e = tid; e < n; e += AMMSE_BLOCK) v += nrm2(Y[e]);
     return block_sum(v, sm.red);
   };
-  // Probe mu: X = (Am + mu I)^{-1} Bm (n x nc) and q = ||V(mu)||^2 with
-  // V = X (antenna space) or V = R^H X (stream space; formed explicitly, as
-  // shorter expressions cancel catastrophically once a stream is switched off
-  // and K is singular).  Returns false if Am + mu I is not positive definite.
-  auto wm_probe = [&](int n, int nc, bool sspace, double mu_, double& q) -> bool {
+  // Probe mu: X = (Am + mu I)^{-1} Bm (n x nc) and q = ||V(mu)||^2 with V = X
+  // (antenna space) or V = R^H X (stream space).  In stream space
+  // ||V||^2 = ||L^{-1} Z||^2 - mu ||X||^2 is used when its rounding error
+  // (about 1e-16 of the two terms) is below 1e-11 of the result; otherwise
+  // (a switched-off stream makes K singular and mu tiny) V is formed.
+  // Returns false if Am + mu I is not positive definite.
+  auto wm_probe = [&](int n, int nc, bool sspace, double mu_, double& q, auto* Lf, auto* Xf)
+      __attribute__((always_inline)) -> bool {
     const int tid = phase_tid();
-    if (!wm_chol(n, mu_)) return false;
-    for (int e = tid; e < n * nc; e += AMMSE_BLOCK) Xm[e] = Bm[e];
+    if (!wm_chol(n, mu_, Lf)) return false;
+    for (int e = tid; e < n * nc; e += AMMSE_BLOCK) Xf[e] = Bm[e];
     __syncthreads();
-    wm_trsm(Xm, n, nc, false);
-    wm_trsm(Xm, n, nc, true);
-    if (sspace) {
+    wm_trsm(Xf, n, nc, false, Lf);
+    const double yy = sspace ? wm_norm2(Xf, n * nc) : 0.0;
+    wm_trsm(Xf, n, nc, true, Lf);
+    const double xx = wm_norm2(Xf, n * nc);
+    if (!sspace) {
+      q = xx;
+    } else if (yy - mu_ * xx > 1e-5 * (yy + mu_ * xx)) {
+      q = yy - mu_ * xx;
+    } else {
       double v = 0.0;
       for (int e = tid; e < M * nc; e += AMMSE_BLOCK) {
         const int m = e / nc, j = e - m * nc;
         zd acc = {0.0, 0.0};
-        for (int k = 0; k < n; ++k) acc = acc + cj(Tm[(long)k * M + m]) * Xm[k * nc + j];
+#pragma unroll 4
+        for (int k = 0; k < n; ++k) acc = acc + cj(Tm[(long)k * M + m]) * Xf[k * nc + j];
         v += nrm2(acc);
       }
       q = block_sum(v, sm.red);
-    } else {
-      q = wm_norm2(Xm, n * nc);
     }
     return true;
   };
@@ -579,73 +595,92 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
         }
       }
       __syncthreads();
-      const double Pc = sm.Pc[c];
-      double q = 0.0;
-      if (!(Pc > 0.0)) {
-        for (int e = tid; e < n * nc; e += AMMSE_BLOCK) Xm[e] = {0.0, 0.0};
-        __syncthreads();
-      } else {
-        // Root of phi(mu) = 1/||V(mu)|| - 1/sqrt(P) (increasing, nearly linear
-        // in mu) by secant steps through the last two probes, kept inside the
-        // bracket [lo, hi]; bisection (geometric once lo > 0) when a step
-        // leaves the bracket or the bracket stops halving.
-        const double sP = sqrt(Pc);
-        bool ok = wm_probe(n, nc, sspace, 0.0, q);
-        double mu_ = 0.0;
-        if (!ok || q > Pc) {
-          double lo = 0.0, hi;
-          if (sspace) {
-            // ||B_c||^2 = ||R^H Z||^2 <= ||K||_F ||Z||_F^2 and ||V(mu)|| <= ||B_c|| / mu
-            hi = sqrt(sqrt(wm_norm2(Am, n * n)) * wm_norm2(Bm, n * nc) / Pc);
-          } else {
-            hi = sqrt(wm_norm2(Bm, n * nc) / Pc);
-          }
-          bool have_a = ok && q > 0.0;
-          double mu_a = 0.0, ph_a = have_a ? 1.0 / sqrt(q) - 1.0 / sP : 0.0;
-          double next = (sm.mu[c] > 0.0 && sm.mu[c] < hi) ? sm.mu[c] : 0.5 * hi;
-          double wref = hi - lo;
-          int since = 0;
-          for (int probe = 0; probe < 100; ++probe) {
-            double mid = (lo > 0.0) ? sqrt(lo * hi) : 0.5 * (lo + hi);
-            if (!(next > lo && next < hi)) next = mid;
-            mu_ = next;
-            ok = wm_probe(n, nc, sspace, mu_, q);
-            if (!ok) {
-              lo = mu_;
-              next = sqrt(lo * hi);
-              have_a = false;
-              continue;
-            }
-            if (q > Pc) lo = mu_;
-            else hi = mu_;
-            if (fabs(sqrt(q) - sP) <= 1e-13 * sP || hi - lo <= 1e-13 * hi) break;
-            const double ph = (q > 0.0) ? 1.0 / sqrt(q) - 1.0 / sP : 1e300;
-            mid = (lo > 0.0) ? sqrt(lo * hi) : 0.5 * (lo + hi);
-            next = (have_a && ph != ph_a) ? mu_ - ph * (mu_ - mu_a) / (ph - ph_a) : mid;
-            have_a = true;
-            mu_a = mu_;
-            ph_a = ph;
-            if (++since >= 3) {
-              if (hi - lo > 0.5 * wref) next = mid;
-              wref = hi - lo;
-              since = 0;
-            }
-          }
-          if (!ok) atomicOr(&sm.fail, AMMSE_INST_CHOLESKY);
+      // where=0: factor and solution in LDS, 1: factor in LDS, 2: both global
+      auto solve_with = [&](auto where) __attribute__((always_inline)) {
+        zd* Lf;
+        zd* Xf;
+        if constexpr (decltype(where)::value == 0) {
+          Lf = (zd*)dyn_lds;
+          Xf = (zd*)dyn_lds + 64 * 64;
+        } else if constexpr (decltype(where)::value == 1) {
+          Lf = (zd*)dyn_lds;
+          Xf = Xm;
+        } else {
+          Lf = Lm;
+          Xf = Xm;
         }
-        if (tid == 0) sm.mu[c] = mu_;
-      }
-      cx<R>* Vc = Xc + (long)M * sm.colOff[c];
-      if (sspace) {   // V_c = R^H X
-        for (int e = tid; e < M * nc; e += AMMSE_BLOCK) {
-          const int m = e / nc, j = e - m * nc;
-          zd acc = {0.0, 0.0};
-          for (int k = 0; k < nsd; ++k) acc = acc + cj(Tm[(long)k * M + m]) * Xm[k * nc + j];
-          Vc[e] = from_d<R>(acc);
+        const double Pc = sm.Pc[c];
+        double q = 0.0;
+        if (!(Pc > 0.0)) {
+          for (int e = tid; e < n * nc; e += AMMSE_BLOCK) Xf[e] = {0.0, 0.0};
+          __syncthreads();
+        } else {
+          // Root of phi(mu) = 1/||V(mu)|| - 1/sqrt(P) (increasing, nearly linear
+          // in mu) by secant steps through the last two probes, kept inside the
+          // bracket [lo, hi]; bisection (geometric once lo > 0) when a step
+          // leaves the bracket or the bracket stops halving.
+          const double sP = sqrt(Pc);
+          bool ok = wm_probe(n, nc, sspace, 0.0, q, Lf, Xf);
+          double mu_ = 0.0;
+          if (!ok || q > Pc) {
+            double lo = 0.0, hi;
+            if (sspace) {
+              // ||B_c||^2 = ||R^H Z||^2 <= ||K||_F ||Z||_F^2 and ||V(mu)|| <= ||B_c|| / mu
+              hi = sqrt(sqrt(wm_norm2(Am, n * n)) * wm_norm2(Bm, n * nc) / Pc);
+            } else {
+              hi = sqrt(wm_norm2(Bm, n * nc) / Pc);
+            }
+            bool have_a = ok && q > 0.0;
+            double mu_a = 0.0, ph_a = have_a ? 1.0 / sqrt(q) - 1.0 / sP : 0.0;
+            double next = (sm.mu[c] > 0.0 && sm.mu[c] < hi) ? sm.mu[c] : 0.5 * hi;
+            double wref = hi - lo;
+            int since = 0;
+            for (int probe = 0; probe < 100; ++probe) {
+              double mid = (lo > 0.0) ? sqrt(lo * hi) : 0.5 * (lo + hi);
+              if (!(next > lo && next < hi)) next = mid;
+              mu_ = next;
+              ok = wm_probe(n, nc, sspace, mu_, q, Lf, Xf);
+              if (!ok) {
+                lo = mu_;
+                next = sqrt(lo * hi);
+                have_a = false;
+                continue;
+              }
+              if (q > Pc) lo = mu_;
+              else hi = mu_;
+              if (fabs(sqrt(q) - sP) <= 1e-13 * sP || hi - lo <= 1e-13 * hi) break;
+              const double ph = (q > 0.0) ? 1.0 / sqrt(q) - 1.0 / sP : 1e300;
+              mid = (lo > 0.0) ? sqrt(lo * hi) : 0.5 * (lo + hi);
+              next = (have_a && ph != ph_a) ? mu_ - ph * (mu_ - mu_a) / (ph - ph_a) : mid;
+              have_a = true;
+              mu_a = mu_;
+              ph_a = ph;
+              if (++since >= 3) {
+                if (hi - lo > 0.5 * wref) next = mid;
+                wref = hi - lo;
+                since = 0;
+              }
+            }
+            if (!ok) atomicOr(&sm.fail, AMMSE_INST_CHOLESKY);
+          }
+          if (tid == 0) sm.mu[c] = mu_;
         }
-      } else {
-        for (int e = tid; e < M * nc; e += AMMSE_BLOCK) Vc[e] = from_d<R>(Xm[e]);
-      }
+        cx<R>* Vc = Xc + (long)M * sm.colOff[c];
+        if (sspace) {   // V_c = R^H X
+          for (int e = tid; e < M * nc; e += AMMSE_BLOCK) {
+            const int m = e / nc, j = e - m * nc;
+            zd acc = {0.0, 0.0};
+  #pragma unroll 4
+            for (int k = 0; k < nsd; ++k) acc = acc + cj(Tm[(long)k * M + m]) * Xf[k * nc + j];
+            Vc[e] = from_d<R>(acc);
+          }
+        } else {
+          for (int e = tid; e < M * nc; e += AMMSE_BLOCK) Vc[e] = from_d<R>(Xf[e]);
+        }
+      };
+      if (p.lds_factor >= 2 && n <= 64 && nc <= 64) solve_with(std::integral_constant<int, 0>{});
+      else if (p.lds_factor >= 1 && n <= 64) solve_with(std::integral_constant<int, 1>{});
+      else solve_with(std::integral_constant<int, 2>{});
       __syncthreads();
     }
   };
@@ -876,12 +911,33 @@ size_t ammse_general_lds_bytes(int precision) {
   return precision == AMMSE_PREC_FP64 ? sizeof(Smem<double>) : sizeof(Smem<float>);
 }
 
-hipError_t ammse_launch_fp64(const ammse_kparams_t& p, hipStream_t s) {
-  hipLaunchKernelGGL(ammse_solve_kernel<double>, dim3(p.batch), dim3(AMMSE_BLOCK), 0, s, p);
+// Exact-V-step algorithms get 64 KiB of dynamic LDS for a factor of order <= 64.
+template <class R>
+hipError_t launch_general(const ammse_kparams_t& p0, hipStream_t s) {
+  ammse_kparams_t p = p0;
+  size_t dyn = 0;
+  if (p.algorithm != AMMSE_ALGO_AMMMSE) {
+    static bool attr_set = false;
+    // FP32: factor and solution block (128 KiB); FP64 (larger static tiles): factor only
+    dyn = sizeof(zd) * 64 * 64 * (sizeof(R) == 4 ? 2 : 1);
+    if (!attr_set) {
+      hipError_t e = hipFuncSetAttribute((const void*)ammse_solve_kernel<R>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+      if (e != hipSuccess) return e;
+      attr_set = true;
+    }
+    p.lds_factor = sizeof(R) == 4 ? 2 : 1;
+  } else {
+    p.lds_factor = 0;
+  }
+  hipLaunchKernelGGL(ammse_solve_kernel<R>, dim3(p.batch), dim3(AMMSE_BLOCK), dyn, s, p);
   return hipGetLastError();
 }
 
+hipError_t ammse_launch_fp64(const ammse_kparams_t& p, hipStream_t s) {
+  return launch_general<double>(p, s);
+}
+
 hipError_t ammse_launch_fp32(const ammse_kparams_t& p, hipStream_t s) {
-  hipLaunchKernelGGL(ammse_solve_kernel<float>, dim3(p.batch), dim3(AMMSE_BLOCK), 0, s, p);
-  return hipGetLastError();
+  return launch_general<float>(p, s);
 }
