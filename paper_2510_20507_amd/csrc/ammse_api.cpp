@@ -205,7 +205,8 @@ ammse_status_t ammse_plan_create(ammse_plan_t* plan, int32_t device,
     d.bs_off = t.bs_off;
     d.ws_off = (int64_t)off;
     if (!fast)
-      off += ammse_ws_layout(rb, t.U, t.M, t.N, t.d, ls, o.algorithm != AMMSE_ALGO_AMMMSE).total;
+      off += ammse_ws_layout(rb, t.C, t.U, t.M, t.N, t.d, ls, o.algorithm != AMMSE_ALGO_AMMMSE)
+                 .total;
   }
 
   ammse_plan_s* P = new (std::nothrow) ammse_plan_s();

@@ -28,7 +28,9 @@ struct ammse_ws_layout_t {
                               // double complex; empty for Algorithm 3
   size_t Tm;                  // WMMSE: S D S H_{:,c} or R = C^H S H_{:,c} ((U N) x M,
                               // double complex)
-  size_t Lwm, Lim, Cm;        // WMMSE: per-user Lw, Lw^{-1}, C (double complex 4 x 4)
+  size_t Qm;                  // S H H^H S ((U N) x (U N), storage precision), see below
+  size_t Lwm, Lim, Cm;        // per-user Lw, Lw^{-1}, C (double complex 4 x 4): WMMSE,
+                              // and Lw^{-1}, C for the Q-based Lanczos
   size_t total;
 };
 
@@ -74,8 +76,8 @@ struct ammse_kparams_t {
 // starts on a 256-byte boundary.
 __host__ __device__ inline size_t ammse_align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-__host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int U, int M, int N,
-                                                             int d, int lanczos_steps,
+__host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int C, int U, int M,
+                                                             int N, int d, int lanczos_steps,
                                                              bool wmmse) {
   const size_t cs = 2 * (size_t)real_bytes;      // storage complex
   const size_t zs = 16;                          // double complex
@@ -100,9 +102,12 @@ __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int
   L.Bm = o;  o += ammse_align256(w * (size_t)M * ud * zs);
   L.Xm = o;  o += ammse_align256(w * (size_t)M * ud * zs);
   L.Tm = o;  o += ammse_align256(w * un * (size_t)M * zs);
+  // Algorithm 3, single cell with U N <= M: Lanczos on Q = S H H^H S
+  const size_t qp = (!wmmse && C == 1 && un <= (size_t)M) ? 1 : 0;
+  L.Qm = o;  o += ammse_align256(qp * un * un * cs);
   L.Lwm = o; o += ammse_align256(w * (size_t)U * 16 * zs);
-  L.Lim = o; o += ammse_align256(w * (size_t)U * 16 * zs);
-  L.Cm = o;  o += ammse_align256(w * (size_t)U * 16 * zs);
+  L.Lim = o; o += ammse_align256((w | qp) * (size_t)U * 16 * zs);
+  L.Cm = o;  o += ammse_align256((w | qp) * (size_t)U * 16 * zs);
   L.total = o;
   return L;
 }

@@ -93,7 +93,8 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   __syncthreads();
 
   const bool wm = p.algorithm != AMMSE_ALGO_AMMMSE;   // exact V step (Algorithm 2 / MMMSE)
-  const ammse_ws_layout_t L = ammse_ws_layout((int)sizeof(R), U, M, N, d, p.lanczos_steps, wm);
+  const bool qpath = C == 1 && un <= M && !wm;   // stream-space Lanczos with Q = S H H^H S
+  const ammse_ws_layout_t L = ammse_ws_layout((int)sizeof(R), C, U, M, N, d, p.lanczos_steps, wm);
   char* ws = p.ws + D.ws_off;
   cx<R>* Gp = (cx<R>*)(ws + L.Gp);
   cx<R>* Gq = (cx<R>*)(ws + L.Gq);
@@ -112,6 +113,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   zd* Bm = (zd*)(ws + L.Bm);
   zd* Xm = (zd*)(ws + L.Xm);
   zd* Tm = (zd*)(ws + L.Tm);
+  cx<R>* Qm = (cx<R>*)(ws + L.Qm);
   zd* Lwm = (zd*)(ws + L.Lwm);
   zd* Lim = (zd*)(ws + L.Lim);
   zd* Cm = (zd*)(ws + L.Cm);
@@ -209,10 +211,8 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
         if (ea == eb) rsum += sm.alpha[u] * 2.0 * log(Lw.x);
         UWm[u * 16 + li] = UWv;
         Em[u * 16 + li] = Ev;
-        if (wm) {
-          Lwm[u * 16 + li] = Lw;
-          Lim[u * 16 + li] = Li;
-        }
+        if (wm) Lwm[u * 16 + li] = Lw;
+        if (wm || qpath) Lim[u * 16 + li] = Li;
         ok = ok && oku;
       }
     }
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
         Dm[u * 16 + li] = scal(al, Dv);
         Ym[u * 16 + li] = scal(al, Ur);
       }
-      if (wm) {   // D = C C^H: C = sqrt(alpha) UW Lw^{-H} (stage II) or sqrt(alpha) U (stage I)
+      if (wm || qpath) {   // D = C C^H: C = sqrt(alpha) UW Lw^{-H} (stage II) or sqrt(alpha) U (stage I)
         const zd Cv = scal(sqrt(al), stage2 ? mm_nh(L4, UWv, Lim[uu * 16 + li]) : T);
         if (act) Cm[u * 16 + li] = Cv;
       }
@@ -258,79 +258,44 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   // wave, combined by shuffles); the three inner products of a step are
   // reduced together.  FP64 forms ||w - alpha q - beta p|| explicitly, FP32
   // uses beta^2 = ||w||^2 - alpha^2 - 2 beta_prev Re(p^H w) + beta_prev^2.
-  auto lanczos_lmax = [&](int c) {
+  // Plain three-term Lanczos for the largest eigenvalue of a Hermitian PSD
+  // operator of order nl (the largest Ritz value converges without
+  // re-orthogonalisation).  apply(q, w) writes w = Op q (vectors in the
+  // workspace).  FP64 forms ||w - alpha q - beta p|| explicitly, FP32 uses
+  // beta^2 = ||w||^2 - alpha^2 - 2 beta_prev Re(p^H w) + beta_prev^2.
+  auto lanczos_core = [&](int nl, auto&& apply) __attribute__((always_inline)) {
     const int tid = phase_tid();
-    const cx<R>* __restrict__ Hc = H + (long)c * un * M;
     zd* qv = Lq;
-    zd* pv = Lq + M;
-    zd* wv = Lq + 2 * M;
-    // 16 consecutive threads per row of H (coalesced), fewer for short rows
-    int tpr = 16;
-    while (tpr > 1 && tpr > M) tpr >>= 1;
-    int tpc = 1;
-    while (tpc < 64 && tpc * 2 * M <= AMMSE_BLOCK) tpc *= 2;
-    for (int i = tid; i < M; i += AMMSE_BLOCK) {
+    zd* pv = Lq + nl;
+    zd* wv = Lq + 2 * nl;
+    for (int i = tid; i < nl; i += AMMSE_BLOCK) {
       qv[i] = {1.0 + 0.5 * sin(0.731 * i + 0.25), 0.3 * cos(1.37 * i + 0.5)};
       pv[i] = {0.0, 0.0};
     }
     double nn = 0.0;
-    for (int i = tid; i < M; i += AMMSE_BLOCK) nn += nrm2(qv[i]);
+    for (int i = tid; i < nl; i += AMMSE_BLOCK) nn += nrm2(qv[i]);
     nn = block_sum(nn, sm.red);
-    for (int i = tid; i < M; i += AMMSE_BLOCK) qv[i] = scal(1.0 / sqrt(nn), qv[i]);
+    for (int i = tid; i < nl; i += AMMSE_BLOCK) qv[i] = scal(1.0 / sqrt(nn), qv[i]);
     __syncthreads();
-    const int m = min(p.lanczos_steps, M);
+    const int m = min(p.lanczos_steps, nl);
     constexpr bool exact_beta = sizeof(R) == 8;
     const double ltol = exact_beta ? 1e-14 : 1e-8;
     const double rtol = exact_beta ? 1e-16 : 1e-10;
     const int first = exact_beta ? 8 : 12, every = exact_beta ? 8 : 4;
     double beta_prev = 0.0, tmax = 0.0, theta = 0.0;
     for (int j = 0; j < m; ++j) {
-      {  // y1 = S H q
-        const int part = tid & (tpr - 1);
-        for (int r = tid / tpr; r < un; r += AMMSE_BLOCK / tpr) {
-          const cx<R>* __restrict__ hr = Hc + (long)r * M;
-          zd acc = {0.0, 0.0};
-#pragma unroll 4
-          for (int i = part; i < M; i += tpr) acc = acc + to_d(hr[i]) * qv[i];
-          for (int o = 1; o < tpr; o <<= 1) {
-            acc.x += __shfl_xor(acc.x, o, 64);
-            acc.y += __shfl_xor(acc.y, o, 64);
-          }
-          if (part == 0) Ly1[r] = scal(sm.invsig[r / N], acc);
-        }
-      }
-      __syncthreads();
-      for (int r = tid; r < un; r += AMMSE_BLOCK) {   // y2 = S D y1
-        const int u = r / N, n = r - u * N;
-        zd acc = {0.0, 0.0};
-        for (int k = 0; k < N; ++k) acc = acc + Dm[u * 16 + n * 4 + k] * Ly1[u * N + k];
-        Ly2[r] = scal(sm.invsig[u], acc);
-      }
+      apply(qv, wv);
       __syncthreads();
       double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-      {  // w = H^H y2 and the inner products
-        const int part = tid & (tpc - 1);
-        for (int i = tid / tpc; i < M; i += AMMSE_BLOCK / tpc) {
-          zd acc = {0.0, 0.0};
-#pragma unroll 4
-          for (int r = part; r < un; r += tpc) acc = acc + cj(to_d(Hc[(long)r * M + i])) * Ly2[r];
-          for (int o = 1; o < tpc; o <<= 1) {
-            acc.x += __shfl_xor(acc.x, o, 64);
-            acc.y += __shfl_xor(acc.y, o, 64);
-          }
-          if (part == 0) {
-            wv[i] = acc;
-            const zd q = qv[i], pp = pv[i];
-            s0 += nrm2(acc);
-            s1 += q.x * acc.x + q.y * acc.y;
-            s2 += pp.x * acc.x + pp.y * acc.y;
-          }
-        }
+      for (int i = tid; i < nl; i += AMMSE_BLOCK) {
+        const zd w = wv[i], q = qv[i], pp = pv[i];
+        s0 += nrm2(w);
+        s1 += q.x * w.x + q.y * w.y;
+        s2 += pp.x * w.x + pp.y * w.y;
       }
       s0 = wave_sum(s0);
       s1 = wave_sum(s1);
       s2 = wave_sum(s2);
-      __syncthreads();
       if ((tid & 63) == 0) {
         sm.red[(tid >> 6)] = s0;
         sm.red[4 + (tid >> 6)] = s1;
@@ -343,7 +308,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       double bb;
       if (exact_beta) {
         double nr = 0.0;
-        for (int i = tid; i < M; i += AMMSE_BLOCK) {
+        for (int i = tid; i < nl; i += AMMSE_BLOCK) {
           const zd w = wv[i] - scal(al, qv[i]) - scal(beta_prev, pv[i]);
           wv[i] = w;
           nr += nrm2(w);
@@ -369,7 +334,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       if (stop) break;
       __syncthreads();
       const double ib = 1.0 / bb;
-      for (int i = tid; i < M; i += AMMSE_BLOCK) {
+      for (int i = tid; i < nl; i += AMMSE_BLOCK) {
         const zd w = exact_beta ? wv[i] : wv[i] - scal(al, qv[i]) - scal(beta_prev, pv[i]);
         pv[i] = qv[i];
         qv[i] = scal(ib, w);
@@ -379,6 +344,84 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     }
     __syncthreads();
     return theta;
+  };
+
+  // lambda_max(A_c), A_c = H_c^H S D S H_c, on the M-dimensional operator:
+  // products with H use several threads per row / column (a power of two
+  // within one wave, combined by shuffles).
+  auto lanczos_lmax = [&](int c) {
+    const int tid = phase_tid();
+    const cx<R>* __restrict__ Hc = H + (long)c * un * M;
+    int tpr = 1;
+    while (tpr < 64 && tpr * 2 * un <= AMMSE_BLOCK) tpr *= 2;
+    int tpc = 1;
+    while (tpc < 64 && tpc * 2 * M <= AMMSE_BLOCK) tpc *= 2;
+    return lanczos_core(M, [&](const zd* qv, zd* wv) {
+      {  // y1 = S H q
+        const int part = tid & (tpr - 1);
+        for (int r = tid / tpr; r < un; r += AMMSE_BLOCK / tpr) {
+          const cx<R>* __restrict__ hr = Hc + (long)r * M;
+          zd acc = {0.0, 0.0};
+#pragma unroll 4
+          for (int i = part; i < M; i += tpr) acc = acc + to_d(hr[i]) * qv[i];
+          for (int o = 1; o < tpr; o <<= 1) {
+            acc.x += __shfl_xor(acc.x, o, 64);
+            acc.y += __shfl_xor(acc.y, o, 64);
+          }
+          if (part == 0) Ly1[r] = scal(sm.invsig[r / N], acc);
+        }
+      }
+      __syncthreads();
+      for (int r = tid; r < un; r += AMMSE_BLOCK) {   // y2 = S D y1
+        const int u = r / N, n = r - u * N;
+        zd acc = {0.0, 0.0};
+        for (int k = 0; k < N; ++k) acc = acc + Dm[u * 16 + n * 4 + k] * Ly1[u * N + k];
+        Ly2[r] = scal(sm.invsig[u], acc);
+      }
+      __syncthreads();
+      {  // w = H^H y2
+        const int part = tid & (tpc - 1);
+        for (int i = tid / tpc; i < M; i += AMMSE_BLOCK / tpc) {
+          zd acc = {0.0, 0.0};
+#pragma unroll 4
+          for (int r = part; r < un; r += tpc) acc = acc + cj(to_d(Hc[(long)r * M + i])) * Ly2[r];
+          for (int o = 1; o < tpc; o <<= 1) {
+            acc.x += __shfl_xor(acc.x, o, 64);
+            acc.y += __shfl_xor(acc.y, o, 64);
+          }
+          if (part == 0) wv[i] = acc;
+        }
+      }
+    });
+  };
+
+  // Single cell with U N <= M: the same lambda_max on the (U N)-dimensional
+  // operator K = C^H Q C, D = C C^H per user and Q = S H H^H S (formed once
+  // per solve), which reads Q once per step instead of H twice.
+  auto lanczos_q = [&]() {
+    const int tid = phase_tid();
+    return lanczos_core(un, [&](const zd* qv, zd* wv) {
+      for (int r = tid; r < un; r += AMMSE_BLOCK) {   // u = C x
+        const int u = r / N, n = r - u * N;
+        zd acc = {0.0, 0.0};
+        for (int k = 0; k < N; ++k) acc = acc + Cm[u * 16 + n * 4 + k] * qv[u * N + k];
+        Ly1[r] = acc;
+      }
+      __syncthreads();
+      for (int r = tid; r < un; r += AMMSE_BLOCK) {   // z = Q u (Q Hermitian: column r)
+        zd acc = {0.0, 0.0};
+#pragma unroll 8
+        for (int c2 = 0; c2 < un; ++c2) acc = acc + cj(to_d(Qm[(long)c2 * un + r])) * Ly1[c2];
+        Ly2[r] = acc;
+      }
+      __syncthreads();
+      for (int r = tid; r < un; r += AMMSE_BLOCK) {   // w = C^H z
+        const int u = r / N, n = r - u * N;
+        zd acc = {0.0, 0.0};
+        for (int k = 0; k < N; ++k) acc = acc + cj(Cm[u * 16 + k * 4 + n]) * Ly2[u * N + k];
+        wv[r] = acc;
+      }
+    });
   };
 
   // The iterate V^t is kept as scur_c * Xc (per BS c) and V^{t-1} as
@@ -692,6 +735,26 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     sm.mu[c] = 0.0;
   }
   __syncthreads();
+  if (qpath && !p.wsr_only) {   // Q = S H H^H S (float products), made exactly Hermitian
+    channel_gemm<R, false, true>(un, un, M, H, M, H, M, sm.tiles, false,
+                                 [&](int i, int j, cx<R> v) {
+                                   const R f = (R)(sm.invsig[i / N] * sm.invsig[j / N]);
+                                   Qm[(long)i * un + j] = {f * v.x, f * v.y};
+                                 });
+    __syncthreads();
+    for (int e = tid; e < un * un; e += AMMSE_BLOCK) {
+      const int i = e / un, j = e - i * un;
+      if (i < j) {
+        const cx<R> x = Qm[e], y = Qm[(long)j * un + i];
+        const cx<R> mm = {R(0.5) * (x.x + y.x), R(0.5) * (x.y - y.y)};
+        Qm[e] = mm;
+        Qm[(long)j * un + i] = {mm.x, -mm.y};
+      } else if (i == j) {
+        Qm[e].y = R(0);
+      }
+    }
+    __syncthreads();
+  }
   channel_product(Gp, Xc, sm.scur, p.lowp_iters >= 1);
   __syncthreads();
   const int T = p.wsr_only ? 0 : p.max_iters;
@@ -767,7 +830,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
                                          t < switch_iter + p.T_c);
     if (adaptive) {
       for (int c = 0; c < C; ++c) {
-        const double lm = (sm.cu[c] > 0) ? lanczos_lmax(c) : 0.0;
+        const double lm = (sm.cu[c] == 0) ? 0.0 : qpath ? lanczos_q() : lanczos_lmax(c);
         if (tid == 0) sm.gamma[c] = (lm > 0.0) ? 1.0 / (2.0 * lm) : 0.0;
         __syncthreads();
       }
