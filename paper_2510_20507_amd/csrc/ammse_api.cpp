@@ -205,7 +205,8 @@ ammse_status_t ammse_plan_create(ammse_plan_t* plan, int32_t device,
     d.bs_off = t.bs_off;
     d.ws_off = (int64_t)off;
     if (!fast)
-      off += ammse_ws_layout(rb, t.C, t.U, t.M, t.N, t.d, ls, o.algorithm != AMMSE_ALGO_AMMMSE)
+      off += ammse_ws_layout(rb, t.C, t.U, t.M, t.N, t.d, ls, o.algorithm != AMMSE_ALGO_AMMMSE,
+                             o.precision == AMMSE_PREC_BF16)
                  .total;
   }
 
@@ -301,6 +302,7 @@ static void fill_common(ammse_plan_t plan, ammse_kparams_t& k) {
   k.gamma_c = o.gamma_c;
   k.lowp_iters = (o.precision == AMMSE_PREC_BF16) ? std::max(0, o.max_iters - o.refine_iters) : -1;
   k.algorithm = o.algorithm;
+  k.bf16_copies = o.precision == AMMSE_PREC_BF16;
 }
 
 ammse_status_t ammse_solve(ammse_plan_t plan, const void* H, const double* sigma2,

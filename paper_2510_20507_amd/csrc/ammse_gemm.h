@@ -127,9 +127,19 @@ __device__ void block_gemm(int m, int n, int k, const cx<R>* __restrict__ A, lon
 // products so that their latency overlaps the MFMA work.  Each of the four
 // waves owns a 16-row strip of the 64 x 64 output tile; a complex product is
 // three real accumulators (Re Re, Im Im, Re Im + Im Re).
-template <class T, bool CONJA, bool CONJB, class Epi>
-__device__ void block_gemm_mfma(int m, int n, int k, const cx<float>* __restrict__ A, long lda,
-                                const cx<float>* __restrict__ B, long ldb, char* lds, Epi&& epi) {
+// Complex bfloat16 in memory (operand copies of the mixed-precision mode).
+struct alignas(4) bfc {   // one 32-bit word per complex element
+  __bf16 x, y;
+};
+__device__ __forceinline__ cx<float> to_f(const cx<float>& v) { return v; }
+__device__ __forceinline__ cx<float> to_f(const bfc& v) { return {(float)v.x, (float)v.y}; }
+__device__ __forceinline__ bfc to_bfc(const cx<float>& v) { return {(__bf16)v.x, (__bf16)v.y}; }
+
+// Operands are float or bfloat16 complex in memory (TA, TB); either way they
+// are converted to T on the way into LDS.
+template <class T, bool CONJA, bool CONJB, class Epi, class TA, class TB>
+__device__ void block_gemm_mfma(int m, int n, int k, const TA* __restrict__ A, long lda,
+                                const TB* __restrict__ B, long ldb, char* lds, Epi&& epi) {
   using Tl = MfmaTile<T>;
   constexpr int KC = Tl::KC, LD = Tl::LD, NA = Tl::NA, NB = Tl::NB;
   T* AsR = (T*)lds;
@@ -161,7 +171,8 @@ __device__ void block_gemm_mfma(int m, int n, int k, const cx<float>* __restrict
       kk = e / TN;
     }
   };
-  cx<float> ra[NA], rb[NB];
+  TA ra[NA];   // raw operand values: converted when stashed, so the
+  TB rb[NB];   // prefetch loads stay in flight during the products
   auto fetch = [&](int s) {
     const int tile = s / nk, k0 = (s - tile * nk) * KC;
     const int i0 = (tile / ntn) * TM, j0 = (tile % ntn) * TN;
@@ -170,7 +181,7 @@ __device__ void block_gemm_mfma(int m, int n, int k, const cx<float>* __restrict
       int row, kk;
       a_rk(q, row, kk);
       const int gi = i0 + row, gk = k0 + kk;
-      ra[q] = {0.f, 0.f};
+      ra[q] = TA{};
       if (gi < m && gk < k) ra[q] = CONJA ? A[(long)gk * lda + gi] : A[(long)gi * lda + gk];
     }
 #pragma unroll
@@ -178,8 +189,8 @@ __device__ void block_gemm_mfma(int m, int n, int k, const cx<float>* __restrict
       int col, kk;
       b_ck(q, col, kk);
       const int gj = j0 + col, gk = k0 + kk;
-      rb[q] = {0.f, 0.f};
-      if (gj < n && gk < k) rb[q] = CONJB ? cj(B[(long)gj * ldb + gk]) : B[(long)gk * ldb + gj];
+      rb[q] = TB{};
+      if (gj < n && gk < k) rb[q] = CONJB ? B[(long)gj * ldb + gk] : B[(long)gk * ldb + gj];
     }
   };
   floatx4_t P[4][3];
@@ -197,15 +208,17 @@ __device__ void block_gemm_mfma(int m, int n, int k, const cx<float>* __restrict
     for (int q = 0; q < NA; ++q) {
       int row, kk;
       a_rk(q, row, kk);
-      AsR[row * LD + kk] = (T)ra[q].x;
-      AsI[row * LD + kk] = (T)(CONJA ? -ra[q].y : ra[q].y);
+      const cx<float> va = to_f(ra[q]);
+      AsR[row * LD + kk] = (T)va.x;
+      AsI[row * LD + kk] = (T)(CONJA ? -va.y : va.y);
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       int col, kk;
       b_ck(q, col, kk);
-      BsR[col * LD + kk] = (T)rb[q].x;
-      BsI[col * LD + kk] = (T)rb[q].y;
+      const cx<float> vb = to_f(rb[q]);
+      BsR[col * LD + kk] = (T)vb.x;
+      BsI[col * LD + kk] = (T)(CONJB ? -vb.y : vb.y);
     }
     __syncthreads();
     if (s + 1 < steps) fetch(s + 1);
@@ -279,6 +292,13 @@ __device__ __forceinline__ void channel_gemm(int m, int n, int k, const cx<R>* A
     cx<R>* As = (cx<R>*)tiles;
     block_gemm<R, CONJA, CONJB>(m, n, k, A, lda, B, ldb, As, As + KC * (TM + 1), epi);
   }
+}
+
+// Mixed-precision products from bfloat16 copies of both operands.
+template <bool CONJA, class Epi>
+__device__ __forceinline__ void channel_gemm_bf16(int m, int n, int k, const bfc* A, long lda,
+                                                  const bfc* B, long ldb, char* tiles, Epi&& epi) {
+  block_gemm_mfma<__bf16, CONJA, false>(m, n, k, A, lda, B, ldb, tiles, epi);
 }
 
 }  // namespace ammse_dev

@@ -29,6 +29,7 @@ struct ammse_ws_layout_t {
   size_t Tm;                  // WMMSE: S D S H_{:,c} or R = C^H S H_{:,c} ((U N) x M,
                               // double complex)
   size_t Qm;                  // S H H^H S ((U N) x (U N), storage precision), see below
+  size_t Hb, Xb, Zb;          // bfloat16 copies of H, X and Z (mixed precision only)
   size_t Lwm, Lim, Cm;        // per-user Lw, Lw^{-1}, C (double complex 4 x 4): WMMSE,
                               // and Lw^{-1}, C for the Q-based Lanczos
   size_t total;
@@ -63,6 +64,7 @@ struct ammse_kparams_t {
   int32_t algorithm;     // AMMSE_ALGO_*
   int32_t lds_factor;    // exact V step: dynamic LDS holds a <= 64 x 64 Cholesky factor
                          // (1) and also the solution block (2)
+  int32_t bf16_copies;   // BF16 mode: the workspace holds bfloat16 operand copies
   int32_t lowp_iters;    // BF16 mode: iterations 1..lowp_iters use bfloat16 products
                          // (and G^0 when lowp_iters >= 1); -1: float products only
   double eps1, eps2, gamma_c;
@@ -78,7 +80,7 @@ __host__ __device__ inline size_t ammse_align256(size_t x) { return (x + 255) & 
 
 __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int C, int U, int M,
                                                              int N, int d, int lanczos_steps,
-                                                             bool wmmse) {
+                                                             bool wmmse, bool bf16 = false) {
   const size_t cs = 2 * (size_t)real_bytes;      // storage complex
   const size_t zs = 16;                          // double complex
   const size_t un = (size_t)U * N, ud = (size_t)U * d;
@@ -108,6 +110,11 @@ __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int
   L.Lwm = o; o += ammse_align256(w * (size_t)U * 16 * zs);
   L.Lim = o; o += ammse_align256((w | qp) * (size_t)U * 16 * zs);
   L.Cm = o;  o += ammse_align256((w | qp) * (size_t)U * 16 * zs);
+  // mixed precision: bfloat16 copies of H (all cells), of the precoder and of Z
+  const size_t bb = bf16 ? 4 : 0;
+  L.Hb = o;  o += ammse_align256(bb * (size_t)C * un * M);
+  L.Xb = o;  o += ammse_align256(bb * (size_t)M * ud);
+  L.Zb = o;  o += ammse_align256(bb * un * ud);
   L.total = o;
   return L;
 }

@@ -94,7 +94,8 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
 
   const bool wm = p.algorithm != AMMSE_ALGO_AMMMSE;   // exact V step (Algorithm 2 / MMMSE)
   const bool qpath = C == 1 && un <= M && !wm;   // stream-space Lanczos with Q = S H H^H S
-  const ammse_ws_layout_t L = ammse_ws_layout((int)sizeof(R), C, U, M, N, d, p.lanczos_steps, wm);
+  const ammse_ws_layout_t L =
+      ammse_ws_layout((int)sizeof(R), C, U, M, N, d, p.lanczos_steps, wm, p.bf16_copies != 0);
   char* ws = p.ws + D.ws_off;
   cx<R>* Gp = (cx<R>*)(ws + L.Gp);
   cx<R>* Gq = (cx<R>*)(ws + L.Gq);
@@ -114,6 +115,10 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   zd* Xm = (zd*)(ws + L.Xm);
   zd* Tm = (zd*)(ws + L.Tm);
   cx<R>* Qm = (cx<R>*)(ws + L.Qm);
+  bfc* Hb = (bfc*)(ws + L.Hb);     // bfloat16 operand copies (mixed precision)
+  bfc* Xb = (bfc*)(ws + L.Xb);
+  bfc* Zb = (bfc*)(ws + L.Zb);
+  const bool copies = sizeof(R) == 4 && p.bf16_copies && p.lowp_iters >= 1 && !p.wsr_only;
   zd* Lwm = (zd*)(ws + L.Lwm);
   zd* Lim = (zd*)(ws + L.Lim);
   zd* Cm = (zd*)(ws + L.Cm);
@@ -130,11 +135,19 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       if (nc == 0) continue;
       cx<R>* __restrict__ Gc = G + (long)un * sm.colOff[c];
       const double sc = scale[c];
+      auto epi = [&](int i, int j, cx<R> v) {
+        const R f = (R)(sc * sm.invsig[i / N]);
+        Gc[(long)i * nc + j] = {f * v.x, f * v.y};
+      };
+      if constexpr (sizeof(R) == 4) {
+        if (lowp && copies) {   // bfloat16 copies of H and of X (the current precoder)
+          channel_gemm_bf16<false>(un, nc, M, Hb + (long)c * un * M, M,
+                                   Xb + (long)M * sm.colOff[c], nc, sm.tiles, epi);
+          continue;
+        }
+      }
       channel_gemm<R, false>(un, nc, M, H + (long)c * un * M, M, X + (long)M * sm.colOff[c], nc,
-                             sm.tiles, lowp, [&](int i, int j, cx<R> v) {
-                               const R f = (R)(sc * sm.invsig[i / N]);
-                               Gc[(long)i * nc + j] = {f * v.x, f * v.y};
-                             });
+                             sm.tiles, lowp, epi);
     }
   };
 
@@ -755,6 +768,14 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     }
     __syncthreads();
   }
+  if constexpr (sizeof(R) == 4) {
+    if (copies) {   // bfloat16 copies of H and V^0 (rounded as the products would round them)
+      const long nh = (long)C * un * M;
+      for (long e = tid; e < nh; e += AMMSE_BLOCK) Hb[e] = to_bfc(H[e]);
+      for (long e = tid; e < Vtot; e += AMMSE_BLOCK) Xb[e] = to_bfc(Xc[e]);
+      __syncthreads();
+    }
+  }
   channel_product(Gp, Xc, sm.scur, p.lowp_iters >= 1);
   __syncthreads();
   const int T = p.wsr_only ? 0 : p.max_iters;
@@ -872,7 +893,14 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
             for (int k = 0; k < AMMSE_MAX_RX; ++k)
               if (k < N) acc = acc + Dm[u * 16 + n * 4 + k] * gh[k];
             if (own) acc = acc - Ym[u * 16 + n * 4 + (j - j0)];
-            Z[g0 + (long)n * nc] = from_d<R>(scal(is, acc));
+            const cx<R> zv = from_d<R>(scal(is, acc));
+            if constexpr (sizeof(R) == 4) {
+              if (lowp && copies) {
+                Zb[g0 + (long)n * nc] = to_bfc(zv);
+                continue;
+              }
+            }
+            Z[g0 + (long)n * nc] = zv;
           }
         }
       }
@@ -890,15 +918,30 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       cx<R>* __restrict__ xp = Xp + base;
       const double a1 = (1.0 + om) * sm.scur[c], a2 = om * sm.sprev[c], g2 = 2.0 * sm.gamma[c];
       double pw = 0.0;
-      channel_gemm<R, true>(M, nc, un, H + (long)c * un * M, M, Z + (long)un * sm.colOff[c], nc,
-                            sm.tiles, lowp, [&](int i, int j, cx<R> g) {
-                              const long e = (long)i * nc + j;
-                              const zd v = to_d(xc[e]), q = to_d(xp[e]);
-                              const cx<R> xs = from_d<R>(zd{a1 * v.x - a2 * q.x - g2 * (double)g.x,
-                                                            a1 * v.y - a2 * q.y - g2 * (double)g.y});
-                              xp[e] = xs;
-                              pw += nrm2(to_d(xs));
-                            });
+      bfc* __restrict__ xb = Xb + base;
+      const bool bcopy = lowp && copies;
+      auto epi = [&](int i, int j, cx<R> g) {
+        const long e = (long)i * nc + j;
+        const zd v = to_d(xc[e]), q = to_d(xp[e]);
+        const cx<R> xs = from_d<R>(zd{a1 * v.x - a2 * q.x - g2 * (double)g.x,
+                                      a1 * v.y - a2 * q.y - g2 * (double)g.y});
+        xp[e] = xs;
+        if constexpr (sizeof(R) == 4) {
+          if (bcopy) xb[e] = to_bfc(xs);
+        }
+        pw += nrm2(to_d(xs));
+      };
+      bool done = false;
+      if constexpr (sizeof(R) == 4) {
+        if (bcopy) {
+          channel_gemm_bf16<true>(M, nc, un, Hb + (long)c * un * M, M,
+                                  Zb + (long)un * sm.colOff[c], nc, sm.tiles, epi);
+          done = true;
+        }
+      }
+      if (!done)
+        channel_gemm<R, true>(M, nc, un, H + (long)c * un * M, M, Z + (long)un * sm.colOff[c], nc,
+                              sm.tiles, lowp, epi);
       pw = block_sum(pw, sm.red);
       if (tid == 0) {
         sm.sprev[c] = sm.scur[c];
