@@ -70,7 +70,7 @@ def read_traffic():
         return None
 
 
-def cpu_baseline(batch, ref, per_p: int = 16):
+def cpu_baseline(batch, ref, per_p: int = 256):
     """FP64 oracle A-MMMSE (as it stands) on a bounded sample of the workload."""
     import oracle as O
     workers = max(1, min(16, os.cpu_count() or 1))
