@@ -255,70 +255,129 @@ __device__ __forceinline__ zd shz(zd v, int src) {
 // ---------------------------------------------------------------------------
 // 4 x 4 complex double matrices spread over a 16-lane group: lane base + 4a + b
 // holds entry (a, b).  All functions must be executed by the whole wave.
+// The 16-lane groups are the DPP rows of the wave, so row-local patterns use
+// DPP moves (a broadcast of one lane of the row; a broadcast within the quad
+// of lanes that holds one matrix row) or a bit-mask swizzle; only transposed
+// reads go through the general lane permutation.
 // ---------------------------------------------------------------------------
 struct Lane4 {
   int base, a, b;
   __device__ __forceinline__ zd at(zd v, int r, int c) const { return shz(v, base + 4 * r + c); }
 };
 
-// In place Cholesky (lower); ok is cleared when a pivot is not positive/finite.
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v) {
+  const long long u = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)u, CTRL, 0xF, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int PAT>
+__device__ __forceinline__ double swz64(double v) {
+  const long long u = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_ds_swizzle((int)u, PAT);
+  const unsigned hi = (unsigned)__builtin_amdgcn_ds_swizzle((int)(u >> 32), PAT);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// entry (K, K) to every lane of the group (DPP row_newbcast)
+template <int K>
+__device__ __forceinline__ zd l4_diag(zd v) {
+  return {dpp64<0x150 + 5 * K>(v.x), dpp64<0x150 + 5 * K>(v.y)};
+}
+// entry (a, K) of the lane's own row a (DPP quad_perm [K, K, K, K])
+template <int K>
+__device__ __forceinline__ zd l4_rowq(zd v) {
+  return {dpp64<0x55 * K>(v.x), dpp64<0x55 * K>(v.y)};
+}
+// entry (K, b) of the lane's own column b (bit-mask swizzle: keep lane bits
+// 0, 1 and 4, set bits 2-3 to K)
+template <int K>
+__device__ __forceinline__ zd l4_colk(zd v) {
+  constexpr int PAT = 0x13 | ((4 * K) << 5);
+  return {swz64<PAT>(v.x), swz64<PAT>(v.y)};
+}
+
+// Cholesky step K of a Hermitian matrix: the trailing block is updated as a
+// whole, so row K above the diagonal still holds conj(column K) and supplies
+// L[b][K] = conj(A[K][b]) / l without a transposed read.
+template <int K>
+__device__ __forceinline__ void chol16_step(const Lane4& L, zd& A, bool& ok) {
+  const double dkk = l4_diag<K>(A).x;
+  const zd rk = l4_colk<K>(A);                  // A[K][b]
+  ok = ok && (dkk > 0.0) && isfinite(dkk);
+  const double l = sqrt(fmax(dkk, 1e-300));
+  const double il = 1.0 / l;
+  if (L.b == K && L.a > K) A = scal(il, A);
+  if (L.a == K && L.b == K) A = {l, 0.0};
+  const zd lak = l4_rowq<K>(A);                 // L[a][K]
+  if (L.a > K && L.b > K) A = A - scal(il, lak * rk);
+}
+
+// In place Cholesky (lower) of a Hermitian matrix; ok is cleared when a pivot
+// is not positive/finite.
 __device__ __forceinline__ zd chol16(const Lane4& L, zd A, bool& ok) {
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const double dkk = L.at(A, k, k).x;
-    ok = ok && (dkk > 0.0) && isfinite(dkk);
-    const double l = sqrt(fmax(dkk, 1e-300));
-    if (L.b == k && L.a > k) A = scal(1.0 / l, A);
-    if (L.a == k && L.b == k) A = {l, 0.0};
-    const zd lak = L.at(A, L.a, k), lbk = L.at(A, L.b, k);
-    if (L.a > k && L.b > k) A = A - mulc(lak, lbk);
-  }
+  chol16_step<0>(L, A, ok);
+  chol16_step<1>(L, A, ok);
+  chol16_step<2>(L, A, ok);
+  chol16_step<3>(L, A, ok);
   if (L.b > L.a) A = {0.0, 0.0};
   return A;
 }
 
+template <int K>
+__device__ __forceinline__ void trsm16_step(const Lane4& L, const zd& lq, double ik, zd& X) {
+  if (L.a == K) X = scal(ik, X);
+  const zd xkb = l4_colk<K>(X);
+  if (L.a > K) X = X - lq * xkb;
+}
+
 // X <- Lo^{-1} X (forward substitution, Lo lower with real diagonal)
 __device__ __forceinline__ zd trsm16(const Lane4& L, zd Lo, zd X) {
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const double lkk = L.at(Lo, k, k).x;
-    if (L.a == k) X = scal(1.0 / lkk, X);
-    const zd xkb = L.at(X, k, L.b), lak = L.at(Lo, L.a, k);
-    if (L.a > k) X = X - lak * xkb;
-  }
+  const double i0 = 1.0 / l4_diag<0>(Lo).x, i1 = 1.0 / l4_diag<1>(Lo).x;
+  const double i2 = 1.0 / l4_diag<2>(Lo).x, i3 = 1.0 / l4_diag<3>(Lo).x;
+  const zd q0 = l4_rowq<0>(Lo), q1 = l4_rowq<1>(Lo), q2 = l4_rowq<2>(Lo);
+  trsm16_step<0>(L, q0, i0, X);
+  trsm16_step<1>(L, q1, i1, X);
+  trsm16_step<2>(L, q2, i2, X);
+  if (L.a == 3) X = scal(i3, X);
   return X;
+}
+
+template <int K>
+__device__ __forceinline__ void trsm16h_step(const Lane4& L, const zd& lka, double ik, zd& X) {
+  if (L.a == K) X = scal(ik, X);
+  const zd xkb = l4_colk<K>(X);
+  if (L.a < K) X = X - cj(lka) * xkb;
 }
 
 // X <- Lo^{-H} X (back substitution with the conjugate transpose)
 __device__ __forceinline__ zd trsm16h(const Lane4& L, zd Lo, zd X) {
-#pragma unroll
-  for (int k = 3; k >= 0; --k) {
-    const double lkk = L.at(Lo, k, k).x;
-    if (L.a == k) X = scal(1.0 / lkk, X);
-    const zd xkb = L.at(X, k, L.b), lka = L.at(Lo, k, L.a);
-    if (L.a < k) X = X - cj(lka) * xkb;
-  }
+  const double i0 = 1.0 / l4_diag<0>(Lo).x, i1 = 1.0 / l4_diag<1>(Lo).x;
+  const double i2 = 1.0 / l4_diag<2>(Lo).x, i3 = 1.0 / l4_diag<3>(Lo).x;
+  const zd t1 = L.at(Lo, 1, L.a), t2 = L.at(Lo, 2, L.a), t3 = L.at(Lo, 3, L.a);   // Lo[k][a]
+  trsm16h_step<3>(L, t3, i3, X);
+  trsm16h_step<2>(L, t2, i2, X);
+  trsm16h_step<1>(L, t1, i1, X);
+  if (L.a == 0) X = scal(i0, X);
   return X;
 }
 
 // A^H B, A B, A B^H
 __device__ __forceinline__ zd mm_hn(const Lane4& L, zd A, zd B) {
-  zd c = {0.0, 0.0};
-#pragma unroll
-  for (int k = 0; k < 4; ++k) c = c + cj(L.at(A, k, L.a)) * L.at(B, k, L.b);
-  return c;
+  const zd a0 = L.at(A, 0, L.a), a1 = L.at(A, 1, L.a), a2 = L.at(A, 2, L.a), a3 = L.at(A, 3, L.a);
+  const zd b0 = l4_colk<0>(B), b1 = l4_colk<1>(B), b2 = l4_colk<2>(B), b3 = l4_colk<3>(B);
+  return ((cj(a0) * b0 + cj(a1) * b1) + (cj(a2) * b2 + cj(a3) * b3));
 }
 __device__ __forceinline__ zd mm_nn(const Lane4& L, zd A, zd B) {
-  zd c = {0.0, 0.0};
-#pragma unroll
-  for (int k = 0; k < 4; ++k) c = c + L.at(A, L.a, k) * L.at(B, k, L.b);
-  return c;
+  (void)L;
+  const zd a0 = l4_rowq<0>(A), a1 = l4_rowq<1>(A), a2 = l4_rowq<2>(A), a3 = l4_rowq<3>(A);
+  const zd b0 = l4_colk<0>(B), b1 = l4_colk<1>(B), b2 = l4_colk<2>(B), b3 = l4_colk<3>(B);
+  return ((a0 * b0 + a1 * b1) + (a2 * b2 + a3 * b3));
 }
 __device__ __forceinline__ zd mm_nh(const Lane4& L, zd A, zd B) {
-  zd c = {0.0, 0.0};
-#pragma unroll
-  for (int k = 0; k < 4; ++k) c = c + mulc(L.at(A, L.a, k), L.at(B, L.b, k));
-  return c;
+  const zd a0 = l4_rowq<0>(A), a1 = l4_rowq<1>(A), a2 = l4_rowq<2>(A), a3 = l4_rowq<3>(A);
+  const zd b0 = L.at(B, L.b, 0), b1 = L.at(B, L.b, 1), b2 = L.at(B, L.b, 2), b3 = L.at(B, L.b, 3);
+  return ((mulc(a0, b0) + mulc(a1, b1)) + (mulc(a2, b2) + mulc(a3, b3)));
 }
 
 __device__ __forceinline__ double rel_change(double a, double b) {

@@ -3,12 +3,10 @@
 // For single-cell instances with M = 64 and U*N = U*d = 64, one workgroup of
 // 256 threads (4 waves) owns one instance for the whole solve; H stays in
 // LDS for all iterations and HBM is touched only to read H, V0 and the
-// per-user scalars and to write the results.  LDS use is kept under 80 KiB
-// so that two instances share a compute unit and one instance's serial
-// phases overlap the other's matrix products.
+// per-user scalars and to write the results.
 //
 // Channel products: v_mfma_f32_16x16x4f32, a complex product being three
-// real accumulators (Re*Re, Im*Im, Re*Im + Im*Re) fed from interleaved
+// real products (Re*Re, Im*Im, (Re + Im)*(Re + Im)) fed from interleaved
 // complex LDS tiles.  Each wave owns whole 16-row strips of the outputs, so
 // the iteration state stays in registers in the MFMA output layout:
 //   G^{t-1}, G^{t-2}  (the extrapolated product follows by linearity)
@@ -26,7 +24,7 @@
 // Per iteration t (Algorithm 3):
 //   J- from registers (reduce-scatter over the 16 lanes of a row group);
 //   Cholesky, rate, U, W per block user; WSR(V^{t-1}); stage latch;
-//   adaptive step by Lanczos on H in LDS;  Z = S (D G^ - Y) -> LDS;
+//   adaptive step by Lanczos on K = C^H Q C (formed in LDS);  Z = S (D G^ - Y) -> LDS;
 //   Grad = 2 H^H Z (MFMA);  V^t = Pi(V^ - gamma Grad) in registers -> LDS;
 //   G^t = S H V^t (MFMA), own blocks -> LDS.
 
@@ -57,14 +55,18 @@ struct Shape {
   static constexpr size_t oQ = oY + sizeof(float2) * NG * 16;       // S H H^H S (UN x UN)
   static constexpr size_t QLD = UN + 2;
   static constexpr size_t oC = oQ + sizeof(float2) * UN * QLD;      // C per block user (D = C C^H)
-  static constexpr size_t oS = oC + sizeof(zd) * NG * 16;           // invsig, alpha per row
+  static constexpr int CST = 17;                                    // padded stride of C blocks (zd)
+  static constexpr size_t oS = oC + sizeof(zd) * NG * CST;          // invsig, alpha per row
   static constexpr size_t oL = oS + sizeof(double) * 2 * UN;        // la, lb
   static constexpr size_t oR = oL + sizeof(double) * 2 * AMMSE_MAX_LANCZOS;
-  static constexpr size_t bytes = oR + sizeof(double) * 8 + 16;
-  // Lanczos vectors alias the product-operand area, which is free between
-  // the last product of an iteration and the Z build.
-  static_assert(sizeof(zd) * 2 * UN + 64 * sizeof(double) <= sizeof(float2) * BROWS * BLD,
-                "Lanczos area");
+  static constexpr size_t oVq = oR + sizeof(double) * 8 + 16;      // V^{t-2}, per lane
+  static constexpr size_t bytes = oVq + sizeof(float2) * 256 * VRB * UDB * 4;
+  // During the step-size computation (between the receivers and the Z build)
+  // K = C^H Q C and a float copy of the Lanczos vector alias the
+  // product-operand area, the partial products alias C, and the tridiagonal
+  // pairs alias la/lb.
+  static_assert(sizeof(double) * 2 * AMMSE_MAX_LANCZOS >= 16 * 64, "tridiagonal pairs");
+  static_assert(UN * UN + UN <= BROWS * BLD, "K and the Lanczos vector copy");
 };
 
 __device__ __forceinline__ float2 c2(float x, float y) { return make_float2(x, y); }
@@ -73,10 +75,13 @@ __device__ __forceinline__ float2 c2(float x, float y) { return make_float2(x, y
 // blocks i (global row block wave + 4 i) and all column blocks j.
 // op(A)[r][k] = A[r*lda + k], or conj(A[k*lda + r]) with CONJA; B[k][j] is
 // B[k*ldb + j], or conj(B[j*ldb + k]) with CONJBT.
-template <int NRB, int NCB, bool CONJA, bool CONJBT = false>
+// Three real products per complex product (Gauss): P0 = Ar Br, P1 = Ai Bi,
+// P2 = (Ar + Ai)(Br + Bi); Re = P0 - P1, Im = P2 - P0 - P1 (see cplx_at).
+template <int NRB, int NCB, int K, bool CONJA, bool CONJBT = false>
 __device__ __forceinline__ void wave_cgemm(const float2* __restrict__ A, int lda,
-                                           const float2* __restrict__ B, int ldb, int K,
+                                           const float2* __restrict__ B, int ldb,
                                            int wave, floatx4 (&P)[NRB][NCB][3]) {
+  static_assert(K % 8 == 0, "two k-steps per loop trip");
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
@@ -85,9 +90,7 @@ __device__ __forceinline__ void wave_cgemm(const float2* __restrict__ A, int lda
     for (int j = 0; j < NCB; ++j)
 #pragma unroll
       for (int q = 0; q < 3; ++q) P[i][j][q] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-  for (int k0 = 0; k0 < K; k0 += 4) {
-    float2 a[NRB], b[NCB];
+  auto load = [&](int k0, float2 (&a)[NRB], float2 (&b)[NCB]) {
     const int kk = k0 + lk;
 #pragma unroll
     for (int i = 0; i < NRB; ++i) {
@@ -108,6 +111,13 @@ __device__ __forceinline__ void wave_cgemm(const float2* __restrict__ A, int lda
         b[j] = B[kk * ldb + 16 * j + li];
       }
     }
+  };
+  auto step = [&](const float2 (&a)[NRB], const float2 (&b)[NCB]) {
+    float as[NRB], bs[NCB];
+#pragma unroll
+    for (int i = 0; i < NRB; ++i) as[i] = a[i].x + a[i].y;
+#pragma unroll
+    for (int j = 0; j < NCB; ++j) bs[j] = b[j].x + b[j].y;
 #pragma unroll
     for (int i = 0; i < NRB; ++i)
 #pragma unroll
@@ -122,41 +132,152 @@ __device__ __forceinline__ void wave_cgemm(const float2* __restrict__ A, int lda
     for (int i = 0; i < NRB; ++i)
 #pragma unroll
       for (int j = 0; j < NCB; ++j)
-        P[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].x, b[j].y, P[i][j][2], 0, 0, 0);
-#pragma unroll
-    for (int i = 0; i < NRB; ++i)
-#pragma unroll
-      for (int j = 0; j < NCB; ++j)
-        P[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].y, b[j].x, P[i][j][2], 0, 0, 0);
+        P[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(as[i], bs[j], P[i][j][2], 0, 0, 0);
+  };
+  // operands of the next k-step are fetched before the current one's MFMAs
+  float2 a0[NRB], b0[NCB], a1[NRB], b1[NCB];
+  load(0, a0, b0);
+#pragma unroll 2
+  for (int k0 = 0; k0 < K; k0 += 8) {
+    load(k0 + 4, a1, b1);
+    step(a0, b0);
+    if (k0 + 8 < K) load(k0 + 8, a0, b0);
+    step(a1, b1);
   }
 }
 
-// Largest eigenvalue of a symmetric tridiagonal matrix (la, lb in LDS, m x m)
-// by multisection inside one wave: 64 probes per round on Sturm counts.
+// Complex entry r of an accumulator triple from wave_cgemm.
+__device__ __forceinline__ float2 cplx_at(const floatx4 (&P)[3], int r) {
+  return c2(P[0][r] - P[1][r], P[2][r] - P[0][r] - P[1][r]);
+}
 
-__device__ __forceinline__ double wave_tridiag_lmax(const double* la, const double* lb, int m,
-                                                    double rtol) {
-  const int lane = threadIdx.x & 63;
-  double lo = 1e300, hi = -1e300;
-  for (int i = 0; i < m; ++i) {
-    const double r = (i > 0 ? fabs(lb[i - 1]) : 0.0) + (i < m - 1 ? fabs(lb[i]) : 0.0);
-    lo = fmin(lo, la[i] - r);
-    hi = fmax(hi, la[i] + r);
+// ---------------------------------------------------------------------------
+// Wave-level helpers (64 lanes, no LDS traffic)
+// ---------------------------------------------------------------------------
+
+// Value of lane l (l uniform over the wave).
+__device__ __forceinline__ double rlane(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)u, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ zd rlane(zd v, int l) { return {rlane(v.x, l), rlane(v.y, l)}; }
+
+// Sum over the 64 lanes; every lane receives the same value (the row sums
+// of lanes 0, 16, 32, 48 added in a fixed order).
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp64<0xB1>(v);     // quad_perm [1,0,3,2]: lane ^ 1
+  v += dpp64<0x4E>(v);     // quad_perm [2,3,0,1]: lane ^ 2
+  v += dpp64<0x124>(v);    // row_ror 4
+  v += dpp64<0x128>(v);    // row_ror 8
+  return (rlane(v, 0) + rlane(v, 16)) + (rlane(v, 32) + rlane(v, 48));
+}
+
+// Sum over the 256-thread block (four waves); every thread receives the
+// same value.  red: four doubles of LDS.
+__device__ __forceinline__ double block_sum4(double v, double* red) {
+  v = wave_sum_dpp(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix held in
+// LDS as pairs tp[k] = (a_k, b_{k-1}^2) (entries of magnitude <= 1; entries
+// from m on padded with a = 8, b = 0, which adds eigenvalues above every
+// probe and leaves the count unchanged).  Sign changes of the leading
+// principal minors p_k(x) = det(T_k - x I), computed without divisions
+// (p_{k+1} = (a_k - x) p_k - b_{k-1}^2 p_{k-1}) and rescaled by powers of two
+// every four steps to stay in range.
+__device__ __forceinline__ int sturm_count(const double2* tp, int m, double x) {
+  const double big = 0x1p400, small = 0x1p-400;
+  double pm = 1.0, pc = tp[0].x - x;
+  auto sgn = [](double v) { return (unsigned)((unsigned long long)__double_as_longlong(v) >> 63); };
+  unsigned cnt = sgn(pc);
+  for (int i = 1; i < m; i += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = i + u;
+      if (k < 64) {                              // uniform; steps from m on are padding
+        const double2 e = tp[k];
+        const double pn = fma(e.x - x, pc, -e.y * pm);
+        cnt += sgn(pn) ^ sgn(pc);
+        pm = pc;
+        pc = pn;
+      }
+    }
+    const double mag = fmax(fabs(pc), fabs(pm));
+    const double f = (mag > big) ? small : ((mag < small) ? big : 1.0);
+    pc *= f;
+    pm *= f;
   }
-  hi += fabs(hi) * 1e-6 + 1e-300;
-  for (int round = 0; round < 8; ++round) {
+  return (int)cnt;
+}
+
+// Largest eigenvalue, to relative width 1e-10, of the m x m symmetric
+// tridiagonal matrix with diagonal ta and off-diagonal tb (lane i: entry i),
+// by multisection inside one wave (64 probes per round on Sturm counts of the
+// matrix scaled by 1/tmax, tmax >= every |a_i| + |b_i|; tp: 64 pairs of LDS
+// owned by the calling wave).  With a previous estimate th_prev > 0 (the
+// value for a leading block, which bounds the new one from below) one round
+// over [th_prev, th_prev (1 + ltol)] first tests whether the value moved by
+// less than ltol; *conv reports that test.
+__device__ __forceinline__ double wave_tridiag_lmax(double ta, double tb, int m, double tmax,
+                                                    double th_prev, double ltol, double2* tp,
+                                                    bool* conv) {
+  const int lane = threadIdx.x & 63;
+  const double rtol = 1e-10;
+  const double is = 1.0 / tmax;
+  const double an = (lane < m) ? ta * is : 8.0;
+  const double bn = (lane < m - 1) ? tb * is : 0.0;
+  const double bl_ = __shfl_up(bn, 1, 64);
+  tp[lane] = make_double2(an, (lane > 0) ? bl_ * bl_ : 0.0);
+  *conv = false;
+  double lo, hi;
+  if (th_prev > 0.0) {
+    const double t0 = th_prev * is;
+    const double x = t0 * (1.0 + ltol * (double)(lane + 1) / 64.0);
+    const unsigned long long mask = __ballot(sturm_count(tp, m, x) == m);
+    if (mask) {
+      *conv = true;
+      const int t = __ffsll((long long)mask) - 1;
+      return th_prev * (1.0 + ltol * (double)(t + 1) / 64.0);
+    }
+    lo = t0 * (1.0 + ltol);
+  } else {
+    lo = 1e300;
+  }
+  // Gershgorin interval
+  double glo = 1e300, ghi = -1e300;
+  if (lane < m) {
+    const double bl = (lane > 0) ? fabs(bl_) : 0.0;
+    const double br = (lane < m - 1) ? fabs(bn) : 0.0;
+    glo = an - bl - br;
+    ghi = an + bl + br;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    glo = fmin(glo, __shfl_xor(glo, off, 64));
+    ghi = fmax(ghi, __shfl_xor(ghi, off, 64));
+  }
+  glo = rlane(glo, 0);
+  ghi = rlane(ghi, 0);
+  hi = ghi + fabs(ghi) * 1e-6 + 1e-300;
+  lo = (th_prev > 0.0) ? fmin(lo, hi) : glo;
+  for (int round = 0; round < 10; ++round) {
     const double w = hi - lo;
     if (!(w > fabs(hi) * rtol)) break;
     const double x = lo + w * (double)(lane + 1) / 65.0;
-    const bool full = sturm_below(la, lb, m, x) == m;
-    const unsigned long long mask = __ballot(full);
+    const unsigned long long mask = __ballot(sturm_count(tp, m, x) == m);
     const int t = mask ? (__ffsll((long long)mask) - 1) : 64;
     const double nhi = (t < 64) ? lo + w * (double)(t + 1) / 65.0 : hi;
     const double nlo = (t > 0) ? lo + w * (double)t / 65.0 : lo;
     lo = nlo;
     hi = nhi;
   }
-  return hi;
+  return hi * tmax;
 }
 
 template <class S>
@@ -202,7 +323,9 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
 
   // register state: element [i][j][r] is row 16 (wave + 4 i) + 4 lk + r,
   // column 16 j + li
-  float2 Vp[S::VRB][S::UDB][4], Vq[S::VRB][S::UDB][4];
+  // V^{t-2} lives in LDS (per lane, entry e of this lane at VqS[e * 256 + tid])
+  float2* VqS = (float2*)(smem + S::oVq);
+  float2 Vp[S::VRB][S::UDB][4];
   float2 Gp[S::GRB][S::UDB][4], Gq[S::GRB][S::UDB][4];
 #pragma unroll
   for (int i = 0; i < S::VRB; ++i)
@@ -212,13 +335,13 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * (wave + 4 * i) + 4 * lk + r, col = 16 * j + li;
         Vp[i][j][r] = Bs[row * S::BLD + col];
-        Vq[i][j][r] = Vp[i][j][r];
+        VqS[((i * S::UDB + j) * 4 + r) * 256 + tid] = Vp[i][j][r];
       }
 
   // Q = S H H^H S for the step-size operator, once per solve
   {
     floatx4 P[S::GRB][S::UNB][3];
-    wave_cgemm<S::GRB, S::UNB, false, true>(Hs, S::HLD, Hs, S::HLD, M, wave, P);
+    wave_cgemm<S::GRB, S::UNB, M, false, true>(Hs, S::HLD, Hs, S::HLD, wave, P);
 #pragma unroll
     for (int i = 0; i < S::GRB; ++i)
 #pragma unroll
@@ -227,7 +350,8 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
         for (int r = 0; r < 4; ++r) {
           const int row = 16 * (wave + 4 * i) + 4 * lk + r, col = 16 * j + li;
           const float s = (float)(invsig[row] * invsig[col]);
-          Qs[row * S::QLD + col] = c2(s * (P[i][j][0][r] - P[i][j][1][r]), s * P[i][j][2][r]);
+          const float2 v = cplx_at(P[i][j], r);
+          Qs[row * S::QLD + col] = c2(s * v.x, s * v.y);
         }
     __syncthreads();
     for (int e = tid; e < UN * UN; e += 256) {      // exactly Hermitian
@@ -247,7 +371,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   // G = S H V (V in Bs) into Gp (previous Gp to Gq); own blocks into Fs
   auto product_G = [&]() {
     floatx4 P[S::GRB][S::UDB][3];
-    wave_cgemm<S::GRB, S::UDB, false>(Hs, S::HLD, Bs, S::BLD, M, wave, P);
+    wave_cgemm<S::GRB, S::UDB, M, false>(Hs, S::HLD, Bs, S::BLD, wave, P);
 #pragma unroll
     for (int i = 0; i < S::GRB; ++i)
 #pragma unroll
@@ -256,7 +380,8 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
         for (int r = 0; r < 4; ++r) {
           const int row = 16 * (wave + 4 * i) + 4 * lk + r, col = 16 * j + li;
           const float s = (float)invsig[row];
-          const float2 g = c2(s * (P[i][j][0][r] - P[i][j][1][r]), s * P[i][j][2][r]);
+          const float2 v = cplx_at(P[i][j], r);
+          const float2 g = c2(s * v.x, s * v.y);
           Gq[i][j][r] = Gp[i][j][r];
           Gp[i][j][r] = g;
           const int u = row >> lgN, c = col - (u << lgd);
@@ -277,29 +402,31 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
 #pragma unroll
     for (int i = 0; i < S::GRB; ++i) {
       const int row0 = 16 * (wave + 4 * i) + 4 * lk;
-      // partial J over this lane's columns, all 16 entries (a, b)
-      zd s[16];
+      // partial J over this lane's columns in float (Hermitian: the upper
+      // triangle is accumulated, the lower one mirrored)
+      float2 s[16];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) s[e] = {0.0, 0.0};
+      for (int e = 0; e < 16; ++e) s[e] = c2(0.f, 0.f);
 #pragma unroll
       for (int j = 0; j < S::UDB; ++j) {
         const int col = 16 * j + li;
-        zd g[4];
         bool own[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          g[r] = {(double)Gp[i][j][r].x, (double)Gp[i][j][r].y};
-          own[r] = (col >> lgd) == ((row0 + r) >> lgN);
-        }
+        for (int r = 0; r < 4; ++r) own[r] = (col >> lgd) == ((row0 + r) >> lgN);
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
+          for (int c = a; c < 4; ++c) {
             const bool use = ((row0 + a) >> lgN == (row0 + c) >> lgN) && !own[a];
-            const zd t = mulc(g[a], g[c]);
-            if (use) s[a * 4 + c] = s[a * 4 + c] + t;
+            const float2 ga = Gp[i][j][a], gc = Gp[i][j][c];
+            const float2 t = c2(ga.x * gc.x + ga.y * gc.y, ga.y * gc.x - ga.x * gc.y);
+            if (use) s[a * 4 + c] = c2(s[a * 4 + c].x + t.x, s[a * 4 + c].y + t.y);
           }
       }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < a; ++c) s[a * 4 + c] = c2(s[c * 4 + a].x, -s[c * 4 + a].y);
       // reduce-scatter over the 16 lanes: lane li ends with entry li
 #pragma unroll
       for (int step = 0; step < 4; ++step) {
@@ -308,13 +435,13 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
         const bool hi = (li & bit) != 0;
 #pragma unroll
         for (int e = 0; e < half; ++e) {
-          const zd keep = hi ? s[e + half] : s[e];
-          const zd send = hi ? s[e] : s[e + half];
-          const zd got = {__shfl_xor(send.x, bit, 64), __shfl_xor(send.y, bit, 64)};
-          s[e] = keep + got;
+          const float2 keep = hi ? s[e + half] : s[e];
+          const float2 send = hi ? s[e] : s[e + half];
+          const float2 got = c2(__shfl_xor(send.x, bit, 64), __shfl_xor(send.y, bit, 64));
+          s[e] = c2(keep.x + got.x, keep.y + got.y);
         }
       }
-      zd J = s[0];
+      zd J = {(double)s[0].x, (double)s[0].y};
       if (L4.a == L4.b) J = {J.x + 1.0, 0.0};
       const float2 fo = Fs[(row0 >> 2) * 16 + li];
       zd F = {(double)fo.x, (double)fo.y};
@@ -349,112 +476,140 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
       Ys[g4 * 16 + li] = c2((float)(al * Ur.x), (float)(al * Ur.y));
       // D = C C^H: C = sqrt(alpha) U (stage I) or sqrt(alpha) UW Lw^{-H} (stage II)
       const zd Cv = stage2 ? mm_nh(L4, UWr[i], Lir[i]) : T;
-      Cs[g4 * 16 + li] = scal(sqrt(al), Cv);
+      Cs[g4 * S::CST + li] = scal(sqrt(al), Cv);
     }
     __syncthreads();
   };
 
   // lambda_max(A), A = H^H S D S H.  With D = C C^H (C block diagonal) and
   // Q = S H H^H S (formed once per solve), lambda_max(A) = lambda_max(K) for
-  // the U N x U N matrix K = C^H Q C; plain Lanczos on K, two block barriers
-  // per step.  Row r of K is handled by 4 lanes (16 columns each); the
-  // Lanczos vectors stay in registers (every lane of a row holds its entry);
-  // u = C x goes through LDS for the dense product with Q;
+  // the U N x U N matrix K = C^H Q C.  K is formed in LDS (over the product
+  // operand, free here; stored transposed so that lane r reads row r of K
+  // from consecutive addresses), then plain Lanczos on K: every wave holds
+  // the whole Lanczos vectors (lane r: entry r), multiplies its 16 columns of
+  // K, and the four partial products meet in LDS (over C, no longer needed);
+  // the recurrence scalars and the tridiagonal eigenvalue are computed by
+  // every wave alike, the stop decision of wave 0 is shared through LDS.
   //   beta^2 = ||y||^2 - alpha^2 - 2 beta_prev Re(p^H y) + beta_prev^2.
   auto lanczos = [&]() {
-    static_assert(UN == 64, "16-row strips per wave");
-    zd* uv = Lq;                                  // u = C x
-    double* part = (double*)(Lq + UN);            // [4 waves][4] partial sums
-    const int sub = lane & 3, idx = 16 * wave + (lane >> 2), gq = lane & ~15;
-    const int g4 = idx >> 2, a4 = idx & 3;
-    zd cr[4], cc[4];                              // row a4 of C, column a4 of C
+    static_assert(UN == 64 && S::NG == 16, "one Lanczos entry per lane");
+    static_assert(sizeof(float2) * UN * UN <= sizeof(float2) * S::BROWS * S::BLD, "K area");
+    static_assert(sizeof(zd) * 4 * UN <= sizeof(zd) * S::NG * S::CST, "partial area");
+    float2* Kt = Bs;                              // Kt[c * UN + r] = K[r][c]
+    zd* part = (zd*)Cs;                           // [4 waves][UN]
+    float2* xs = Bs + UN * UN;                    // float copy of x; each wave writes and
+                                                  // reads back only its own 16 columns
+    double2* tp = (double2*)la;                   // tridiagonal pairs (wave 0)
+    {
+      // block (g, h): K_gh = C_g^H Q_gh C_h, one thread per block; Q_gh is
+      // read as Q_hg^H (Q is exactly Hermitian) for conflict-light LDS reads
+      const int g = tid & 15, h = tid >> 4;
+      float2 q[4][4];
+      float2 cg[4][4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      cr[k] = Cs[g4 * 16 + a4 * 4 + k];
-      cc[k] = Cs[g4 * 16 + k * 4 + a4];
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float2 qt = Qs[(4 * h + k) * S::QLD + 4 * g + a];
+          q[a][k] = c2(qt.x, -qt.y);
+          const zd c = Cs[g * S::CST + a * 4 + k];
+          cg[a][k] = c2((float)c.x, (float)c.y);
+        }
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) {
+        zd ch[4], w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) ch[k] = Cs[h * S::CST + k * 4 + bb];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          w[a] = {0.0, 0.0};
+#pragma unroll
+          for (int k = 0; k < 4; ++k) w[a] = w[a] + zd{(double)q[a][k].x, (double)q[a][k].y} * ch[k];
+        }
+        float4 kv2[2];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          zd kv = {0.0, 0.0};
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            kv = kv + cj(zd{(double)cg[k][a].x, (double)cg[k][a].y}) * w[k];
+          if (a & 1) {
+            kv2[a >> 1].z = (float)kv.x;
+            kv2[a >> 1].w = (float)kv.y;
+          } else {
+            kv2[a >> 1].x = (float)kv.x;
+            kv2[a >> 1].y = (float)kv.y;
+          }
+        }
+        float4* dst = (float4*)(Kt + (4 * h + bb) * UN + 4 * g);
+        dst[0] = kv2[0];
+        dst[1] = kv2[1];
+      }
     }
-    zd x = {1.0 + 0.5 * sin(0.731 * idx + 0.25), 0.3 * cos(1.37 * idx + 0.5)};
-    const double nn = block_sum((sub == 0) ? nrm2(x) : 0.0, red);
-    x = scal(1.0 / sqrt(nn), x);
-    zd pp = {0.0, 0.0};
-    auto put_u = [&]() {                          // u = C x for row idx
-      zd u = {0.0, 0.0};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) u = u + cr[k] * shz(x, gq + 4 * k + sub);
-      if (sub == 0) uv[idx] = u;
-    };
-    put_u();
     __syncthreads();
-    const int m = min(p.lanczos_steps, UN);
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    zd x = {1.0 + 0.5 * sin(0.731 * lane + 0.25), 0.3 * cos(1.37 * lane + 0.5)};
+    x = scal(1.0 / sqrt(wave_sum_dpp(nrm2(x))), x);
+    zd pp = {0.0, 0.0};
+    double ta = 0.0, tb = 0.0;                    // T entries, lane j holds entry j
+    const int m = max(1, min(p.lanczos_steps, UN));
     const double ltol = 1e-8;
     double beta_prev = 0.0, tmax = 0.0, theta = 0.0;
-    for (int j = 0; j < m; ++j) {
-      zd z = {0.0, 0.0};
-#pragma unroll 4
-      for (int k = 0; k < 16; ++k) {
-        const int c = 16 * sub + ((k + idx) & 15);
-        const float2 q = Qs[idx * S::QLD + c];
-        z = z + zd{(double)q.x, (double)q.y} * uv[c];
-      }
-      z.x += __shfl_xor(z.x, 1, 64);
-      z.y += __shfl_xor(z.y, 1, 64);
-      z.x += __shfl_xor(z.x, 2, 64);
-      z.y += __shfl_xor(z.y, 2, 64);
-      zd y = {0.0, 0.0};                          // y = C^H z in the block user
+    bool stop = false;
+    for (int j = 0;; ++j) {
+      // partial product over this wave's 16 columns in float (K is stored in
+      // float), two accumulator pairs, combined in double
+      float2 ya = c2(0.f, 0.f), yb = c2(0.f, 0.f);
+      {
+        if ((lane >> 4) == wv) xs[lane] = c2((float)x.x, (float)x.y);   // read back broadcast
+        float2 kv[16], xv[16];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) y = y + cj(cc[k]) * shz(z, gq + 4 * k + sub);
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-      if (sub == 0) {
-        s0 = nrm2(y);
-        s1 = x.x * y.x + x.y * y.y;
-        s2 = pp.x * y.x + pp.y * y.y;
+        for (int k = 0; k < 16; ++k) {
+          kv[k] = Kt[(16 * wv + k) * UN + lane];
+          xv[k] = xs[16 * wv + k];
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          float2& acc = (k & 1) ? yb : ya;
+          acc.x += kv[k].x * xv[k].x - kv[k].y * xv[k].y;
+          acc.y += kv[k].x * xv[k].y + kv[k].y * xv[k].x;
+        }
       }
-      s0 = wave_sum(s0);
-      s1 = wave_sum(s1);
-      s2 = wave_sum(s2);
-      if (lane == 0) {
-        part[wave * 4 + 0] = s0;
-        part[wave * 4 + 1] = s1;
-        part[wave * 4 + 2] = s2;
+      const zd yw = {(double)ya.x + (double)yb.x, (double)ya.y + (double)yb.y};
+      if (tid == 0) {
+        misc[1] = stop ? 1 : 0;
+        red[7] = theta;
       }
       __syncthreads();
-      double yy = 0.0, al = 0.0, py = 0.0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        yy += part[q * 4 + 0];
-        al += part[q * 4 + 1];
-        py += part[q * 4 + 2];
-      }
+      if (misc[1]) break;
+      part[wave * UN + lane] = yw;
+      __syncthreads();
+      const zd y = (part[lane] + part[UN + lane]) + (part[2 * UN + lane] + part[3 * UN + lane]);
+      const double al = wave_sum_dpp(x.x * y.x + x.y * y.y);
+      const double yy = wave_sum_dpp(nrm2(y));
+      const double py = wave_sum_dpp(pp.x * y.x + pp.y * y.y);
       const double bb = sqrt(fmax(yy - al * al - 2.0 * beta_prev * py + beta_prev * beta_prev, 0.0));
-      if (tid == 0) {
-        la[j] = al;
-        lb[j] = bb;
+      if (lane == j) {
+        ta = al;
+        tb = bb;
       }
       const int msz = j + 1;
       tmax = fmax(tmax, fabs(al) + bb);
       const bool breakdown = !(bb > 1e-12 * tmax);
-      bool stop = breakdown;
-      if (breakdown || (msz >= 12 && (msz % 4) == 0) || msz == m) {
-        __syncthreads();
-        if (wave == 0) {
-          const double th = (tmax > 0.0) ? wave_tridiag_lmax(la, lb, msz, 1e-10) : 0.0;
-          if (lane == 0) red[7] = th;
-        }
-        __syncthreads();
-        const double th = red[7];
-        stop = stop || fabs(th - theta) <= ltol * fabs(th);
-        theta = th;
+      // only wave 0's decision is used (shared through LDS above)
+      if (wave == 0 && (breakdown || (msz >= 16 && (msz % 4) == 0) || msz == m)) {
+        bool conv = false;
+        theta = (tmax > 0.0) ? wave_tridiag_lmax(ta, tb, msz, tmax, theta, ltol, tp, &conv) : 0.0;
+        stop = breakdown || conv || msz == m;
       }
-      if (stop) break;
-      const zd xn = scal(1.0 / bb, y - scal(al, x) - scal(beta_prev, pp));
-      pp = x;
-      x = xn;
-      beta_prev = bb;
-      put_u();
-      __syncthreads();
+      if (!stop) {
+        const zd xn = scal(1.0 / bb, y - scal(al, x) - scal(beta_prev, pp));
+        pp = x;
+        x = xn;
+        beta_prev = bb;
+      }
     }
-    __syncthreads();
-    return theta;
+    return red[7];
   };
 
   product_G();
@@ -478,7 +633,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   for (int t = 1; t <= T; ++t) {
     const double rs = receivers();
     wsr_prev2 = wsr_prev;
-    wsr_prev = block_sum(rs, red) * (1.0 / M_LN2);
+    wsr_prev = block_sum4(rs, red) * (1.0 / M_LN2);
     if (p.trace && tid == 0) p.trace[(long)b * p.trace_len + (t - 1)] = wsr_prev;
     if (misc[0]) {
       status |= misc[0];
@@ -550,7 +705,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
     // gradient and the extrapolated projected step, in registers
     {
       floatx4 P[S::VRB][S::UDB][3];
-      wave_cgemm<S::VRB, S::UDB, true>(Hs, S::HLD, Bs, S::BLD, UN, wave, P);
+      wave_cgemm<S::VRB, S::UDB, UN, true>(Hs, S::HLD, Bs, S::BLD, wave, P);
       const float g2 = (float)(2.0 * gamma);
       double pw = 0.0;
 #pragma unroll
@@ -559,14 +714,17 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
         for (int j = 0; j < S::UDB; ++j)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const float gx = P[i][j][0][r] - P[i][j][1][r], gy = P[i][j][2][r];
-            const float2 v = Vp[i][j][r], q = Vq[i][j][r];
+            const float2 gv = cplx_at(P[i][j], r);
+            const float gx = gv.x, gy = gv.y;
+            const int e = ((i * S::UDB + j) * 4 + r) * 256 + tid;
+            const float2 v = Vp[i][j][r], q = VqS[e];
             const float2 x = c2((1.f + om) * v.x - om * q.x - g2 * gx,
                                 (1.f + om) * v.y - om * q.y - g2 * gy);
-            Vq[i][j][r] = x;     // temporarily holds V~
+            VqS[e] = v;          // V^{t-1} becomes V^{t-2}
+            Vp[i][j][r] = x;     // temporarily holds V~
             pw += (double)x.x * x.x + (double)x.y * x.y;
           }
-      pw = block_sum(pw, red);
+      pw = block_sum4(pw, red);
       const float sc = (pw > Pc) ? (float)sqrt(Pc / pw) : 1.f;
 #pragma unroll
       for (int i = 0; i < S::VRB; ++i)
@@ -574,9 +732,8 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
         for (int j = 0; j < S::UDB; ++j)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const float2 x = Vq[i][j][r];
+            const float2 x = Vp[i][j][r];
             const float2 vn = c2(sc * x.x, sc * x.y);
-            Vq[i][j][r] = Vp[i][j][r];
             Vp[i][j][r] = vn;
             const int row = 16 * (wave + 4 * i) + 4 * lk + r, col = 16 * j + li;
             Bs[row * S::BLD + col] = vn;
@@ -592,7 +749,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   double wsr_final;
   if (iters_run == T && !status) {
     const double rs = receivers();
-    wsr_final = block_sum(rs, red) * (1.0 / M_LN2);
+    wsr_final = block_sum4(rs, red) * (1.0 / M_LN2);
     if (misc[0]) status |= misc[0];
     if (!isfinite(wsr_final)) status |= AMMSE_INST_NONFINITE;
     if (p.trace && tid == 0) p.trace[(long)b * p.trace_len + T] = wsr_final;
@@ -613,7 +770,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
           Vg[row * UD + col] = v;
         }
       }
-  pw = block_sum(pw, red);
+  pw = block_sum4(pw, red);
   if (pw == 0.0) status |= AMMSE_INST_ZERO_POWER;
   if (tid == 0) {
     p.wsr[b] = wsr_final;
