@@ -740,8 +740,9 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
           }
     }
     __syncthreads();
+    // G^t; the own blocks it leaves in LDS are read back by the same wave, and
+    // the next writer of the product operand comes after further barriers
     product_G();
-    __syncthreads();
     prev_step_stage2 = stage2;
     iters_run = t;
   }
