@@ -60,7 +60,8 @@ struct Shape {
   static constexpr size_t oL = oS + sizeof(double) * 2 * UN;        // la, lb
   static constexpr size_t oR = oL + sizeof(double) * 2 * AMMSE_MAX_LANCZOS;
   static constexpr size_t oVq = oR + sizeof(double) * 8 + 16;      // V^{t-2}, per lane
-  static constexpr size_t bytes = oVq + sizeof(float2) * 256 * VRB * UDB * 4;
+  static constexpr size_t oP2 = oVq + sizeof(float2) * 256 * VRB * UDB * 4;  // Lanczos partials
+  static constexpr size_t bytes = oP2 + sizeof(zd) * 4 * UN;
   // During the step-size computation (between the receivers and the Z build)
   // K = C^H Q C and a float copy of the Lanczos vector alias the
   // product-operand area, the partial products alias C, and the tridiagonal
@@ -280,6 +281,31 @@ __device__ __forceinline__ double wave_tridiag_lmax(double ta, double tb, int m,
   return hi * tmax;
 }
 
+// Value of lane (lane ^ BIT) within the 16-lane row, BIT in {1, 2, 4, 8}.
+template <int BIT>
+__device__ __forceinline__ float xor_lane(float v) {
+  const int u = __float_as_int(v);
+  int r;
+  if (BIT == 1) r = __builtin_amdgcn_mov_dpp(u, 0xB1, 0xF, 0xF, false);        // quad_perm [1,0,3,2]
+  else if (BIT == 2) r = __builtin_amdgcn_mov_dpp(u, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  else if (BIT == 4) r = __builtin_amdgcn_ds_swizzle(u, 0x1F | (4 << 10));     // swizzle xor 4
+  else r = __builtin_amdgcn_mov_dpp(u, 0x128, 0xF, 0xF, false);                // row_ror 8
+  return __int_as_float(r);
+}
+
+// One level of the 16-lane reduce-scatter of 16 complex partial sums: the
+// lane keeps one half of s[0 .. 2 BIT) and adds the partner's copy of it.
+template <int BIT>
+__device__ __forceinline__ void rs_level(float2 (&s)[16], int li) {
+  const bool hi = (li & BIT) != 0;
+#pragma unroll
+  for (int e = 0; e < BIT; ++e) {
+    const float2 keep = hi ? s[e + BIT] : s[e];
+    const float2 send = hi ? s[e] : s[e + BIT];
+    s[e] = c2(keep.x + xor_lane<BIT>(send.x), keep.y + xor_lane<BIT>(send.y));
+  }
+}
+
 template <class S>
 __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   extern __shared__ __align__(16) char smem[];
@@ -295,7 +321,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   double* la = (double*)(smem + S::oL);
   double* lb = la + AMMSE_MAX_LANCZOS;
   double* red = (double*)(smem + S::oR);
-  int* misc = (int*)(red + 8);                 // [0] fail flag, [1] multisection index
+  int* misc = (int*)(red + 8);                 // [0] fail flag, [1], [2] Lanczos stop flags
   zd* Lq = (zd*)Bs;                            // Lanczos vectors (alias, see Shape)
 
   constexpr int M = S::M, UN = S::UN, UD = S::UD;
@@ -428,19 +454,11 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
 #pragma unroll
         for (int c = 0; c < a; ++c) s[a * 4 + c] = c2(s[c * 4 + a].x, -s[c * 4 + a].y);
       // reduce-scatter over the 16 lanes: lane li ends with entry li
-#pragma unroll
-      for (int step = 0; step < 4; ++step) {
-        const int bit = 8 >> step;                 // 8, 4, 2, 1
-        const int half = bit;                      // entries exchanged
-        const bool hi = (li & bit) != 0;
-#pragma unroll
-        for (int e = 0; e < half; ++e) {
-          const float2 keep = hi ? s[e + half] : s[e];
-          const float2 send = hi ? s[e] : s[e + half];
-          const float2 got = c2(__shfl_xor(send.x, bit, 64), __shfl_xor(send.y, bit, 64));
-          s[e] = c2(keep.x + got.x, keep.y + got.y);
-        }
-      }
+      // (partner lane li ^ bit: DPP row_ror 8, swizzle xor 4, DPP quad_perm)
+      rs_level<8>(s, li);
+      rs_level<4>(s, li);
+      rs_level<2>(s, li);
+      rs_level<1>(s, li);
       zd J = {(double)s[0].x, (double)s[0].y};
       if (L4.a == L4.b) J = {J.x + 1.0, 0.0};
       const float2 fo = Fs[(row0 >> 2) * 16 + li];
@@ -451,7 +469,9 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
       if (L4.a == L4.b) X = {X.x + 1.0, 0.0};
       UWr[i] = trsm16h(L4, Lo, F);                // J-^{-1} G_own
       const zd Lw = chol16(L4, X, ok);
-      if (L4.a == L4.b) rsum += alpha[row0 + L4.a] * 2.0 * log(Lw.x);
+      // rate term 2 log Lw_aa in float (the WSR enters only the stage and stop
+      // tests and the reported value, all at FP32 accuracy here)
+      if (L4.a == L4.b) rsum += alpha[row0 + L4.a] * (double)(2.0f * __logf((float)Lw.x));
       const zd Li = trsm16(L4, Lw, zd{(L4.a == L4.b) ? 1.0 : 0.0, 0.0});
       Er[i] = mm_hn(L4, Li, Li);                  // E = Lw^{-H} Lw^{-1}
       Lir[i] = Li;
@@ -460,7 +480,8 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
     return rsum;
   };
 
-  // D = alpha U W U^H and Y = alpha U W per block user, into LDS
+  // S D and S Y per block user (D = alpha U W U^H, Y = alpha U W), and C with
+  // D = C C^H, into LDS
   auto weights = [&](bool stage2) {
 #pragma unroll
     for (int i = 0; i < S::GRB; ++i) {
@@ -471,9 +492,10 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
       const zd Dt = L4.at(Dv, L4.b, L4.a);
       Dv = {0.5 * (Dv.x + Dt.x), 0.5 * (Dv.y - Dt.y)};   // exactly Hermitian
       const double al = alpha[row0 + L4.a];
+      const double ais = al * invsig[row0 + L4.a];   // row scale S folded in for Z
       const int g4 = row0 >> 2;
-      Ds[g4 * 16 + li] = c2((float)(al * Dv.x), (float)(al * Dv.y));
-      Ys[g4 * 16 + li] = c2((float)(al * Ur.x), (float)(al * Ur.y));
+      Ds[g4 * 16 + li] = c2((float)(ais * Dv.x), (float)(ais * Dv.y));
+      Ys[g4 * 16 + li] = c2((float)(ais * Ur.x), (float)(ais * Ur.y));
       // D = C C^H: C = sqrt(alpha) U (stage I) or sqrt(alpha) UW Lw^{-H} (stage II)
       const zd Cv = stage2 ? mm_nh(L4, UWr[i], Lir[i]) : T;
       Cs[g4 * S::CST + li] = scal(sqrt(al), Cv);
@@ -496,7 +518,8 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
     static_assert(sizeof(float2) * UN * UN <= sizeof(float2) * S::BROWS * S::BLD, "K area");
     static_assert(sizeof(zd) * 4 * UN <= sizeof(zd) * S::NG * S::CST, "partial area");
     float2* Kt = Bs;                              // Kt[c * UN + r] = K[r][c]
-    zd* part = (zd*)Cs;                           // [4 waves][UN]
+    zd* part0 = (zd*)Cs;                          // [4 waves][UN], even steps
+    zd* part1 = (zd*)(smem + S::oP2);             // odd steps
     float2* xs = Bs + UN * UN;                    // float copy of x; each wave writes and
                                                   // reads back only its own 16 columns
     double2* tp = (double2*)la;                   // tridiagonal pairs (wave 0)
@@ -556,6 +579,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
     const double ltol = 1e-8;
     double beta_prev = 0.0, tmax = 0.0, theta = 0.0;
     bool stop = false;
+    int jlast = 0;
     for (int j = 0;; ++j) {
       // partial product over this wave's 16 columns in float (K is stored in
       // float), two accumulator pairs, combined in double
@@ -576,14 +600,20 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
         }
       }
       const zd yw = {(double)ya.x + (double)yb.x, (double)ya.y + (double)yb.y};
+      // one barrier per step: partials, the stop flag and theta alternate
+      // between two slots, so a slot is rewritten only after every wave has
+      // passed the barrier that follows its last read
+      zd* part = (j & 1) ? part1 : part0;
       if (tid == 0) {
-        misc[1] = stop ? 1 : 0;
-        red[7] = theta;
+        misc[1 + (j & 1)] = stop ? 1 : 0;
+        red[4 + (j & 1)] = theta;
       }
-      __syncthreads();
-      if (misc[1]) break;
       part[wave * UN + lane] = yw;
       __syncthreads();
+      if (misc[1 + (j & 1)]) {
+        jlast = j;
+        break;
+      }
       const zd y = (part[lane] + part[UN + lane]) + (part[2 * UN + lane] + part[3 * UN + lane]);
       const double al = wave_sum_dpp(x.x * y.x + x.y * y.y);
       const double yy = wave_sum_dpp(nrm2(y));
@@ -609,7 +639,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
         beta_prev = bb;
       }
     }
-    return red[7];
+    return red[4 + (jlast & 1)];
   };
 
   product_G();
@@ -663,7 +693,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
       gamma = p.gamma_c;
     }
 
-    // Z = S (D G^ - Y) from the registers, into Bs
+    // Z = S (D G^ - Y) from the registers (S folded into D and Y), into Bs
     const float om = p.extrapolate ? (float)fmax((t - 2.0) / (t + 1.0), 0.0) : 0.f;
 #pragma unroll
     for (int i = 0; i < S::GRB; ++i) {
@@ -695,8 +725,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
             zx -= y.x;
             zy -= y.y;
           }
-          const float is = (float)invsig[row0 + r];
-          Bs[(row0 + r) * S::BLD + col] = c2(is * zx, is * zy);
+          Bs[(row0 + r) * S::BLD + col] = c2(zx, zy);
         }
       }
     }
