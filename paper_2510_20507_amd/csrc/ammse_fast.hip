@@ -322,7 +322,6 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   double* lb = la + AMMSE_MAX_LANCZOS;
   double* red = (double*)(smem + S::oR);
   int* misc = (int*)(red + 8);                 // [0] fail flag, [1], [2] Lanczos stop flags
-  zd* Lq = (zd*)Bs;                            // Lanczos vectors (alias, see Shape)
 
   constexpr int M = S::M, UN = S::UN, UD = S::UD;
   const ammse_desc_t Dd = p.desc[blockIdx.x];
@@ -347,22 +346,21 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   for (int e = tid; e < M * UD; e += 256) Bs[(e / UD) * S::BLD + (e % UD)] = Vg[e];
   __syncthreads();
 
-  // register state: element [i][j][r] is row 16 (wave + 4 i) + 4 lk + r,
-  // column 16 j + li
-  // V^{t-2} lives in LDS (per lane, entry e of this lane at VqS[e * 256 + tid])
-  float2* VqS = (float2*)(smem + S::oVq);
-  float2 Vp[S::VRB][S::UDB][4];
+  // The precoder is carried implicitly: V^t = c_t V^0 + H^H S X^t with
+  // X^t of the shape of G (U N x U d), so that G^t = S H V^t = c_t G^0 + Q X^t
+  // follows from G^{t-1}, G^{t-2} and one product with Q per iteration
+  // (G^t = s (G^ - 2 gamma Q Z'), X^t = s (X^ - 2 gamma Z'), Z' = D G^ - Y, s
+  // the projection factor); V^T is rebuilt with one product by H^H at the end.
+  // Register state: element [i][j][r] is row 16 (wave + 4 i) + 4 lk + r,
+  // column 16 j + li.  X^{t-2} and G^0 live in LDS per lane (entry e of this
+  // lane at [e * 256 + tid]); G^0 reuses the area of H, which the loop does
+  // not read.
+  float2* XqS = (float2*)(smem + S::oVq);
+  float2* G0S = Hs;
+  static_assert(sizeof(float2) * 256 * S::GRB * S::UDB * 4 <= sizeof(float2) * UN * S::HLD,
+                "G0 area");
+  float2 Xp[S::GRB][S::UDB][4];
   float2 Gp[S::GRB][S::UDB][4], Gq[S::GRB][S::UDB][4];
-#pragma unroll
-  for (int i = 0; i < S::VRB; ++i)
-#pragma unroll
-    for (int j = 0; j < S::UDB; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 16 * (wave + 4 * i) + 4 * lk + r, col = 16 * j + li;
-        Vp[i][j][r] = Bs[row * S::BLD + col];
-        VqS[((i * S::UDB + j) * 4 + r) * 256 + tid] = Vp[i][j][r];
-      }
 
   // Q = S H H^H S for the step-size operator, once per solve
   {
@@ -480,8 +478,8 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
     return rsum;
   };
 
-  // S D and S Y per block user (D = alpha U W U^H, Y = alpha U W), and C with
-  // D = C C^H, into LDS
+  // D = alpha U W U^H and Y = alpha U W per block user, and C with D = C C^H,
+  // into LDS
   auto weights = [&](bool stage2) {
 #pragma unroll
     for (int i = 0; i < S::GRB; ++i) {
@@ -492,10 +490,9 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
       const zd Dt = L4.at(Dv, L4.b, L4.a);
       Dv = {0.5 * (Dv.x + Dt.x), 0.5 * (Dv.y - Dt.y)};   // exactly Hermitian
       const double al = alpha[row0 + L4.a];
-      const double ais = al * invsig[row0 + L4.a];   // row scale S folded in for Z
       const int g4 = row0 >> 2;
-      Ds[g4 * 16 + li] = c2((float)(ais * Dv.x), (float)(ais * Dv.y));
-      Ys[g4 * 16 + li] = c2((float)(ais * Ur.x), (float)(ais * Ur.y));
+      Ds[g4 * 16 + li] = c2((float)(al * Dv.x), (float)(al * Dv.y));
+      Ys[g4 * 16 + li] = c2((float)(al * Ur.x), (float)(al * Ur.y));
       // D = C C^H: C = sqrt(alpha) U (stage I) or sqrt(alpha) UW Lw^{-H} (stage II)
       const zd Cv = stage2 ? mm_nh(L4, UWr[i], Lir[i]) : T;
       Cs[g4 * S::CST + li] = scal(sqrt(al), Cv);
@@ -642,14 +639,32 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
     return red[4 + (jlast & 1)];
   };
 
+  // G^0 = S H V^0 (V^0 in Bs) and nu = ||V^0||^2
   product_G();
-  __syncthreads();
+  double nu = 0.0;
+#pragma unroll
+  for (int i = 0; i < S::VRB; ++i)
+#pragma unroll
+    for (int j = 0; j < S::UDB; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float2 v = Bs[(16 * (wave + 4 * i) + 4 * lk + r) * S::BLD + 16 * j + li];
+        nu += (double)v.x * v.x + (double)v.y * v.y;
+      }
+  nu = block_sum4(nu, red);                    // its barriers also end the reads of H
 #pragma unroll
   for (int i = 0; i < S::GRB; ++i)
 #pragma unroll
     for (int j = 0; j < S::UDB; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Gq[i][j][r] = Gp[i][j][r];
+      for (int r = 0; r < 4; ++r) {
+        const int e = ((i * S::UDB + j) * 4 + r) * 256 + tid;
+        Gq[i][j][r] = Gp[i][j][r];
+        G0S[e] = Gp[i][j][r];
+        Xp[i][j][r] = c2(0.f, 0.f);
+        XqS[e] = c2(0.f, 0.f);
+      }
+  double c1 = 1.0, c2s = 1.0;                  // c_{t-1}, c_{t-2}
 
   const int T = p.wsr_only ? 0 : p.max_iters;
   int fsw = p.force_switch_iter;
@@ -693,7 +708,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
       gamma = p.gamma_c;
     }
 
-    // Z = S (D G^ - Y) from the registers (S folded into D and Y), into Bs
+    // Z' = D G^ - Y from the registers, into Bs (the gradient is 2 H^H S Z')
     const float om = p.extrapolate ? (float)fmax((t - 2.0) / (t + 1.0), 0.0) : 0.f;
 #pragma unroll
     for (int i = 0; i < S::GRB; ++i) {
@@ -731,76 +746,128 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
     }
     __syncthreads();
 
-    // gradient and the extrapolated projected step, in registers
+    // G~ = G^ - 2 gamma Q Z', X~ = X^ - 2 gamma Z', and the projection:
+    // ||V~||^2 = c^2 nu + c Re<G^0, X~> + Re<X~, G~>  (c = c^, exact algebra
+    // of V~ = c V^0 + H^H S X~ with G~ = c G^0 + Q X~)
     {
-      floatx4 P[S::VRB][S::UDB][3];
-      wave_cgemm<S::VRB, S::UDB, UN, true>(Hs, S::HLD, Bs, S::BLD, wave, P);
+      floatx4 P[S::GRB][S::UDB][3];
+      wave_cgemm<S::GRB, S::UDB, UN, false>(Qs, S::QLD, Bs, S::BLD, wave, P);
       const float g2 = (float)(2.0 * gamma);
-      double pw = 0.0;
+      const double ch = (1.0 + om) * c1 - om * c2s;
+      const float chf = (float)ch;
+      double acc = 0.0;
 #pragma unroll
-      for (int i = 0; i < S::VRB; ++i)
+      for (int i = 0; i < S::GRB; ++i)
 #pragma unroll
         for (int j = 0; j < S::UDB; ++j)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const float2 gv = cplx_at(P[i][j], r);
-            const float gx = gv.x, gy = gv.y;
             const int e = ((i * S::UDB + j) * 4 + r) * 256 + tid;
-            const float2 v = Vp[i][j][r], q = VqS[e];
-            const float2 x = c2((1.f + om) * v.x - om * q.x - g2 * gx,
-                                (1.f + om) * v.y - om * q.y - g2 * gy);
-            VqS[e] = v;          // V^{t-1} becomes V^{t-2}
-            Vp[i][j][r] = x;     // temporarily holds V~
-            pw += (double)x.x * x.x + (double)x.y * x.y;
+            const int row = 16 * (wave + 4 * i) + 4 * lk + r, col = 16 * j + li;
+            const float2 pq = cplx_at(P[i][j], r);
+            const float2 gp = Gp[i][j][r], gq = Gq[i][j][r];
+            const float2 gt = c2((1.f + om) * gp.x - om * gq.x - g2 * pq.x,
+                                 (1.f + om) * gp.y - om * gq.y - g2 * pq.y);
+            const float2 xp = Xp[i][j][r], xq = XqS[e], z = Bs[row * S::BLD + col];
+            const float2 xt = c2((1.f + om) * xp.x - om * xq.x - g2 * z.x,
+                                 (1.f + om) * xp.y - om * xq.y - g2 * z.y);
+            const float2 g0 = G0S[e];
+            acc += (double)chf * ((double)g0.x * xt.x + (double)g0.y * xt.y) +
+                   ((double)xt.x * gt.x + (double)xt.y * gt.y);
+            XqS[e] = xp;             // X^{t-1} becomes X^{t-2}
+            Xp[i][j][r] = xt;        // temporarily X~
+            Gq[i][j][r] = gp;
+            Gp[i][j][r] = gt;        // temporarily G~
           }
-      pw = block_sum4(pw, red);
-      const float sc = (pw > Pc) ? (float)sqrt(Pc / pw) : 1.f;
+      const double pw = ch * ch * nu + block_sum4(acc, red);
+      const double scd = (pw > Pc) ? sqrt(Pc / pw) : 1.0;
+      const float sc = (float)scd;
+      c2s = c1;
+      c1 = scd * ch;
 #pragma unroll
-      for (int i = 0; i < S::VRB; ++i)
+      for (int i = 0; i < S::GRB; ++i)
 #pragma unroll
         for (int j = 0; j < S::UDB; ++j)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const float2 x = Vp[i][j][r];
-            const float2 vn = c2(sc * x.x, sc * x.y);
-            Vp[i][j][r] = vn;
             const int row = 16 * (wave + 4 * i) + 4 * lk + r, col = 16 * j + li;
-            Bs[row * S::BLD + col] = vn;
+            Xp[i][j][r] = c2(sc * Xp[i][j][r].x, sc * Xp[i][j][r].y);
+            const float2 g = c2(sc * Gp[i][j][r].x, sc * Gp[i][j][r].y);
+            Gp[i][j][r] = g;
+            const int u = row >> lgN, c = col - (u << lgd);
+            if (c >= 0 && c < d) {
+              const int g4 = row >> 2, u0 = (g4 * 4) >> lgN;
+              Fs[g4 * 16 + r * 4 + ((u - u0) << lgN) + c] = g;
+            }
           }
     }
-    __syncthreads();
-    // G^t; the own blocks it leaves in LDS are read back by the same wave, and
-    // the next writer of the product operand comes after further barriers
-    product_G();
     prev_step_stage2 = stage2;
     iters_run = t;
   }
 
+  // V = c V^0 + H^H S X (the precoder of the last state), projected onto the
+  // power ball exactly, written out; then its WSR from G = S H V.
+  double pw = 0.0;
+  if (!p.wsr_only) {
+    __syncthreads();                           // loop reads of Bs, G^0 and X done
+    for (int e = tid; e < UN * M; e += 256) Hs[(e / M) * S::HLD + (e % M)] = Hg[e];
+#pragma unroll
+    for (int i = 0; i < S::GRB; ++i)
+#pragma unroll
+      for (int j = 0; j < S::UDB; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * (wave + 4 * i) + 4 * lk + r, col = 16 * j + li;
+          const float s = (float)invsig[row];
+          Bs[row * S::BLD + col] = c2(s * Xp[i][j][r].x, s * Xp[i][j][r].y);
+        }
+    __syncthreads();
+    floatx4 P[S::VRB][S::UDB][3];
+    wave_cgemm<S::VRB, S::UDB, UN, true>(Hs, S::HLD, Bs, S::BLD, wave, P);
+    const float cf = (float)c1;
+    float2 vf[S::VRB][S::UDB][4];
+#pragma unroll
+    for (int i = 0; i < S::VRB; ++i)
+#pragma unroll
+      for (int j = 0; j < S::UDB; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * (wave + 4 * i) + 4 * lk + r, col = 16 * j + li;
+          const float2 v0 = Vg[row * UD + col];
+          const float2 hx = cplx_at(P[i][j], r);
+          const float2 v = c2(cf * v0.x + hx.x, cf * v0.y + hx.y);
+          vf[i][j][r] = v;
+          pw += (double)v.x * v.x + (double)v.y * v.y;
+        }
+    pw = block_sum4(pw, red);                  // its barriers also end the reads of Bs
+    const float sc = (pw > Pc) ? (float)sqrt(Pc / pw) : 1.f;
+    if (pw > Pc) pw = Pc;
+#pragma unroll
+    for (int i = 0; i < S::VRB; ++i)
+#pragma unroll
+      for (int j = 0; j < S::UDB; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * (wave + 4 * i) + 4 * lk + r, col = 16 * j + li;
+          const float2 v = c2(sc * vf[i][j][r].x, sc * vf[i][j][r].y);
+          Bs[row * S::BLD + col] = v;
+          Vg[row * UD + col] = v;
+        }
+    __syncthreads();
+    product_G();
+  } else {
+    pw = nu;
+  }
   double wsr_final;
-  if (iters_run == T && !status) {
+  if (!status) {
     const double rs = receivers();
     wsr_final = block_sum4(rs, red) * (1.0 / M_LN2);
     if (misc[0]) status |= misc[0];
     if (!isfinite(wsr_final)) status |= AMMSE_INST_NONFINITE;
-    if (p.trace && tid == 0) p.trace[(long)b * p.trace_len + T] = wsr_final;
+    if (p.trace && tid == 0 && iters_run == T) p.trace[(long)b * p.trace_len + T] = wsr_final;
   } else {
     wsr_final = wsr_prev;
   }
-  double pw = 0.0;
-#pragma unroll
-  for (int i = 0; i < S::VRB; ++i)
-#pragma unroll
-    for (int j = 0; j < S::UDB; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float2 v = Vp[i][j][r];
-        pw += (double)v.x * v.x + (double)v.y * v.y;
-        if (!p.wsr_only) {
-          const int row = 16 * (wave + 4 * i) + 4 * lk + r, col = 16 * j + li;
-          Vg[row * UD + col] = v;
-        }
-      }
-  pw = block_sum4(pw, red);
   if (pw == 0.0) status |= AMMSE_INST_ZERO_POWER;
   if (tid == 0) {
     p.wsr[b] = wsr_final;
