@@ -59,7 +59,7 @@ struct Shape {
   static constexpr size_t oS = oC + sizeof(zd) * NG * CST;          // invsig, alpha per row
   static constexpr size_t oL = oS + sizeof(double) * 2 * UN;        // la, lb
   static constexpr size_t oR = oL + sizeof(double) * 2 * AMMSE_MAX_LANCZOS;
-  static constexpr size_t oVq = oR + sizeof(double) * 8 + 16;      // V^{t-2}, per lane
+  static constexpr size_t oVq = oR + sizeof(double) * 16 + 16;     // X^{t-2}, per lane
   static constexpr size_t oP2 = oVq + sizeof(float2) * 256 * VRB * UDB * 4;  // Lanczos partials
   static constexpr size_t bytes = oP2 + sizeof(zd) * 4 * UN;
   // During the step-size computation (between the receivers and the Z build)
@@ -176,10 +176,11 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
 }
 
 // Sum over the 256-thread block (four waves); every thread receives the
-// same value.  red: four doubles of LDS.
+// same value.  red: four doubles of LDS, which the caller must not hand to
+// another call before every wave has passed a further barrier (one barrier
+// per call).
 __device__ __forceinline__ double block_sum4(double v, double* red) {
   v = wave_sum_dpp(v);
-  __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   return (red[0] + red[1]) + (red[2] + red[3]);
@@ -321,7 +322,9 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   double* la = (double*)(smem + S::oL);
   double* lb = la + AMMSE_MAX_LANCZOS;
   double* red = (double*)(smem + S::oR);
-  int* misc = (int*)(red + 8);                 // [0] fail flag, [1], [2] Lanczos stop flags
+  // red: three slots of four partial sums ([0], [4], [8]; a slot is reused
+  // only across further barriers) and two Lanczos values ([12], [13])
+  int* misc = (int*)(red + 16);                // [0] fail flag, [1], [2] Lanczos stop flags
 
   constexpr int M = S::M, UN = S::UN, UD = S::UD;
   const ammse_desc_t Dd = p.desc[blockIdx.x];
@@ -603,7 +606,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
       zd* part = (j & 1) ? part1 : part0;
       if (tid == 0) {
         misc[1 + (j & 1)] = stop ? 1 : 0;
-        red[4 + (j & 1)] = theta;
+        red[12 + (j & 1)] = theta;
       }
       part[wave * UN + lane] = yw;
       __syncthreads();
@@ -636,7 +639,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
         beta_prev = bb;
       }
     }
-    return red[4 + (jlast & 1)];
+    return red[12 + (jlast & 1)];
   };
 
   // G^0 = S H V^0 (V^0 in Bs) and nu = ||V^0||^2
@@ -651,7 +654,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
         const float2 v = Bs[(16 * (wave + 4 * i) + 4 * lk + r) * S::BLD + 16 * j + li];
         nu += (double)v.x * v.x + (double)v.y * v.y;
       }
-  nu = block_sum4(nu, red);                    // its barriers also end the reads of H
+  nu = block_sum4(nu, red);                    // its barrier also ends the reads of H
 #pragma unroll
   for (int i = 0; i < S::GRB; ++i)
 #pragma unroll
@@ -678,7 +681,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   for (int t = 1; t <= T; ++t) {
     const double rs = receivers();
     wsr_prev2 = wsr_prev;
-    wsr_prev = block_sum4(rs, red) * (1.0 / M_LN2);
+    wsr_prev = block_sum4(rs, red + 4) * (1.0 / M_LN2);
     if (p.trace && tid == 0) p.trace[(long)b * p.trace_len + (t - 1)] = wsr_prev;
     if (misc[0]) {
       status |= misc[0];
@@ -755,7 +758,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
       const float g2 = (float)(2.0 * gamma);
       const double ch = (1.0 + om) * c1 - om * c2s;
       const float chf = (float)ch;
-      double acc = 0.0;
+      float acc = 0.f;
 #pragma unroll
       for (int i = 0; i < S::GRB; ++i)
 #pragma unroll
@@ -772,14 +775,13 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
             const float2 xt = c2((1.f + om) * xp.x - om * xq.x - g2 * z.x,
                                  (1.f + om) * xp.y - om * xq.y - g2 * z.y);
             const float2 g0 = G0S[e];
-            acc += (double)chf * ((double)g0.x * xt.x + (double)g0.y * xt.y) +
-                   ((double)xt.x * gt.x + (double)xt.y * gt.y);
+            acc += chf * (g0.x * xt.x + g0.y * xt.y) + (xt.x * gt.x + xt.y * gt.y);
             XqS[e] = xp;             // X^{t-1} becomes X^{t-2}
             Xp[i][j][r] = xt;        // temporarily X~
             Gq[i][j][r] = gp;
             Gp[i][j][r] = gt;        // temporarily G~
           }
-      const double pw = ch * ch * nu + block_sum4(acc, red);
+      const double pw = ch * ch * nu + block_sum4((double)acc, red + 8);
       const double scd = (pw > Pc) ? sqrt(Pc / pw) : 1.0;
       const float sc = (float)scd;
       c2s = c1;
@@ -839,7 +841,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
           vf[i][j][r] = v;
           pw += (double)v.x * v.x + (double)v.y * v.y;
         }
-    pw = block_sum4(pw, red);                  // its barriers also end the reads of Bs
+    pw = block_sum4(pw, red);                  // its barrier also ends the reads of Bs
     const float sc = (pw > Pc) ? (float)sqrt(Pc / pw) : 1.f;
     if (pw > Pc) pw = Pc;
 #pragma unroll
@@ -861,7 +863,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   double wsr_final;
   if (!status) {
     const double rs = receivers();
-    wsr_final = block_sum4(rs, red) * (1.0 / M_LN2);
+    wsr_final = block_sum4(rs, red + 4) * (1.0 / M_LN2);
     if (misc[0]) status |= misc[0];
     if (!isfinite(wsr_final)) status |= AMMSE_INST_NONFINITE;
     if (p.trace && tid == 0 && iters_run == T) p.trace[(long)b * p.trace_len + T] = wsr_final;
