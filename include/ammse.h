@@ -144,7 +144,11 @@ typedef struct ammse_options_t {
   int32_t refine_iters;      /* AMMSE_PREC_BF16: final iterations with float products
                                 (the refinement pass); ignored otherwise */
   int32_t algorithm;         /* AMMSE_ALGO_AMMMSE (Algorithm 3), _WMMSE or _MMMSE */
-  int32_t reserved;          /* must be 0 */
+  int32_t tile;              /* output tile shape of the MFMA channel products of the
+                                general kernel (FP32 and BF16): 0 = the plan's choice
+                                (shape 0 until ammse_autotune picks one per shape
+                                class); 1, 2, 3 = force shape 0, 1, 2 (64 x 64,
+                                128 x 16, 64 x 32) for every instance */
   double eps1;               /* stage-switch tolerance (paper: 0.1) */
   double eps2;               /* stop tolerance (0: run exactly max_iters) */
   double gamma_c;            /* > 0: fixed step after the adaptive window;
@@ -197,6 +201,29 @@ ammse_status_t ammse_plan_workspace_size(ammse_plan_t plan, size_t* bytes);
 #define AMMSE_KERNEL_LDS_MFMA 0  /* LDS-resident, MFMA FP32 channel products */
 #define AMMSE_KERNEL_GENERAL 1   /* any shape; workspace-resident state */
 ammse_status_t ammse_plan_info(ammse_plan_t plan, int32_t* kernel, size_t* lds_bytes);
+
+/*
+ * Tile-shape autotuner of the general kernel's MFMA channel products.  The
+ * instances of the plan fall into three shape classes by the widest
+ * precoder block of one cell, n = max_c U_c d (the column count of the
+ * products G_c = H_{:,c} V_c and 2 H_{:,c}^H Z_c): n <= 16, 16 < n <= 32,
+ * n > 32.  For every class present, a sample of at most 64 of its instances
+ * is solved (a few iterations, on a scratch copy of V) with each output tile
+ * shape (0: 64 x 64, 1: 128 x 16, 2: 64 x 32), timed with HIP events on
+ * `stream`, and the fastest shape is kept in the plan for every instance of
+ * the class; later ammse_solve / ammse_wsr calls with options.tile = 0 use
+ * it.  Arguments as for ammse_solve (V is only read); choice: host int32[3]
+ * (may be NULL) receives the shape picked per class, -1 for an absent class.
+ * Plans without MFMA tile choices (the LDS-resident kernel, FP64) return
+ * AMMSE_OK with every choice -1.  Blocks until the trials have run;
+ * allocates and frees temporary device memory (AMMSE_ERR_ALLOC on failure).
+ * The results of a solve do not depend on the tile shape up to the
+ * summation order of the products.
+ */
+ammse_status_t ammse_autotune(ammse_plan_t plan, const void* H, const double* sigma2,
+                              const double* alpha, const double* P, const void* V,
+                              void* workspace, size_t workspace_bytes, int32_t* choice,
+                              ammse_stream_t stream);
 
 /* Release the plan's device tables.  NULL is accepted. */
 ammse_status_t ammse_plan_destroy(ammse_plan_t plan);

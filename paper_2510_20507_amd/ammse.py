@@ -35,7 +35,7 @@ INST_ZERO_POWER = 4
 EXPORTED = ("ammse_version", "ammse_status_string", "ammse_default_options", "ammse_validate",
             "ammse_plan_create", "ammse_plan_workspace_size", "ammse_plan_destroy",
             "ammse_solve", "ammse_wsr", "ammse_plan_info", "ammse_unrolled_workspace_size",
-            "ammse_unrolled_forward", "ammse_unrolled_backward")
+            "ammse_unrolled_forward", "ammse_unrolled_backward", "ammse_autotune")
 KERNEL_LDS_MFMA = 0
 KERNEL_GENERAL = 1
 
@@ -53,7 +53,7 @@ class AmmseOptions(ctypes.Structure):
                 ("extrapolate", ctypes.c_int32), ("rearm_at_switch", ctypes.c_int32),
                 ("force_switch_iter", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32),
                 ("path", ctypes.c_int32), ("refine_iters", ctypes.c_int32),
-                ("algorithm", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("algorithm", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("eps1", ctypes.c_double), ("eps2", ctypes.c_double), ("gamma_c", ctypes.c_double)]
 
 
@@ -97,6 +97,8 @@ def lib() -> ctypes.CDLL:
     L.ammse_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.ammse_wsr.restype = i32
     L.ammse_wsr.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.ammse_autotune.restype = i32
+    L.ammse_autotune.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, P(i32), vp]
     L.ammse_unrolled_workspace_size.restype = i32
     L.ammse_unrolled_workspace_size.argtypes = [vp, i32, P(sz), P(sz)]
     L.ammse_unrolled_forward.restype = i32
@@ -135,7 +137,7 @@ class Options:
     path: int = 0
     refine_iters: int = 10
     algorithm: int = ALGO_AMMMSE
-    reserved: int = 0
+    tile: int = 0            # 0: plan's (autotuned) tile shapes; v + 1: force shape v
     eps1: float = 0.1
     eps2: float = 0.0
     gamma_c: float = 0.0
@@ -268,6 +270,21 @@ class Plan:
             int(ckpt_every), _ptr(switch_iter), _ptr(ckpt), _ptr(dwsr), _ptr(dH), _ptr(dgamma),
             _ptr(workspace), workspace.numel() * workspace.element_size(), stream)
         _check(code, "ammse_unrolled_backward")
+
+    def autotune(self, H, sigma2, alpha, P, V, workspace=None, stream=None) -> list:
+        """ammse_autotune on device tensors (V is only read); returns the tile
+        shape picked per shape class (-1: class absent or nothing to tune)."""
+        import torch
+        if workspace is None:
+            workspace = self.workspace()
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        choice = (ctypes.c_int32 * 3)()
+        code = lib().ammse_autotune(self._handle, _ptr(H), _ptr(sigma2), _ptr(alpha), _ptr(P),
+                                    _ptr(V), _ptr(workspace),
+                                    workspace.numel() * workspace.element_size(), choice, stream)
+        _check(code, "ammse_autotune")
+        return [int(c) for c in choice]
 
     def wsr(self, H, sigma2, alpha, V, wsr, workspace=None, stream=None):
         """ammse_wsr on device tensors."""

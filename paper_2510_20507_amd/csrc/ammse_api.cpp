@@ -23,6 +23,10 @@ struct ammse_plan_s {
   bool h_disjoint = true;      // channel blocks do not overlap (dH is written)
   int64_t v_elems = 0;         // minimum length of V (complex elements)
   std::vector<std::array<int32_t, 4>> shapes;   // (U, M, N, d) per instance
+  // autotuned tile shapes: host copy of the descriptors (launch order) and
+  // the shape class of each launch position
+  std::vector<ammse_desc_t> h_desc;
+  std::vector<int8_t> tile_class;
 };
 
 namespace {
@@ -44,10 +48,10 @@ ammse_status_t check_options(const ammse_options_t& o) {
   if (o.lanczos_steps < 0 || o.lanczos_steps > AMMSE_MAX_LANCZOS) return AMMSE_ERR_OPTION;
   if (o.path != AMMSE_PATH_AUTO && o.path != AMMSE_PATH_GENERAL) return AMMSE_ERR_OPTION;
   if (o.refine_iters < 0) return AMMSE_ERR_OPTION;
+  if (o.tile < 0 || o.tile > 3) return AMMSE_ERR_OPTION;
   if (o.algorithm != AMMSE_ALGO_AMMMSE && o.algorithm != AMMSE_ALGO_WMMSE &&
       o.algorithm != AMMSE_ALGO_MMMSE)
     return AMMSE_ERR_OPTION;
-  if (o.reserved != 0) return AMMSE_ERR_OPTION;
   if (o.algorithm != AMMSE_ALGO_AMMMSE && o.precision == AMMSE_PREC_BF16)
     return AMMSE_ERR_UNSUPPORTED;
   if (!(o.eps1 >= 0.0) || !(o.eps2 >= 0.0)) return AMMSE_ERR_OPTION;
@@ -90,7 +94,7 @@ void ammse_default_options(ammse_options_t* opt) {
   opt->path = AMMSE_PATH_AUTO;
   opt->refine_iters = 10;
   opt->algorithm = AMMSE_ALGO_AMMMSE;
-  opt->reserved = 0;
+  opt->tile = 0;
   opt->eps1 = 0.1;
   opt->eps2 = 0.0;
   opt->gamma_c = 0.0;
@@ -198,7 +202,7 @@ ammse_status_t ammse_plan_create(ammse_plan_t* plan, int32_t device,
     d.un = t.U * t.N;
     d.ud = t.U * t.d;
     d.b = order[k];
-    d.pad = 0;
+    d.tile = 0;
     d.h_off = t.h_off;
     d.v_off = t.v_off;
     d.user_off = t.user_off;
@@ -234,6 +238,14 @@ ammse_status_t ammse_plan_create(ammse_plan_t* plan, int32_t device,
   P->opt = o;
   P->opt.lanczos_steps = ls;
   P->ws_bytes = std::max<size_t>(off, 256);
+  P->h_desc = desc;
+  P->tile_class.resize(batch);
+  for (int32_t k = 0; k < batch; ++k) {
+    const ammse_instance_t& t = table[order[k]];
+    int32_t n = 0;
+    for (int c = 0; c < t.C; ++c) n = std::max(n, cell_users[(int64_t)t.cell_off + c] * t.d);
+    P->tile_class[k] = (int8_t)((n <= 16) ? 0 : (n <= 32) ? 1 : 2);
+  }
   if (hipMalloc(&P->d_desc, sizeof(ammse_desc_t) * batch) != hipSuccess ||
       hipMalloc(&P->d_cell_users, sizeof(int32_t) * std::max<int64_t>(ncu, 1)) != hipSuccess) {
     if (P->d_desc) (void)hipFree(P->d_desc);
@@ -303,6 +315,7 @@ static void fill_common(ammse_plan_t plan, ammse_kparams_t& k) {
   k.lowp_iters = (o.precision == AMMSE_PREC_BF16) ? std::max(0, o.max_iters - o.refine_iters) : -1;
   k.algorithm = o.algorithm;
   k.bf16_copies = o.precision == AMMSE_PREC_BF16;
+  k.tile_force = o.tile;
 }
 
 ammse_status_t ammse_solve(ammse_plan_t plan, const void* H, const double* sigma2,
@@ -351,6 +364,113 @@ ammse_status_t ammse_wsr(ammse_plan_t plan, const void* H, const double* sigma2,
   k.trace_len = 1;
   k.lowp_iters = -1;   // the WSR of V is evaluated with float products
   return launch(plan, k, (hipStream_t)stream);
+}
+
+ammse_status_t ammse_autotune(ammse_plan_t plan, const void* H, const double* sigma2,
+                              const double* alpha, const double* P, const void* V,
+                              void* workspace, size_t workspace_bytes, int32_t* choice,
+                              ammse_stream_t stream) {
+  if (choice)
+    for (int c = 0; c < 3; ++c) choice[c] = -1;
+  if (!plan || !H || !sigma2 || !alpha || !P || !V || !workspace) return AMMSE_ERR_NULL;
+  if (workspace_bytes < plan->ws_bytes) return AMMSE_ERR_WORKSPACE;
+  if (((uintptr_t)workspace & 255) != 0) return AMMSE_ERR_WORKSPACE;
+  if (plan->use_fast || plan->opt.precision == AMMSE_PREC_FP64) return AMMSE_OK;
+  if (hipSetDevice(plan->device) != hipSuccess) return AMMSE_ERR_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t vbytes = (size_t)plan->v_elems * 2 * sizeof(float);
+  const int32_t nsample_max = 64;
+  void* Vs = nullptr;
+  double* wsr = nullptr;
+  ammse_desc_t* dd = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ammse_status_t st = AMMSE_OK;
+  auto cleanup = [&]() {
+    if (Vs) (void)hipFree(Vs);
+    if (wsr) (void)hipFree(wsr);
+    if (dd) (void)hipFree(dd);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if (hipMalloc(&Vs, std::max<size_t>(vbytes, 16)) != hipSuccess ||
+      hipMalloc((void**)&wsr, sizeof(double) * plan->batch) != hipSuccess ||
+      hipMalloc((void**)&dd, sizeof(ammse_desc_t) * nsample_max) != hipSuccess) {
+    cleanup();
+    return AMMSE_ERR_ALLOC;
+  }
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return AMMSE_ERR_HIP;
+  }
+  int32_t picked[3] = {-1, -1, -1};
+  for (int cls = 0; cls < 3 && st == AMMSE_OK; ++cls) {
+    std::vector<int32_t> pos;
+    for (int32_t k = 0; k < plan->batch; ++k)
+      if (plan->tile_class[k] == cls) pos.push_back(k);
+    if (pos.empty()) continue;
+    // evenly spaced sample of the class (launch order is by decreasing work)
+    std::vector<ammse_desc_t> sample;
+    const size_t ns = std::min<size_t>(pos.size(), nsample_max);
+    for (size_t q = 0; q < ns; ++q) sample.push_back(plan->h_desc[pos[q * pos.size() / ns]]);
+    float best_ms = 0.f;
+    for (int v = 0; v < AMMSE_TILE_SHAPES && st == AMMSE_OK; ++v) {
+      for (auto& d : sample) d.tile = v;
+      if (hipMemcpyAsync(dd, sample.data(), sizeof(ammse_desc_t) * ns, hipMemcpyHostToDevice, s) !=
+          hipSuccess) {
+        st = AMMSE_ERR_HIP;
+        break;
+      }
+      ammse_kparams_t k;
+      fill_common(plan, k);
+      k.desc = dd;
+      k.batch = (int32_t)ns;
+      k.max_iters = std::min(plan->opt.max_iters, 8);
+      k.trace_len = k.max_iters + 1;
+      if (k.lowp_iters >= 0) k.lowp_iters = std::max(0, k.max_iters - std::min(plan->opt.refine_iters, 2));
+      k.tile_force = 0;
+      k.H = H;
+      k.sigma2 = sigma2;
+      k.alpha = alpha;
+      k.P = P;
+      k.V = Vs;
+      k.wsr = wsr;
+      k.ws = (char*)workspace;
+      float ms = 0.f;
+      for (int rep = 0; rep < 3 && st == AMMSE_OK; ++rep) {   // one warm-up, two timed
+        if (hipMemcpyAsync(Vs, V, vbytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            hipEventRecord(e0, s) != hipSuccess) {
+          st = AMMSE_ERR_HIP;
+          break;
+        }
+        st = launch(plan, k, s);
+        if (st != AMMSE_OK) break;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          st = AMMSE_ERR_HIP;
+          break;
+        }
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+          st = AMMSE_ERR_HIP;
+          break;
+        }
+        if (rep == 1 || (rep == 2 && t < ms)) ms = t;
+      }
+      if (st == AMMSE_OK && (picked[cls] < 0 || ms < best_ms)) {
+        picked[cls] = v;
+        best_ms = ms;
+      }
+    }
+    if (st == AMMSE_OK)
+      for (int32_t k : pos) plan->h_desc[k].tile = picked[cls];
+  }
+  if (st == AMMSE_OK &&
+      hipMemcpy(plan->d_desc, plan->h_desc.data(), sizeof(ammse_desc_t) * plan->batch,
+                hipMemcpyHostToDevice) != hipSuccess)
+    st = AMMSE_ERR_HIP;
+  cleanup();
+  if (st == AMMSE_OK && choice)
+    for (int c = 0; c < 3; ++c) choice[c] = picked[c];
+  return st;
 }
 
 static ammse_status_t unroll_check(ammse_plan_t plan, int32_t ckpt_every) {

@@ -18,31 +18,47 @@ __device__ __forceinline__ int phase_tid() {
   return x;
 }
 
-constexpr int KC = 16;   // k-chunk of the channel products
-constexpr int TM = 64;   // output tile rows
-constexpr int TN = 64;   // output tile columns
+constexpr int KC = 16;   // k-chunk of the FP64 channel products
+constexpr int TM = 64;   // FP64 output tile rows
+constexpr int TN = 64;   // FP64 output tile columns
 
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
-template <class T>
+// Output tile shapes of the MFMA channel products (the autotuned choice):
+//   0: 64 x 64  (each wave one 16-row block, four 16-column blocks)
+//   1: 128 x 16 (each wave two 16-row blocks, one column block) for the
+//      tall, narrow products of instances with few streams per cell
+//   2: 64 x 32  (each wave one row block, two column blocks)
+static_assert(AMMSE_TILE_SHAPES == 3, "tile shapes below");
+template <int V> struct TileShape;
+template <> struct TileShape<0> { static constexpr int TM = 64, TN = 64; };
+template <> struct TileShape<1> { static constexpr int TM = 128, TN = 16; };
+template <> struct TileShape<2> { static constexpr int TM = 64, TN = 32; };
+
+template <class T, int V>
 struct MfmaTile {
   static constexpr bool LOW = sizeof(T) == 2;
+  static constexpr int TM = TileShape<V>::TM, TN = TileShape<V>::TN;
+  static constexpr int RB = TM / 64, CB = TN / 16;  // 16 x 16 blocks per wave
   static constexpr int KC = LOW ? 32 : 16;          // k-chunk
   static constexpr int LD = LOW ? KC + 8 : KC + 1;  // padded k stride (elements)
   static constexpr int NA = TM * KC / AMMSE_BLOCK;  // staged A elements per thread
   static constexpr int NB = KC * TN / AMMSE_BLOCK;
   static constexpr size_t bytes = sizeof(T) * 2 * (TM + TN) * LD;
+  static_assert(NA >= 1 && NB >= 1, "every thread stages one element of each operand");
 };
 
+constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 
 template <class R>
 constexpr size_t tile_bytes() {
   if constexpr (sizeof(R) == 8) {
     return sizeof(cx<R>) * KC * (TM + 1 + TN + 1);
   } else {
-    return MfmaTile<float>::bytes > MfmaTile<__bf16>::bytes ? MfmaTile<float>::bytes
-                                                             : MfmaTile<__bf16>::bytes;
+    return cmax(cmax(cmax(MfmaTile<float, 0>::bytes, MfmaTile<__bf16, 0>::bytes),
+                     cmax(MfmaTile<float, 1>::bytes, MfmaTile<__bf16, 1>::bytes)),
+                cmax(MfmaTile<float, 2>::bytes, MfmaTile<__bf16, 2>::bytes));
   }
 }
 
@@ -125,8 +141,9 @@ __device__ void block_gemm(int m, int n, int k, const cx<R>* __restrict__ A, lon
 // planes, k contiguous per row / column, converted to T on the way in); the
 // global loads of the next k-chunk are issued before the current chunk's
 // products so that their latency overlaps the MFMA work.  Each of the four
-// waves owns a 16-row strip of the 64 x 64 output tile; a complex product is
-// three real accumulators (Re Re, Im Im, Re Im + Im Re).
+// waves owns a strip of RB 16-row blocks of the output tile and its CB
+// 16-column blocks; a complex product is three real accumulators (Re Re,
+// Im Im, Re Im + Im Re).
 // Complex bfloat16 in memory (operand copies of the mixed-precision mode).
 struct alignas(4) bfc {   // one 32-bit word per complex element
   __bf16 x, y;
@@ -137,11 +154,12 @@ __device__ __forceinline__ bfc to_bfc(const cx<float>& v) { return {(__bf16)v.x,
 
 // Operands are float or bfloat16 complex in memory (TA, TB); either way they
 // are converted to T on the way into LDS.
-template <class T, bool CONJA, bool CONJB, class Epi, class TA, class TB>
+template <class T, int VAR, bool CONJA, bool CONJB, class Epi, class TA, class TB>
 __device__ void block_gemm_mfma(int m, int n, int k, const TA* __restrict__ A, long lda,
                                 const TB* __restrict__ B, long ldb, char* lds, Epi&& epi) {
-  using Tl = MfmaTile<T>;
+  using Tl = MfmaTile<T, VAR>;
   constexpr int KC = Tl::KC, LD = Tl::LD, NA = Tl::NA, NB = Tl::NB;
+  constexpr int TM = Tl::TM, TN = Tl::TN, RB = Tl::RB, CB = Tl::CB;
   T* AsR = (T*)lds;
   T* AsI = AsR + TM * LD;
   T* BsR = AsI + TM * LD;
@@ -193,15 +211,17 @@ __device__ void block_gemm_mfma(int m, int n, int k, const TA* __restrict__ A, l
       if (gj < n && gk < k) rb[q] = CONJB ? B[(long)gj * ldb + gk] : B[(long)gk * ldb + gj];
     }
   };
-  floatx4_t P[4][3];
+  floatx4_t P[RB][CB][3];
   fetch(0);
   for (int s = 0; s < steps; ++s) {
     const int tile = s / nk, kc = s - tile * nk;
     if (kc == 0) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int i = 0; i < RB; ++i)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) P[j][q] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < CB; ++j)
+#pragma unroll
+          for (int q = 0; q < 3; ++q) P[i][j][q] = floatx4_t{0.f, 0.f, 0.f, 0.f};
     }
     __syncthreads();   // the previous chunk's products are done with the tiles
 #pragma unroll
@@ -223,72 +243,100 @@ __device__ void block_gemm_mfma(int m, int n, int k, const TA* __restrict__ A, l
     __syncthreads();
     if (s + 1 < steps) fetch(s + 1);
     if constexpr (Tl::LOW) {
-      const int ar = (16 * wave + li) * LD + 8 * lk;
-      const bf16x8_t axr = *(const bf16x8_t*)(AsR + ar), axi = *(const bf16x8_t*)(AsI + ar);
-      bf16x8_t bxr[4], bxi[4];
+      bf16x8_t axr[RB], axi[RB], bxr[CB], bxi[CB];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int i = 0; i < RB; ++i) {
+        const int ar = (16 * (RB * wave + i) + li) * LD + 8 * lk;
+        axr[i] = *(const bf16x8_t*)(AsR + ar);
+        axi[i] = *(const bf16x8_t*)(AsI + ar);
+      }
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
         const int br = (16 * j + li) * LD + 8 * lk;
         bxr[j] = *(const bf16x8_t*)(BsR + br);
         bxi[j] = *(const bf16x8_t*)(BsI + br);
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        P[j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(axr, bxr[j], P[j][0], 0, 0, 0);
-        P[j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(axi, bxi[j], P[j][1], 0, 0, 0);
-        P[j][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(axr, bxi[j], P[j][2], 0, 0, 0);
-        P[j][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(axi, bxr[j], P[j][2], 0, 0, 0);
-      }
+      for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+          P[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(axr[i], bxr[j], P[i][j][0], 0, 0, 0);
+          P[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(axi[i], bxi[j], P[i][j][1], 0, 0, 0);
+          P[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(axr[i], bxi[j], P[i][j][2], 0, 0, 0);
+          P[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(axi[i], bxr[j], P[i][j][2], 0, 0, 0);
+        }
     } else {
 #pragma unroll
       for (int kk = 0; kk < KC; kk += 4) {
-        const int ar = (16 * wave + li) * LD + kk + lk;
-        const float axr = AsR[ar], axi = AsI[ar];
-        float bxr[4], bxi[4];
+        float axr[RB], axi[RB], bxr[CB], bxi[CB];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int i = 0; i < RB; ++i) {
+          const int ar = (16 * (RB * wave + i) + li) * LD + kk + lk;
+          axr[i] = AsR[ar];
+          axi[i] = AsI[ar];
+        }
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
           const int br = (16 * j + li) * LD + kk + lk;
           bxr[j] = BsR[br];
           bxi[j] = BsI[br];
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          P[j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(axr, bxr[j], P[j][0], 0, 0, 0);
-          P[j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(axi, bxi[j], P[j][1], 0, 0, 0);
-          P[j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(axr, bxi[j], P[j][2], 0, 0, 0);
-          P[j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(axi, bxr[j], P[j][2], 0, 0, 0);
-        }
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+          for (int j = 0; j < CB; ++j) {
+            P[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(axr[i], bxr[j], P[i][j][0], 0, 0, 0);
+            P[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(axi[i], bxi[j], P[i][j][1], 0, 0, 0);
+            P[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(axr[i], bxi[j], P[i][j][2], 0, 0, 0);
+            P[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(axi[i], bxr[j], P[i][j][2], 0, 0, 0);
+          }
       }
     }
     if (kc == nk - 1) {
       const int i0 = (tile / ntn) * TM, j0 = (tile % ntn) * TN;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gi = i0 + 16 * wave + 4 * lk + r;
-        if (gi >= m) continue;
+      for (int i = 0; i < RB; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int gj = j0 + 16 * j + li;
-          if (gj < n) epi(gi, gj, cx<float>{P[j][0][r] - P[j][1][r], P[j][2][r]});
+        for (int r = 0; r < 4; ++r) {
+          const int gi = i0 + 16 * (RB * wave + i) + 4 * lk + r;
+          if (gi >= m) continue;
+#pragma unroll
+          for (int j = 0; j < CB; ++j) {
+            const int gj = j0 + 16 * j + li;
+            if (gj < n) epi(gi, gj, cx<float>{P[i][j][0][r] - P[i][j][1][r], P[i][j][2][r]});
+          }
         }
-      }
     }
   }
   __syncthreads();
 }
 
+// MFMA product with the tile shape chosen at run time (uniform per workgroup).
+template <class T, bool CONJA, bool CONJB, class Epi, class TA, class TB>
+__device__ __forceinline__ void mfma_dispatch(int m, int n, int k, const TA* A, long lda,
+                                              const TB* B, long ldb, char* tiles, int tile,
+                                              Epi&& epi) {
+  if (tile == 1)
+    block_gemm_mfma<T, 1, CONJA, CONJB>(m, n, k, A, lda, B, ldb, tiles, epi);
+  else if (tile == 2)
+    block_gemm_mfma<T, 2, CONJA, CONJB>(m, n, k, A, lda, B, ldb, tiles, epi);
+  else
+    block_gemm_mfma<T, 0, CONJA, CONJB>(m, n, k, A, lda, B, ldb, tiles, epi);
+}
+
 // Channel product dispatch: MFMA for FP32 storage (bfloat16 products when
-// lowp), LDS-tiled FMA for FP64.
+// lowp; tile: output tile shape, see TileShape), LDS-tiled FMA for FP64.
 template <class R, bool CONJA, bool CONJB = false, class Epi>
 __device__ __forceinline__ void channel_gemm(int m, int n, int k, const cx<R>* A, long lda,
                                              const cx<R>* B, long ldb, char* tiles, bool lowp,
-                                             Epi&& epi) {
+                                             int tile, Epi&& epi) {
   if constexpr (sizeof(R) == 4) {
     if (lowp)
-      block_gemm_mfma<__bf16, CONJA, CONJB>(m, n, k, A, lda, B, ldb, tiles, epi);
+      mfma_dispatch<__bf16, CONJA, CONJB>(m, n, k, A, lda, B, ldb, tiles, tile, epi);
     else
-      block_gemm_mfma<float, CONJA, CONJB>(m, n, k, A, lda, B, ldb, tiles, epi);
+      mfma_dispatch<float, CONJA, CONJB>(m, n, k, A, lda, B, ldb, tiles, tile, epi);
   } else {
+    (void)tile;
     cx<R>* As = (cx<R>*)tiles;
     block_gemm<R, CONJA, CONJB>(m, n, k, A, lda, B, ldb, As, As + KC * (TM + 1), epi);
   }
@@ -297,8 +345,9 @@ __device__ __forceinline__ void channel_gemm(int m, int n, int k, const cx<R>* A
 // Mixed-precision products from bfloat16 copies of both operands.
 template <bool CONJA, class Epi>
 __device__ __forceinline__ void channel_gemm_bf16(int m, int n, int k, const bfc* A, long lda,
-                                                  const bfc* B, long ldb, char* tiles, Epi&& epi) {
-  block_gemm_mfma<__bf16, CONJA, false>(m, n, k, A, lda, B, ldb, tiles, epi);
+                                                  const bfc* B, long ldb, char* tiles, int tile,
+                                                  Epi&& epi) {
+  mfma_dispatch<__bf16, CONJA, false>(m, n, k, A, lda, B, ldb, tiles, tile, epi);
 }
 
 }  // namespace ammse_dev

@@ -13,7 +13,7 @@ struct ammse_desc_t {
   int32_t un;   // U*N: rows of a stacked channel H_{:,c}
   int32_t ud;   // U*d: columns of all precoders together
   int32_t b;    // index of the instance in the caller's table
-  int32_t pad;
+  int32_t tile; // output tile shape of the MFMA channel products (0, 1, 2)
   int64_t h_off, v_off, user_off, bs_off;
   int64_t ws_off;  // byte offset of the instance workspace
 };
@@ -67,10 +67,12 @@ struct ammse_kparams_t {
   int32_t bf16_copies;   // BF16 mode: the workspace holds bfloat16 operand copies
   int32_t lowp_iters;    // BF16 mode: iterations 1..lowp_iters use bfloat16 products
                          // (and G^0 when lowp_iters >= 1); -1: float products only
+  int32_t tile_force;    // 0: per-instance tile shape from the descriptor; v + 1: shape v
   double eps1, eps2, gamma_c;
 };
 
 #define AMMSE_BLOCK 256
+#define AMMSE_TILE_SHAPES 3   // output tile shapes of the MFMA channel products
 #define AMMSE_MAX_LANCZOS 64
 
 // Workspace layout of one instance (bytes), for complex storage of

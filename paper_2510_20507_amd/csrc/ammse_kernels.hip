@@ -64,6 +64,9 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   __shared__ Smem<R> sm;
   extern __shared__ __align__(16) char dyn_lds[];   // WMMSE / MMMSE: Cholesky factor
   const ammse_desc_t D = p.desc[blockIdx.x];
+  // output tile shape of the channel products: forced by the options, else
+  // the plan's (autotuned) choice for this instance's shape class
+  const int tile = (p.tile_force > 0) ? p.tile_force - 1 : D.tile;
   const int tid = threadIdx.x;
   const int C = D.C, U = D.U, M = D.M, N = D.N, d = D.d, un = D.un;
   const int b = D.b;
@@ -142,12 +145,12 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       if constexpr (sizeof(R) == 4) {
         if (lowp && copies) {   // bfloat16 copies of H and of X (the current precoder)
           channel_gemm_bf16<false>(un, nc, M, Hb + (long)c * un * M, M,
-                                   Xb + (long)M * sm.colOff[c], nc, sm.tiles, epi);
+                                   Xb + (long)M * sm.colOff[c], nc, sm.tiles, tile, epi);
           continue;
         }
       }
       channel_gemm<R, false>(un, nc, M, H + (long)c * un * M, M, X + (long)M * sm.colOff[c], nc,
-                             sm.tiles, lowp, epi);
+                             sm.tiles, lowp, tile, epi);
     }
   };
 
@@ -749,7 +752,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   }
   __syncthreads();
   if (qpath && !p.wsr_only) {   // Q = S H H^H S (float products), made exactly Hermitian
-    channel_gemm<R, false, true>(un, un, M, H, M, H, M, sm.tiles, false,
+    channel_gemm<R, false, true>(un, un, M, H, M, H, M, sm.tiles, false, tile,
                                  [&](int i, int j, cx<R> v) {
                                    const R f = (R)(sm.invsig[i / N] * sm.invsig[j / N]);
                                    Qm[(long)i * un + j] = {f * v.x, f * v.y};
@@ -935,13 +938,13 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       if constexpr (sizeof(R) == 4) {
         if (bcopy) {
           channel_gemm_bf16<true>(M, nc, un, Hb + (long)c * un * M, M,
-                                  Zb + (long)un * sm.colOff[c], nc, sm.tiles, epi);
+                                  Zb + (long)un * sm.colOff[c], nc, sm.tiles, tile, epi);
           done = true;
         }
       }
       if (!done)
         channel_gemm<R, true>(M, nc, un, H + (long)c * un * M, M, Z + (long)un * sm.colOff[c], nc,
-                              sm.tiles, lowp, epi);
+                              sm.tiles, lowp, tile, epi);
       pw = block_sum(pw, sm.red);
       if (tid == 0) {
         sm.sprev[c] = sm.scur[c];

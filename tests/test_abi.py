@@ -28,7 +28,7 @@ def L():
 
 def test_every_declared_symbol_is_exported(L):
     names = _declared_functions()
-    assert len(names) == 13
+    assert len(names) == 14
     assert set(names) == set(ammse.EXPORTED)
     for n in names:
         assert hasattr(L, n), n
@@ -46,6 +46,7 @@ def test_struct_layout_matches_header():
     assert ammse.AmmseInstance.h_off.offset == 24
     assert ctypes.sizeof(ammse.AmmseOptions) == 72
     assert ammse.AmmseOptions.algorithm.offset == 40
+    assert ammse.AmmseOptions.tile.offset == 44
     assert ammse.AmmseOptions.eps1.offset == 48
 
 
@@ -54,7 +55,7 @@ def test_default_options_match_paper(L):
     L.ammse_default_options(ctypes.byref(o))
     assert (o.precision, o.max_iters, o.T_c, o.warm_start, o.extrapolate) == (1, 100, 3, 1, 1)
     assert o.eps1 == pytest.approx(0.1) and o.eps2 == 0.0 and o.force_switch_iter == -1
-    assert o.refine_iters == 10 and o.algorithm == ammse.ALGO_AMMMSE and o.reserved == 0
+    assert o.refine_iters == 10 and o.algorithm == ammse.ALGO_AMMMSE and o.tile == 0
 
 
 def test_validate_reports_buffer_lengths(L):
@@ -97,7 +98,7 @@ def test_validate_rejects_overlapping_precoders(L):
     dict(precision=7), dict(max_iters=-1), dict(T_c=-1), dict(lanczos_steps=65),
     dict(force_switch_iter=0), dict(eps1=-0.1), dict(T_c=0), dict(eps2=float("nan")),
     dict(path=2), dict(refine_iters=-1), dict(precision=3), dict(algorithm=3),
-    dict(reserved=1),
+    dict(tile=4), dict(tile=-1),
 ])
 def test_validate_rejects_bad_options(L, opt):
     table, cu = _one()
