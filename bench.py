@@ -316,6 +316,9 @@ def profile_leg(name: str, reps: int) -> int:
     V = torch.empty_like(db.V0)
     wsr = torch.empty(batch.batch, dtype=torch.float64, device="cuda")
     flops = float(batch.total_flops_per_iter().sum()) * opts.max_iters
+    if name == "hexcell":   # tile shapes of the channel products per shape class
+        choice = plan.autotune(db.H, db.sigma2, db.alpha, db.P, db.V0, workspace=ws)
+        print(json.dumps({"leg": name, "autotuned_tile_shapes": choice}), flush=True)
     for r in range(reps):
         V.copy_(db.V0)
         e0 = torch.cuda.Event(enable_timing=True)
@@ -454,6 +457,11 @@ def main():
 
     flops = float(batch.total_flops_per_iter().sum()) * ITERS
     achieved = flops / (kern_ms / 1e3) / 1e12
+    # the LDS-resident kernel does one U N x U N x U d product with
+    # Q = S H H^H S per iteration (G^t by recursion, V carried as
+    # c V^0 + H^H S X) plus Q, G^0, the final V and G once per solve
+    un, ud, M_ = 64, 64, 64
+    executed = B * 8.0 * (un * un * ud * ITERS + un * M_ * un + 3 * un * M_ * ud)
     traffic = read_traffic()
     line = {
         "metric": "instances/s reaching 99% of FP64 WMMSE WSR; batched/mixed vs plain, same GPU",
@@ -481,7 +489,9 @@ def main():
                      "kernel": ("ammse_fast_kernel (LDS-resident, MFMA FP32)"
                                 if plan.kernel == ammse.KERNEL_LDS_MFMA
                                 else "ammse_solve_kernel<float> (general)"),
-                     "kernel_ms": kern_ms, "flops_per_launch": flops},
+                     "kernel_ms": kern_ms, "flops_per_launch": flops,
+                     "executed_flops_per_launch": executed,
+                     "executed_tflops": executed / (kern_ms / 1e3) / 1e12},
     }
     if not a.no_plain:
         line["plain_per_instance"] = plain_per_instance(batch, ref, opts)
