@@ -423,7 +423,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   // rate, UW = J-^{-1} G_own and E = (I + G_own^H J-^{-1} G_own)^{-1}.
   // Returns the weighted rate contribution of this lane (diagonal lanes).
   zd UWr[S::GRB], Er[S::GRB], Lir[S::GRB];
-  auto receivers = [&]() {
+  auto receivers = [&](bool with_rate) {
     double rsum = 0.0;
     bool ok = true;
 #pragma unroll
@@ -472,7 +472,8 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
       const zd Lw = chol16(L4, X, ok);
       // rate term 2 log Lw_aa in float (the WSR enters only the stage and stop
       // tests and the reported value, all at FP32 accuracy here)
-      if (L4.a == L4.b) rsum += alpha[row0 + L4.a] * (double)(2.0f * __logf((float)Lw.x));
+      if (with_rate && L4.a == L4.b)
+        rsum += alpha[row0 + L4.a] * (double)(2.0f * __logf((float)Lw.x));
       const zd Li = trsm16(L4, Lw, zd{(L4.a == L4.b) ? 1.0 : 0.0, 0.0});
       Er[i] = mm_hn(L4, Li, Li);                  // E = Lw^{-H} Lw^{-1}
       Lir[i] = Li;
@@ -483,7 +484,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
 
   // D = alpha U W U^H and Y = alpha U W per block user, and C with D = C C^H,
   // into LDS
-  auto weights = [&](bool stage2) {
+  auto weights = [&](bool stage2, bool for_step) {
 #pragma unroll
     for (int i = 0; i < S::GRB; ++i) {
       const int row0 = 16 * (wave + 4 * i) + 4 * lk;
@@ -500,7 +501,8 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
       const zd Cv = stage2 ? mm_nh(L4, UWr[i], Lir[i]) : T;
       Cs[g4 * S::CST + li] = scal(sqrt(al), Cv);
     }
-    __syncthreads();
+    // D and Y are read back by the same wave; C by all waves (step size only)
+    if (for_step) __syncthreads();
   };
 
   // lambda_max(A), A = H^H S D S H.  With D = C C^H (C block diagonal) and
@@ -679,20 +681,28 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   int iters_run = 0, status = 0;
 
   for (int t = 1; t <= T; ++t) {
-    const double rs = receivers();
+    // WSR(V^{t-1}) is needed for the stage test (stage I), the eps2 stop and
+    // the trace; otherwise the rate terms and their block reduction are skipped
+    // (a factorisation failure is then caught after the next barrier)
+    const bool need_wsr = !stage2 || p.eps2 > 0 || p.trace != nullptr;
+    const double rs = receivers(need_wsr);
     wsr_prev2 = wsr_prev;
-    wsr_prev = block_sum4(rs, red + 4) * (1.0 / M_LN2);
-    if (p.trace && tid == 0) p.trace[(long)b * p.trace_len + (t - 1)] = wsr_prev;
-    if (misc[0]) {
-      status |= misc[0];
-      break;
+    if (need_wsr) {
+      wsr_prev = block_sum4(rs, red + 4) * (1.0 / M_LN2);
+      if (p.trace && tid == 0) p.trace[(long)b * p.trace_len + (t - 1)] = wsr_prev;
+      if (misc[0]) {
+        status |= misc[0];
+        break;
+      }
+      if (!isfinite(wsr_prev)) {
+        status |= AMMSE_INST_NONFINITE;
+        break;
+      }
+      if (p.eps2 > 0 && t >= 2 && prev_step_stage2 && rel_change(wsr_prev, wsr_prev2) <= p.eps2)
+        break;
+    } else {
+      wsr_prev = NAN;
     }
-    if (!isfinite(wsr_prev)) {
-      status |= AMMSE_INST_NONFINITE;
-      break;
-    }
-    if (p.eps2 > 0 && t >= 2 && prev_step_stage2 && rel_change(wsr_prev, wsr_prev2) <= p.eps2)
-      break;
     if (!stage2) {
       const bool trig = (fsw >= 1) ? (t >= fsw)
                                    : (t >= 2 && rel_change(wsr_prev, wsr_prev2) <= p.eps1);
@@ -701,9 +711,9 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
         switch_iter = t;
       }
     }
-    weights(stage2);
     const bool adaptive = t <= p.T_c || (p.rearm && switch_iter >= 1 && t >= switch_iter &&
                                          t < switch_iter + p.T_c);
+    weights(stage2, adaptive);
     if (adaptive) {
       const double lm = lanczos();
       gamma = (lm > 0.0) ? 1.0 / (2.0 * lm) : 0.0;
@@ -748,6 +758,10 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
       }
     }
     __syncthreads();
+    if (!need_wsr && misc[0]) {   // factorisation failure flagged by this iteration's receivers
+      status |= misc[0];
+      break;
+    }
 
     // G~ = G^ - 2 gamma Q Z', X~ = X^ - 2 gamma Z', and the projection:
     // ||V~||^2 = c^2 nu + c Re<G^0, X~> + Re<X~, G~>  (c = c^, exact algebra
@@ -862,7 +876,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   }
   double wsr_final;
   if (!status) {
-    const double rs = receivers();
+    const double rs = receivers(true);
     wsr_final = block_sum4(rs, red + 4) * (1.0 / M_LN2);
     if (misc[0]) status |= misc[0];
     if (!isfinite(wsr_final)) status |= AMMSE_INST_NONFINITE;

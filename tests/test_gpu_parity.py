@@ -378,3 +378,18 @@ def test_lds_kernel_matches_general_kernel():
     np.testing.assert_allclose(fast.trace[same, :21], gen.trace[same, :21], rtol=1e-4)
     low = same & (np.arange(b.batch) < 32)
     np.testing.assert_allclose(fast.wsr[low], gen.wsr[low], rtol=2e-4)
+
+
+def test_lds_kernel_without_trace_matches_traced_run():
+    """Without a trace and eps2 = 0 the LDS kernel skips the per-iteration WSR
+    reduction in stage II; the iterates do not depend on it, so the precoders,
+    WSR, switch iteration and status equal those of the traced run."""
+    b = synth.rayleigh_sweep(B_per_p=8)
+    opts = ammse.Options(precision=ammse.PREC_FP32, max_iters=100)
+    say("case: lds kernel with / without trace")
+    a = ammse.solve(b, opts, want_trace=True)
+    c = ammse.solve(b, opts, want_trace=False)
+    np.testing.assert_array_equal(c.switch_iter, a.switch_iter)
+    np.testing.assert_array_equal(c.status, a.status)
+    np.testing.assert_array_equal(c.V, a.V)
+    np.testing.assert_array_equal(c.wsr, a.wsr)
