@@ -422,7 +422,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   // Per block user (i = row block of this wave, group lk): J-, Cholesky,
   // rate, UW = J-^{-1} G_own and E = (I + G_own^H J-^{-1} G_own)^{-1}.
   // Returns the weighted rate contribution of this lane (diagonal lanes).
-  zd UWr[S::GRB], Er[S::GRB], Lir[S::GRB];
+  zd UWr[S::GRB], Lir[S::GRB];
   auto receivers = [&](bool with_rate) {
     double rsum = 0.0;
     bool ok = true;
@@ -475,8 +475,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
       if (with_rate && L4.a == L4.b)
         rsum += alpha[row0 + L4.a] * (double)(2.0f * __logf((float)Lw.x));
       const zd Li = trsm16(L4, Lw, zd{(L4.a == L4.b) ? 1.0 : 0.0, 0.0});
-      Er[i] = mm_hn(L4, Li, Li);                  // E = Lw^{-H} Lw^{-1}
-      Lir[i] = Li;
+      Lir[i] = Li;                                // E = Li^H Li (formed where needed)
     }
     if (!ok) atomicOr(&misc[0], AMMSE_INST_CHOLESKY);
     return rsum;
@@ -488,17 +487,23 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
 #pragma unroll
     for (int i = 0; i < S::GRB; ++i) {
       const int row0 = 16 * (wave + 4 * i) + 4 * lk;
-      const zd T = mm_nn(L4, UWr[i], Er[i]);     // U
-      const zd Ur = stage2 ? UWr[i] : T;
-      zd Dv = mm_nh(L4, T, Ur);
+      // stage II (W = E^{-1}): U W = UW, D = alpha UW E UW^H = alpha C C^H with
+      // C = UW Li^H; stage I (W = I): U = UW E, D = alpha U U^H, C = U
+      zd Ur, Cv;
+      if (stage2) {
+        Cv = mm_nh(L4, UWr[i], Lir[i]);
+        Ur = UWr[i];
+      } else {
+        Cv = mm_nn(L4, UWr[i], mm_hn(L4, Lir[i], Lir[i]));
+        Ur = Cv;
+      }
+      zd Dv = mm_nh(L4, Cv, Cv);
       const zd Dt = L4.at(Dv, L4.b, L4.a);
       Dv = {0.5 * (Dv.x + Dt.x), 0.5 * (Dv.y - Dt.y)};   // exactly Hermitian
       const double al = alpha[row0 + L4.a];
       const int g4 = row0 >> 2;
       Ds[g4 * 16 + li] = c2((float)(al * Dv.x), (float)(al * Dv.y));
       Ys[g4 * 16 + li] = c2((float)(al * Ur.x), (float)(al * Ur.y));
-      // D = C C^H: C = sqrt(alpha) U (stage I) or sqrt(alpha) UW Lw^{-H} (stage II)
-      const zd Cv = stage2 ? mm_nh(L4, UWr[i], Lir[i]) : T;
       Cs[g4 * S::CST + li] = scal(sqrt(al), Cv);
     }
     // D and Y are read back by the same wave; C by all waves (step size only)
