@@ -138,7 +138,7 @@ __device__ __forceinline__ void wave_cgemm(const float2* __restrict__ A, int lda
   // operands of the next k-step are fetched before the current one's MFMAs
   float2 a0[NRB], b0[NCB], a1[NRB], b1[NCB];
   load(0, a0, b0);
-#pragma unroll 2
+#pragma unroll
   for (int k0 = 0; k0 < K; k0 += 8) {
     load(k0 + 4, a1, b1);
     step(a0, b0);
