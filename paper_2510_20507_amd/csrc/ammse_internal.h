@@ -31,7 +31,9 @@ struct ammse_ws_layout_t {
   size_t Qm;                  // S H H^H S ((U N) x (U N), storage precision), see below
   size_t Hb, Xb, Zb;          // bfloat16 copies of H, X and Z (mixed precision only)
   size_t Lwm, Lim, Cm;        // per-user Lw, Lw^{-1}, C (double complex 4 x 4): WMMSE,
-                              // and Lw^{-1}, C for the Q-based Lanczos
+                              // and Lw^{-1}, C for the Q- and Gram-based Lanczos
+  size_t Rg, Kg;              // Gram-based Lanczos: R = C^H S H_{:,c} ((U d) x M) and
+                              // K = R R^H ((U d) x (U d)), storage precision
   size_t total;
 };
 
@@ -80,6 +82,17 @@ struct ammse_kparams_t {
 // starts on a 256-byte boundary.
 __host__ __device__ inline size_t ammse_align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Step-size Lanczos of Algorithm 3 on the stream-space Gram matrix
+// K_c = R_c R_c^H, R_c = C^H S H_{:,c} (D = C C^H), instead of the operator
+// x -> H_{:,c}^H S D S H_{:,c} x: float storage, not the single-cell Q path,
+// and fewer matrix entries per step ((U d)^2 < 2 U N M).
+__host__ __device__ inline bool ammse_gram_path(int real_bytes, int C, int U, int M, int N, int d,
+                                                bool wmmse) {
+  const long un = (long)U * N, ud = (long)U * d;
+  const bool qp = !wmmse && C == 1 && un <= M;
+  return real_bytes == 4 && !wmmse && !qp && ud * ud < 2 * un * (long)M;
+}
+
 __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int C, int U, int M,
                                                              int N, int d, int lanczos_steps,
                                                              bool wmmse, bool bf16 = false) {
@@ -96,7 +109,9 @@ __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int
   L.Em = o;  o += ammse_align256((size_t)U * 16 * zs);
   L.Dm = o;  o += ammse_align256((size_t)U * 16 * zs);
   L.Ym = o;  o += ammse_align256((size_t)U * 16 * zs);
-  L.Lq = o;  o += ammse_align256((size_t)3 * M * zs);   // three Lanczos vectors
+  const size_t gp = ammse_gram_path(real_bytes, C, U, M, N, d, wmmse) ? 1 : 0;
+  const size_t nl = (gp && ud > (size_t)M) ? ud : (size_t)M;   // Lanczos order (at most)
+  L.Lq = o;  o += ammse_align256((size_t)3 * nl * zs);   // three Lanczos vectors
   L.Lw = o;  o += ammse_align256((size_t)M * zs);
   L.Ly1 = o; o += ammse_align256(un * zs);
   L.Ly2 = o; o += ammse_align256(un * zs);
@@ -109,9 +124,13 @@ __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int
   // Algorithm 3, single cell with U N <= M: Lanczos on Q = S H H^H S
   const size_t qp = (!wmmse && C == 1 && un <= (size_t)M) ? 1 : 0;
   L.Qm = o;  o += ammse_align256(qp * un * un * cs);
+  // Algorithm 3 otherwise, float storage, when the (U d) x (U d) Gram matrix
+  // is smaller than two passes over H_{:,c}: Lanczos on K = R R^H (gp above)
   L.Lwm = o; o += ammse_align256(w * (size_t)U * 16 * zs);
-  L.Lim = o; o += ammse_align256((w | qp) * (size_t)U * 16 * zs);
-  L.Cm = o;  o += ammse_align256((w | qp) * (size_t)U * 16 * zs);
+  L.Lim = o; o += ammse_align256((w | qp | gp) * (size_t)U * 16 * zs);
+  L.Cm = o;  o += ammse_align256((w | qp | gp) * (size_t)U * 16 * zs);
+  L.Rg = o;  o += ammse_align256(gp * ud * (size_t)M * cs);
+  L.Kg = o;  o += ammse_align256(gp * ud * ud * cs);
   // mixed precision: bfloat16 copies of H (all cells), of the precoder and of Z
   const size_t bb = bf16 ? 4 : 0;
   L.Hb = o;  o += ammse_align256(bb * (size_t)C * un * M);

@@ -97,6 +97,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
 
   const bool wm = p.algorithm != AMMSE_ALGO_AMMMSE;   // exact V step (Algorithm 2 / MMMSE)
   const bool qpath = C == 1 && un <= M && !wm;   // stream-space Lanczos with Q = S H H^H S
+  const bool gpath = ammse_gram_path((int)sizeof(R), C, U, M, N, d, wm);   // ... with K = R R^H
   const ammse_ws_layout_t L =
       ammse_ws_layout((int)sizeof(R), C, U, M, N, d, p.lanczos_steps, wm, p.bf16_copies != 0);
   char* ws = p.ws + D.ws_off;
@@ -125,6 +126,8 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   zd* Lwm = (zd*)(ws + L.Lwm);
   zd* Lim = (zd*)(ws + L.Lim);
   zd* Cm = (zd*)(ws + L.Cm);
+  cx<R>* Rg = (cx<R>*)(ws + L.Rg);
+  cx<R>* Kg = (cx<R>*)(ws + L.Kg);
   const cx<R>* H = (const cx<R>*)p.H + D.h_off;
   cx<R>* V = (cx<R>*)p.V + D.v_off;
   const long Vtot = (long)M * D.ud;
@@ -228,7 +231,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
         UWm[u * 16 + li] = UWv;
         Em[u * 16 + li] = Ev;
         if (wm) Lwm[u * 16 + li] = Lw;
-        if (wm || qpath) Lim[u * 16 + li] = Li;
+        if (wm || qpath || gpath) Lim[u * 16 + li] = Li;
         ok = ok && oku;
       }
     }
@@ -260,7 +263,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
         Dm[u * 16 + li] = scal(al, Dv);
         Ym[u * 16 + li] = scal(al, Ur);
       }
-      if (wm || qpath) {   // D = C C^H: C = sqrt(alpha) UW Lw^{-H} (stage II) or sqrt(alpha) U (stage I)
+      if (wm || qpath || gpath) {   // D = C C^H: C = sqrt(alpha) UW Lw^{-H} (stage II) or sqrt(alpha) U (stage I)
         const zd Cv = scal(sqrt(al), stage2 ? mm_nh(L4, UWv, Lim[uu * 16 + li]) : T);
         if (act) Cm[u * 16 + li] = Cv;
       }
@@ -436,6 +439,72 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
         zd acc = {0.0, 0.0};
         for (int k = 0; k < N; ++k) acc = acc + cj(Cm[u * 16 + k * 4 + n]) * Ly2[u * N + k];
         wv[r] = acc;
+      }
+    });
+  };
+
+  // lambda_max(A_c) on the stream side: with D = C C^H (C block diagonal,
+  // N x d per user), A_c = R_c^H R_c for R_c = C^H S H_{:,c} ((U d) x M), so
+  // lambda_max(A_c) = lambda_max(K_c), K_c = R_c R_c^H ((U d) x (U d)).  R_c is
+  // formed in one pass over H_{:,c}, K_c by one MFMA product (made exactly
+  // Hermitian), and each Lanczos step reads K_c once instead of H_{:,c} twice.
+  auto lanczos_gram = [&](int c) {
+    const int tid = phase_tid();
+    const cx<R>* __restrict__ Hc = H + (long)c * un * M;
+    const int ud = U * d;
+    for (int e = tid; e < ud * M; e += AMMSE_BLOCK) {
+      const int i = e / M, m = e - i * M;
+      const int u = i / d, s = i - u * d;
+      zd acc = {0.0, 0.0};
+      for (int n = 0; n < N; ++n)
+        acc = acc + cj(Cm[u * 16 + n * 4 + s]) * to_d(Hc[(long)(u * N + n) * M + m]);
+      const double f = sm.invsig[u];
+      Rg[e] = {(R)(f * acc.x), (R)(f * acc.y)};
+    }
+    __syncthreads();
+    channel_gemm<R, false, true>(ud, ud, M, Rg, M, Rg, M, sm.tiles, false, tile,
+                                 [&](int i, int j, cx<R> v) { Kg[(long)i * ud + j] = v; });
+    __syncthreads();
+    for (int e = tid; e < ud * ud; e += AMMSE_BLOCK) {   // exactly Hermitian
+      const int i = e / ud, j = e - i * ud;
+      if (i < j) {
+        const cx<R> x = Kg[e], y = Kg[(long)j * ud + i];
+        const cx<R> mm = {(R)0.5 * (x.x + y.x), (R)0.5 * (x.y - y.y)};
+        Kg[e] = mm;
+        Kg[(long)j * ud + i] = {mm.x, -mm.y};
+      } else if (i == j) {
+        Kg[e].y = (R)0;
+      }
+    }
+    __syncthreads();
+    // w = K q with K Hermitian (column r read for row r, coalesced over r):
+    // nparts threads per row, each over every nparts-th column, partial sums
+    // combined through LDS (the product tiles, free here)
+    const int nparts = (ud >= AMMSE_BLOCK) ? 1 : AMMSE_BLOCK / ud;
+    zd* partial = (zd*)sm.tiles;
+    return lanczos_core(ud, [&](const zd* qv, zd* wv) {
+      if (nparts == 1) {
+        for (int r = tid; r < ud; r += AMMSE_BLOCK) {
+          zd acc = {0.0, 0.0};
+#pragma unroll 16
+          for (int c2 = 0; c2 < ud; ++c2) acc = acc + cj(to_d(Kg[(long)c2 * ud + r])) * qv[c2];
+          wv[r] = acc;
+        }
+        return;
+      }
+      const int r = tid % ud, part = tid / ud;
+      if (part < nparts) {
+        zd acc = {0.0, 0.0};
+#pragma unroll 16
+        for (int c2 = part; c2 < ud; c2 += nparts)
+          acc = acc + cj(to_d(Kg[(long)c2 * ud + r])) * qv[c2];
+        partial[part * ud + r] = acc;
+      }
+      __syncthreads();
+      for (int rr = tid; rr < ud; rr += AMMSE_BLOCK) {
+        zd acc = {0.0, 0.0};
+        for (int q = 0; q < nparts; ++q) acc = acc + partial[q * ud + rr];
+        wv[rr] = acc;
       }
     });
   };
@@ -854,7 +923,10 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
                                          t < switch_iter + p.T_c);
     if (adaptive) {
       for (int c = 0; c < C; ++c) {
-        const double lm = (sm.cu[c] == 0) ? 0.0 : qpath ? lanczos_q() : lanczos_lmax(c);
+        const double lm = (sm.cu[c] == 0) ? 0.0
+                          : qpath ? lanczos_q()
+                          : gpath ? lanczos_gram(c)
+                                  : lanczos_lmax(c);
         if (tid == 0) sm.gamma[c] = (lm > 0.0) ? 1.0 / (2.0 * lm) : 0.0;
         __syncthreads();
       }
