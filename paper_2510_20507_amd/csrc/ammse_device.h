@@ -136,15 +136,37 @@ __device__ inline int sturm_below(const double* a, const double* b, int m, doubl
 // la, lb: diagonal and off-diagonal in LDS; imin: an LDS int used for the
 // reduction; stops when the bracket is narrower than rtol * lambda.  Every
 // thread of the block must call it.
+// With th_prev > 0 (the value for a leading block, a lower bound of the new
+// one) and conv != NULL, one round of probes over [th_prev, th_prev (1 + ltol)]
+// first tests whether the value moved by less than ltol (*conv).
 __device__ inline double tridiag_lmax(const double* la, const double* lb, int m, int* imin,
-                                     double rtol = 1e-16) {
+                                     double rtol = 1e-16, double th_prev = 0.0,
+                                     double ltol = 0.0, bool* conv = nullptr) {
   double lo = 1e300, hi = -1e300;
+  if (conv) *conv = false;
+  double qlo = -1e300;
+  if (conv && th_prev > 0.0) {
+    const double n1 = (double)blockDim.x;
+    if (threadIdx.x == 0) *imin = blockDim.x;
+    __syncthreads();
+    const double x = th_prev * (1.0 + ltol * (double)(threadIdx.x + 1) / n1);
+    if (sturm_below(la, lb, m, x) == m) atomicMin(imin, (int)threadIdx.x);
+    __syncthreads();
+    const int t = *imin;
+    __syncthreads();
+    if (t < (int)blockDim.x) {
+      *conv = true;
+      return th_prev * (1.0 + ltol * (double)(t + 1) / n1);
+    }
+    qlo = th_prev * (1.0 + ltol);
+  }
   for (int i = 0; i < m; ++i) {
     const double r = (i > 0 ? fabs(lb[i - 1]) : 0.0) + (i < m - 1 ? fabs(lb[i]) : 0.0);
     lo = fmin(lo, la[i] - r);
     hi = fmax(hi, la[i] + r);
   }
   hi += 1e-300 + fabs(hi) * 1e-15;
+  if (qlo > lo) lo = fmin(qlo, hi);
   for (int round = 0; round < 8; ++round) {
     const double w = hi - lo;
     if (!(w > fabs(hi) * rtol)) break;

@@ -346,8 +346,14 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       bool stop = breakdown;
       if (breakdown || (msz >= first && (msz % every) == 0) || msz == m) {
         __syncthreads();
-        const double th = (tmax > 0.0) ? tridiag_lmax(sm.la, sm.lb, msz, &sm.imin, rtol) : 0.0;
-        stop = stop || fabs(th - theta) <= ltol * fabs(th);
+        // FP32: one quick round tests the ltol criterion above the previous
+        // value before any full multisection (FP64: full value every check)
+        bool conv = false;
+        const double th = (tmax > 0.0) ? tridiag_lmax(sm.la, sm.lb, msz, &sm.imin, rtol,
+                                                      exact_beta ? 0.0 : theta, ltol,
+                                                      exact_beta ? nullptr : &conv)
+                                       : 0.0;
+        stop = stop || conv || (exact_beta && fabs(th - theta) <= ltol * fabs(th));
         theta = th;
       }
       if (stop) break;
