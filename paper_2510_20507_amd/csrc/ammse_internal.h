@@ -34,6 +34,9 @@ struct ammse_ws_layout_t {
                               // and Lw^{-1}, C for the Q- and Gram-based Lanczos
   size_t Rg, Kg;              // Gram-based Lanczos: R = C^H S H_{:,c} ((U d) x M) and
                               // K = R R^H ((U d) x (U d)), storage precision
+  size_t X1, X2, G0;          // Q recursion (single cell, U N <= M, float products): the
+                              // implicit precoder's X^{t-1}, X^{t-2} and G^0 ((U N) x (U d),
+                              // storage precision)
   size_t total;
 };
 
@@ -131,6 +134,10 @@ __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int
   L.Cm = o;  o += ammse_align256((w | qp | gp) * (size_t)U * 16 * zs);
   L.Rg = o;  o += ammse_align256(gp * ud * (size_t)M * cs);
   L.Kg = o;  o += ammse_align256(gp * ud * ud * cs);
+  const size_t rp = (qp && real_bytes == 4) ? 1 : 0;
+  L.X1 = o;  o += ammse_align256(rp * un * ud * cs);
+  L.X2 = o;  o += ammse_align256(rp * un * ud * cs);
+  L.G0 = o;  o += ammse_align256(rp * un * ud * cs);
   // mixed precision: bfloat16 copies of H (all cells), of the precoder and of Z
   const size_t bb = bf16 ? 4 : 0;
   L.Hb = o;  o += ammse_align256(bb * (size_t)C * un * M);

@@ -98,6 +98,11 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   const bool wm = p.algorithm != AMMSE_ALGO_AMMMSE;   // exact V step (Algorithm 2 / MMMSE)
   const bool qpath = C == 1 && un <= M && !wm;   // stream-space Lanczos with Q = S H H^H S
   const bool gpath = ammse_gram_path((int)sizeof(R), C, U, M, N, d, wm);   // ... with K = R R^H
+  // float products on the Q path: one product with Q per iteration, the
+  // precoder carried implicitly as V = c V^0 + H^H S X (see the update below).
+  // Not with bfloat16 products: the projection norm would then come from a
+  // bfloat16 product and the iterates would leave the power sphere by ~1e-3.
+  const bool rpath = qpath && sizeof(R) == 4 && p.lowp_iters <= 0;
   const ammse_ws_layout_t L =
       ammse_ws_layout((int)sizeof(R), C, U, M, N, d, p.lanczos_steps, wm, p.bf16_copies != 0);
   char* ws = p.ws + D.ws_off;
@@ -128,6 +133,9 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   zd* Cm = (zd*)(ws + L.Cm);
   cx<R>* Rg = (cx<R>*)(ws + L.Rg);
   cx<R>* Kg = (cx<R>*)(ws + L.Kg);
+  cx<R>* X1 = (cx<R>*)(ws + L.X1);   // Q recursion: X^{t-1}, X^{t-2}, G^0
+  cx<R>* X2 = (cx<R>*)(ws + L.X2);
+  cx<R>* G0 = (cx<R>*)(ws + L.G0);
   const cx<R>* H = (const cx<R>*)p.H + D.h_off;
   cx<R>* V = (cx<R>*)p.V + D.v_off;
   const long Vtot = (long)M * D.ud;
@@ -165,7 +173,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   //   UW = J-^{-1} G_own, E = Lw^{-H} Lw^{-1}
   // UW and E go to the workspace; returns the sum of alpha_u R_u (nats) over
   // the block.
-  auto receivers = [&](const cx<R>* G) -> double {
+  auto receivers = [&](const cx<R>* G, double gscale) -> double {
     const int tid = phase_tid();
     const int lane = tid & 63, li = lane & 15;
     const Lane4 L4{lane & ~15, li >> 2, li & 3};
@@ -192,7 +200,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
           zd g[AMMSE_MAX_RX];
 #pragma unroll
           for (int k = 0; k < AMMSE_MAX_RX; ++k)
-            g[k] = (k < N) ? to_d(r0[(long)k * nc + j]) : zd{0.0, 0.0};
+            g[k] = (k < N) ? scal(gscale, to_d(r0[(long)k * nc + j])) : zd{0.0, 0.0};
 #pragma unroll
           for (int x = 0; x < AMMSE_MAX_RX; ++x)
 #pragma unroll
@@ -215,7 +223,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       if (ea < N && eb < N) J = J + sj[0];
       if (ea < N && eb < d) {
         const int c = cown, nc = sm.cu[c] * d;
-        F = to_d(G[(long)un * sm.colOff[c] + (long)(uu * N + ea) * nc + j0 + eb]);
+        F = scal(gscale, to_d(G[(long)un * sm.colOff[c] + (long)(uu * N + ea) * nc + j0 + eb]));
       }
       bool oku = true;
       const zd Lo = chol16(L4, J, oku);
@@ -857,12 +865,28 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   channel_product(Gp, Xc, sm.scur, p.lowp_iters >= 1);
   __syncthreads();
   const int T = p.wsr_only ? 0 : p.max_iters;
+  // Q recursion state: V^t = c_t V^0 + H^H S (xs_t X_t), G buffers carry
+  // scales gsp (G^{t-1}) and gsq (G^{t-2}) applied where they are read
+  double c1 = 1.0, c2 = 1.0, xs1 = 1.0, xs2 = 1.0, gsp = 1.0, gsq = 1.0, nu = 0.0;
   if (!p.wsr_only) {
     const int nv = (int)Vtot, ng = un * D.ud;
+    if (rpath) {
+      for (int e = tid; e < nv; e += AMMSE_BLOCK) nu += nrm2(to_d(Xc[e]));
 #pragma unroll 4
-    for (int e = tid; e < nv; e += AMMSE_BLOCK) Xp[e] = Xc[e];
+      for (int e = tid; e < ng; e += AMMSE_BLOCK) {
+        const cx<R> g = Gp[e];
+        Gq[e] = g;
+        G0[e] = g;
+        X1[e] = cx<R>{(R)0, (R)0};
+        X2[e] = cx<R>{(R)0, (R)0};
+      }
+      nu = block_sum(nu, sm.red);
+    } else {
 #pragma unroll 4
-    for (int e = tid; e < ng; e += AMMSE_BLOCK) Gq[e] = Gp[e];
+      for (int e = tid; e < nv; e += AMMSE_BLOCK) Xp[e] = Xc[e];
+#pragma unroll 4
+      for (int e = tid; e < ng; e += AMMSE_BLOCK) Gq[e] = Gp[e];
+    }
   }
   __syncthreads();
 
@@ -884,7 +908,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       __syncthreads();
     }
     // receivers and rate of V^{t-1}
-    const double rs = receivers(Gp);
+    const double rs = receivers(Gp, gsp);
     wsr_prev2 = wsr_prev;
     wsr_prev = wsr_sum(rs);
     if (p.trace) {
@@ -945,6 +969,8 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     // (user, column), consecutive threads along the columns; the N rows of
     // the user's block of G^ are read once and give the N rows of Z.
     const double om = p.extrapolate ? fmax((t - 2.0) / (t + 1.0), 0.0) : 0.0;
+    const double ga1 = (1.0 + om) * gsp, ga2 = om * gsq;
+    const double xa1 = (1.0 + om) * xs1, xa2 = om * xs2, gz = 2.0 * sm.gamma[0];
     for (int c = 0; c < C; ++c) {
       const int nc = sm.cu[c] * d;
       const long base = (long)un * sm.colOff[c];
@@ -959,8 +985,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
           gh[k] = {0.0, 0.0};
           if (k < N) {
             const cx<R> a = Gp[g0 + (long)k * nc], q = Gq[g0 + (long)k * nc];
-            gh[k] = {(1.0 + om) * (double)a.x - om * (double)q.x,
-                     (1.0 + om) * (double)a.y - om * (double)q.y};
+            gh[k] = {ga1 * (double)a.x - ga2 * (double)q.x, ga1 * (double)a.y - ga2 * (double)q.y};
           }
         }
         const int j0 = sm.local[u] * d;
@@ -974,6 +999,16 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
             for (int k = 0; k < AMMSE_MAX_RX; ++k)
               if (k < N) acc = acc + Dm[u * 16 + n * 4 + k] * gh[k];
             if (own) acc = acc - Ym[u * 16 + n * 4 + (j - j0)];
+            if (rpath) {
+              // implicit precoder: Z' = D G^ - Y (the gradient is 2 H^H S Z'),
+              // X~ = X^ - 2 gamma Z' over X^{t-2}
+              const long e = g0 + (long)n * nc;
+              const cx<R> x1 = X1[e], x2 = X2[e];
+              const cx<R> xt = from_d<R>(zd{xa1 * (double)x1.x - xa2 * (double)x2.x - gz * acc.x,
+                                            xa1 * (double)x1.y - xa2 * (double)x2.y - gz * acc.y});
+              X2[e] = xt;
+              continue;
+            }
             const cx<R> zv = from_d<R>(scal(is, acc));
             if constexpr (sizeof(R) == 4) {
               if (lowp && copies) {
@@ -987,6 +1022,43 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       }
     }
     __syncthreads();
+
+    if (rpath) {
+      // One product P = Q X~ (single cell).  With V^t = c_t V^0 + H^H S X^t,
+      // G^t = S H V^t = c_t G^0 + Q X^t, and X~ = X^ - 2 gamma Z' formed above:
+      //   G~ = c~ G^0 + P,  ||V~||^2 = c~^2 ||V^0||^2 + 2 c~ Re<G^0, X~> + Re<X~, P>
+      // (c~ = c^, the extrapolated coefficient); G~ goes over G^{t-2} and the
+      // projection factor becomes the scale of G~ and X~.
+      const int ud = D.ud;
+      const double ch = (1.0 + om) * c1 - om * c2;
+      double acc = 0.0;
+      auto epi = [&](int i, int j, cx<R> pq) {
+        const long e = (long)i * ud + j;
+        const cx<R> x = X2[e], g0 = G0[e];
+        acc += 2.0 * ch * ((double)g0.x * x.x + (double)g0.y * x.y) +
+               ((double)x.x * pq.x + (double)x.y * pq.y);
+        Gq[e] = from_d<R>(zd{ch * (double)g0.x + (double)pq.x, ch * (double)g0.y + (double)pq.y});
+      };
+      channel_gemm<R, false>(un, ud, un, Qm, un, X2, ud, sm.tiles, false, tile, epi);
+      const double pw = ch * ch * nu + block_sum(acc, sm.red);
+      const double sc = (pw > sm.Pc[0]) ? sqrt(sm.Pc[0] / pw) : 1.0;
+      cx<R>* tg = Gq;
+      Gq = Gp;
+      Gp = tg;
+      gsq = gsp;
+      gsp = sc;
+      cx<R>* tx = X2;
+      X2 = X1;
+      X1 = tx;
+      xs2 = xs1;
+      xs1 = sc;
+      c2 = c1;
+      c1 = sc * ch;
+      __syncthreads();
+      prev_step_stage2 = stage2;
+      iters_run = t;
+      continue;
+    }
 
     // gradient 2 H_c^H Z_c and, in the product's epilogue, the extrapolated
     // step X~ = (1+w) V^{t-1} - w V^{t-2} - gamma Grad written over V^{t-2};
@@ -1048,14 +1120,49 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     iters_run = t;
   }
 
+  // ---- recursion path: V = c V^0 + H^H S (xs X) into the caller's buffer,
+  // projected onto the power ball exactly, and G = S H V for its WSR
+  if (rpath && !p.wsr_only) {
+    const int ud = D.ud;
+    __syncthreads();
+    for (int e = tid; e < un * ud; e += AMMSE_BLOCK) {
+      const int i = e / ud;
+      const double f = xs1 * sm.invsig[i / N];
+      const cx<R> x = X1[e];
+      Z[e] = {(R)(f * x.x), (R)(f * x.y)};
+    }
+    __syncthreads();
+    double pw = 0.0;
+    channel_gemm<R, true>(M, ud, un, H, M, Z, ud, sm.tiles, false, tile,
+                          [&](int i, int j, cx<R> v) {
+                            const long e = (long)i * ud + j;
+                            const cx<R> v0 = V[e];
+                            const zd w = {c1 * (double)v0.x + (double)v.x,
+                                          c1 * (double)v0.y + (double)v.y};
+                            V[e] = from_d<R>(w);
+                            pw += nrm2(w);
+                          });
+    pw = block_sum(pw, sm.red);
+    if (pw > sm.Pc[0]) {
+      const double sc = sqrt(sm.Pc[0] / pw);
+      for (long e = tid; e < Vtot; e += AMMSE_BLOCK) {
+        const cx<R> v = V[e];
+        V[e] = {(R)(sc * v.x), (R)(sc * v.y)};
+      }
+    }
+    __syncthreads();
+    channel_product(Gp, V, sm.scur, false);
+    gsp = 1.0;
+    __syncthreads();
+  }
   // ---- WSR of the returned precoders
   double wsr_final;
-  if (iters_run == T && !status) {
-    const double rs = receivers(Gp);
+  if ((iters_run == T || rpath) && !status) {
+    const double rs = receivers(Gp, gsp);
     wsr_final = wsr_sum(rs);
     if (sm.fail) status |= sm.fail;
     if (!isfinite(wsr_final)) status |= AMMSE_INST_NONFINITE;
-    if (p.trace && tid == 0) p.trace[(long)b * p.trace_len + T] = wsr_final;
+    if (p.trace && tid == 0 && iters_run == T) p.trace[(long)b * p.trace_len + T] = wsr_final;
   } else {
     wsr_final = wsr_prev;   // stopped early: V^{iters_run} is the iterate, WSR already known
   }
