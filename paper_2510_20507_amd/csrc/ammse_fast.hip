@@ -1,32 +1,37 @@
 // LDS-resident A-MMMSE solve kernel on MFMA (FP32 storage), gfx950.
 //
 // For single-cell instances with M = 64 and U*N = U*d = 64, one workgroup of
-// 256 threads (4 waves) owns one instance for the whole solve; H stays in
-// LDS for all iterations and HBM is touched only to read H, V0 and the
-// per-user scalars and to write the results.
+// 256 threads (4 waves) owns one instance for the whole solve; HBM is touched
+// only to read H, V0 and the per-user scalars (and H, V0 once more at the
+// end) and to write the results.
 //
-// Channel products: v_mfma_f32_16x16x4f32, a complex product being three
-// real products (Re*Re, Im*Im, (Re + Im)*(Re + Im)) fed from interleaved
-// complex LDS tiles.  Each wave owns whole 16-row strips of the outputs, so
-// the iteration state stays in registers in the MFMA output layout:
-//   G^{t-1}, G^{t-2}  (the extrapolated product follows by linearity)
-//   V^{t-1}, V^{t-2}  (the extrapolated precoder)
+// The precoder is carried implicitly, V^t = c_t V^0 + H^H S X^t, so that one
+// product with Q = S H H^H S per iteration gives G^t = S H V^t (see the
+// iteration below); V^T is rebuilt with one product by H^H at the end.
+//
+// Products: v_mfma_f32_16x16x4f32, a complex product being three real
+// products (Re*Re, Im*Im, (Re + Im)*(Re + Im)) fed from interleaved complex
+// LDS tiles.  Each wave owns whole 16-row strips of the outputs, so the
+// iteration state stays in registers in the MFMA output layout:
+//   G^{t-1}, G^{t-2}  (the extrapolated G follows by linearity)
+//   X^{t-1}           (X^{t-2} and G^0 in LDS, per lane)
 // A lane holds 4 consecutive rows of one column.  Four consecutive rows form
 // a "block user": one user for N = 4, two for N = 2, four for N = 1; its
 // N x N and d x d algebra is done as one block-diagonal 4 x 4 problem.
 //
 // Per-user algebra (Section IV equations for U and W, in the Woodbury form
 // used throughout this library) runs lane-parallel in double: the 16 lanes
-// of a 4-lane-row group hold the 16 entries of a 4 x 4 complex matrix and
-// exchange them with cross-lane shuffles.  The interference-plus-noise
-// covariance of every user is reduced directly from the G registers.
+// of a DPP row hold the 16 entries of a 4 x 4 complex matrix and exchange
+// them with DPP moves and swizzles.  The interference-plus-noise covariance
+// of every user is reduced directly from the G registers.
 //
 // Per iteration t (Algorithm 3):
 //   J- from registers (reduce-scatter over the 16 lanes of a row group);
-//   Cholesky, rate, U, W per block user; WSR(V^{t-1}); stage latch;
-//   adaptive step by Lanczos on K = C^H Q C (formed in LDS);  Z = S (D G^ - Y) -> LDS;
-//   Grad = 2 H^H Z (MFMA);  V^t = Pi(V^ - gamma Grad) in registers -> LDS;
-//   G^t = S H V^t (MFMA), own blocks -> LDS.
+//   Cholesky, U, W per block user; WSR(V^{t-1}) when a test needs it; stage
+//   latch; adaptive step by Lanczos on K = C^H Q C (formed in LDS);
+//   Z' = D G^ - Y -> LDS;  P = Q Z' (MFMA);  in the epilogue
+//   G~ = G^ - 2 gamma P, X~ = X^ - 2 gamma Z', the projection norm, and the
+//   projection factor applied to G~, X~ and c.
 
 #include "ammse_device.h"
 
@@ -319,8 +324,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   zd* Cs = (zd*)(smem + S::oC);
   double* invsig = (double*)(smem + S::oS);    // per row: 1/sigma of the row's user
   double* alpha = invsig + S::UN;              // per row: alpha of the row's user
-  double* la = (double*)(smem + S::oL);
-  double* lb = la + AMMSE_MAX_LANCZOS;
+  double* la = (double*)(smem + S::oL);         // tridiagonal pairs of the step size
   double* red = (double*)(smem + S::oR);
   // red: three slots of four partial sums ([0], [4], [8]; a slot is reused
   // only across further barriers) and two Lanczos values ([12], [13])

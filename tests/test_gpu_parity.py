@@ -393,3 +393,25 @@ def test_lds_kernel_without_trace_matches_traced_run():
     np.testing.assert_array_equal(c.status, a.status)
     np.testing.assert_array_equal(c.V, a.V)
     np.testing.assert_array_equal(c.wsr, a.wsr)
+
+
+@pytest.mark.parametrize("eps2", [0.0, 1e-4])
+def test_general_q_path_rebuilds_the_returned_precoder(eps2):
+    """Single-cell instances with U N <= M on the general kernel in float (one
+    product with Q per iteration, V carried as c V^0 + H^H S X and rebuilt at
+    the end, also after an eps2 stop): the reported WSR is the WSR of the
+    returned precoders (ammse_wsr) and every precoder meets its budget."""
+    b = synth.rayleigh_large(6, seed=24777)
+    opts = ammse.Options(precision=ammse.PREC_FP32, max_iters=100, eps2=eps2,
+                         path=ammse.PATH_GENERAL)
+    say("case: general Q path rebuild, eps2", eps2)
+    res = ammse.solve(b, opts)
+    assert np.all(res.status == 0)
+    if eps2 > 0:
+        assert np.any(res.iters < 100)
+    w = ammse.wsr(b, res.V, precision=ammse.PREC_FP32)
+    np.testing.assert_allclose(res.wsr, w, rtol=1e-6)
+    n = int(b.M[0]) * int(b.U[0]) * int(b.d[0])
+    for i in range(b.batch):
+        Vi = res.V[b.v_off[i]: b.v_off[i] + n]
+        assert np.vdot(Vi, Vi).real <= b.P[i] * (1 + 1e-5)
