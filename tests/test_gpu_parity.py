@@ -415,3 +415,45 @@ def test_general_q_path_rebuilds_the_returned_precoder(eps2):
     for i in range(b.batch):
         Vi = res.V[b.v_off[i]: b.v_off[i] + n]
         assert np.vdot(Vi, Vi).real <= b.P[i] * (1 + 1e-5)
+
+
+@pytest.mark.parametrize("variant", ["eps2", "no_extrapolation", "no_warm_start", "forced_switch"])
+def test_lds_kernel_option_variants(variant):
+    """The LDS-resident kernel under the option variants (eps2 stop, omega = 0,
+    A-WMMSE without warm start, a forced stage switch): the reported WSR is the
+    WSR of the returned precoders (ammse_wsr), every precoder meets its budget,
+    and at 0 and 10 dB the WSR trajectory follows the oracle run with the same
+    options over the first 20 iterations."""
+    okw, gkw = {"eps2": (dict(eps2=1e-4), dict(eps2=1e-4)),
+                "no_extrapolation": (dict(extrapolate=False), dict(extrapolate=0)),
+                "no_warm_start": (dict(warm_start=False), dict(warm_start=0)),
+                "forced_switch": (dict(force_switch_iter=5), dict(force_switch_iter=5))}[variant]
+    T = 60
+    b = synth.rayleigh_sweep(B_per_p=2)
+    opts = ammse.Options(precision=ammse.PREC_FP32, max_iters=T, **gkw)
+    say("case: lds kernel variant", variant)
+    res = ammse.solve(b, opts, want_trace=True)
+    assert np.all(res.status == 0)
+    if variant == "forced_switch":
+        assert np.all(res.switch_iter == 5)
+    if variant == "eps2":
+        assert np.any(res.iters < T)
+    w = ammse.wsr(b, res.V, precision=ammse.PREC_FP32)
+    np.testing.assert_allclose(res.wsr, w, rtol=1e-6)
+    n = 64 * 16 * 4
+    for i in range(b.batch):
+        Vi = res.V[b.v_off[i]: b.v_off[i] + n]
+        assert np.vdot(Vi, Vi).real <= b.P[i] * (1 + 1e-5)
+    idx = [0, 1, 2, 3]          # 0 dB and 10 dB
+    refs = oracle_runs(b, idx, iters=T, **okw)
+    for k, i in enumerate(idx):
+        ref = refs[k]
+        tr = res.trace[i]
+        if res.switch_iter[i] != ref["switch_iter"]:
+            r2 = ammse.solve(b.subset([i]), opts, want_trace=True,
+                             force_switch=np.array([ref["switch_iter"]], np.int32))
+            tr = r2.trace[0]
+        m = min(21, len(ref["trace"]))
+        np.testing.assert_allclose(tr[:m], ref["trace"][:m], rtol=1e-4, err_msg=str(i))
+        if variant == "eps2":
+            assert abs(int(res.iters[i]) - ref["iters"]) <= 2, (i, res.iters[i], ref["iters"])
