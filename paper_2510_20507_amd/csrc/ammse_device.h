@@ -282,6 +282,12 @@ __device__ __forceinline__ zd shz(zd v, int src) {
 // of lanes that holds one matrix row) or a bit-mask swizzle; only transposed
 // reads go through the general lane permutation.
 // ---------------------------------------------------------------------------
+// Component-wise select (a select of whole structs can end up as a select of
+// stack addresses)
+__device__ __forceinline__ zd sel(bool c, zd a, zd b) {
+  return {c ? a.x : b.x, c ? a.y : b.y};
+}
+
 struct Lane4 {
   int base, a, b;
   __device__ __forceinline__ zd at(zd v, int r, int c) const { return shz(v, base + 4 * r + c); }
@@ -329,10 +335,13 @@ __device__ __forceinline__ void chol16_step(const Lane4& L, zd& A, bool& ok) {
   ok = ok && (dkk > 0.0) && isfinite(dkk);
   const double l = sqrt(fmax(dkk, 1e-300));
   const double il = 1.0 / l;
-  if (L.b == K && L.a > K) A = scal(il, A);
-  if (L.a == K && L.b == K) A = {l, 0.0};
+  // lane-dependent updates as selects (no divergent branches)
+  const zd sa = scal(il, A);
+  A = sel(L.b == K && L.a > K, sa, A);
+  A = sel(L.a == K && L.b == K, zd{l, 0.0}, A);
   const zd lak = l4_rowq<K>(A);                 // L[a][K]
-  if (L.a > K && L.b > K) A = A - scal(il, lak * rk);
+  const zd up = A - scal(il, lak * rk);
+  A = sel(L.a > K && L.b > K, up, A);
 }
 
 // In place Cholesky (lower) of a Hermitian matrix; ok is cleared when a pivot
@@ -342,15 +351,16 @@ __device__ __forceinline__ zd chol16(const Lane4& L, zd A, bool& ok) {
   chol16_step<1>(L, A, ok);
   chol16_step<2>(L, A, ok);
   chol16_step<3>(L, A, ok);
-  if (L.b > L.a) A = {0.0, 0.0};
-  return A;
+  return sel(L.b > L.a, zd{0.0, 0.0}, A);
 }
 
 template <int K>
 __device__ __forceinline__ void trsm16_step(const Lane4& L, const zd& lq, double ik, zd& X) {
-  if (L.a == K) X = scal(ik, X);
+  const zd sx = scal(ik, X);
+  X = sel(L.a == K, sx, X);
   const zd xkb = l4_colk<K>(X);
-  if (L.a > K) X = X - lq * xkb;
+  const zd up = X - lq * xkb;
+  X = sel(L.a > K, up, X);
 }
 
 // X <- Lo^{-1} X (forward substitution, Lo lower with real diagonal)
@@ -361,15 +371,17 @@ __device__ __forceinline__ zd trsm16(const Lane4& L, zd Lo, zd X) {
   trsm16_step<0>(L, q0, i0, X);
   trsm16_step<1>(L, q1, i1, X);
   trsm16_step<2>(L, q2, i2, X);
-  if (L.a == 3) X = scal(i3, X);
-  return X;
+  const zd sx = scal(i3, X);
+  return sel(L.a == 3, sx, X);
 }
 
 template <int K>
 __device__ __forceinline__ void trsm16h_step(const Lane4& L, const zd& lka, double ik, zd& X) {
-  if (L.a == K) X = scal(ik, X);
+  const zd sx = scal(ik, X);
+  X = sel(L.a == K, sx, X);
   const zd xkb = l4_colk<K>(X);
-  if (L.a < K) X = X - cj(lka) * xkb;
+  const zd up = X - cj(lka) * xkb;
+  X = sel(L.a < K, up, X);
 }
 
 // X <- Lo^{-H} X (back substitution with the conjugate transpose)
@@ -380,8 +392,8 @@ __device__ __forceinline__ zd trsm16h(const Lane4& L, zd Lo, zd X) {
   trsm16h_step<3>(L, t3, i3, X);
   trsm16h_step<2>(L, t2, i2, X);
   trsm16h_step<1>(L, t1, i1, X);
-  if (L.a == 0) X = scal(i0, X);
-  return X;
+  const zd sx = scal(i0, X);
+  return sel(L.a == 0, sx, X);
 }
 
 // A^H B, A B, A B^H

@@ -756,12 +756,13 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
             zx += dm[r][k].x * gh[k].x - dm[r][k].y * gh[k].y;
             zy += dm[r][k].x * gh[k].y + dm[r][k].y * gh[k].x;
           }
+          // Y is nonzero only on the own block; its load is issued for every
+          // entry (clamped index) so the loads are not serialised by branches
           const int u = (row0 + r) >> lgN, c = col - (u << lgd);
-          if (c >= 0 && c < d) {
-            const float2 y = Ys[g4 * 16 + r * 4 + ((u - u0) << lgN) + c];
-            zx -= y.x;
-            zy -= y.y;
-          }
+          const bool own = c >= 0 && c < d;
+          const float2 y = Ys[g4 * 16 + r * 4 + ((u - u0) << lgN) + min(max(c, 0), d - 1)];
+          zx = own ? zx - y.x : zx;
+          zy = own ? zy - y.y : zy;
           Bs[(row0 + r) * S::BLD + col] = c2(zx, zy);
         }
       }
