@@ -67,6 +67,7 @@ struct Shape {
   static constexpr size_t oVq = oR + sizeof(double) * 16 + 16;     // X^{t-2}, per lane
   static constexpr size_t oP2 = oVq + sizeof(float2) * 256 * VRB * UDB * 4;  // Lanczos partials
   static constexpr size_t bytes = oP2 + sizeof(zd) * 4 * UN;
+  static_assert(bytes <= 160 * 1024, "LDS of one CU");
   // During the step-size computation (between the receivers and the Z build)
   // K = C^H Q C and a float copy of the Lanczos vector alias the
   // product-operand area, the partial products alias C, and the tridiagonal
@@ -180,6 +181,26 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
   return (rlane(v, 0) + rlane(v, 16)) + (rlane(v, 32) + rlane(v, 48));
 }
 
+// Three wave sums at once (the same additions as wave_sum_dpp for each value,
+// interleaved level by level).
+__device__ __forceinline__ void wave_sum3_dpp(double& a, double& b, double& c) {
+  a += dpp64<0xB1>(a);
+  b += dpp64<0xB1>(b);
+  c += dpp64<0xB1>(c);
+  a += dpp64<0x4E>(a);
+  b += dpp64<0x4E>(b);
+  c += dpp64<0x4E>(c);
+  a += dpp64<0x124>(a);
+  b += dpp64<0x124>(b);
+  c += dpp64<0x124>(c);
+  a += dpp64<0x128>(a);
+  b += dpp64<0x128>(b);
+  c += dpp64<0x128>(c);
+  a = (rlane(a, 0) + rlane(a, 16)) + (rlane(a, 32) + rlane(a, 48));
+  b = (rlane(b, 0) + rlane(b, 16)) + (rlane(b, 32) + rlane(b, 48));
+  c = (rlane(c, 0) + rlane(c, 16)) + (rlane(c, 32) + rlane(c, 48));
+}
+
 // Sum over the 256-thread block (four waves); every thread receives the
 // same value.  red: four doubles of LDS, which the caller must not hand to
 // another call before every wave has passed a further barrier (one barrier
@@ -228,9 +249,11 @@ __device__ __forceinline__ int sturm_count(const double2* tp, int m, double x) {
 // by multisection inside one wave (64 probes per round on Sturm counts of the
 // matrix scaled by 1/tmax, tmax >= every |a_i| + |b_i|; tp: 64 pairs of LDS
 // owned by the calling wave).  With a previous estimate th_prev > 0 (the
-// value for a leading block, which bounds the new one from below) one round
-// over [th_prev, th_prev (1 + ltol)] first tests whether the value moved by
-// less than ltol; *conv reports that test.
+// value for a leading block, which bounds the new one from below) the first
+// round places 16 probes ltol/16 apart above th_prev and 48 in geometric
+// progression up to the Gershgorin bound, so that a small and a large move of
+// the value are bracketed in one round; when the value lies within
+// th_prev (1 + ltol), *conv reports convergence.
 __device__ __forceinline__ double wave_tridiag_lmax(double ta, double tb, int m, double tmax,
                                                     double th_prev, double ltol, double2* tp,
                                                     bool* conv) {
@@ -242,20 +265,6 @@ __device__ __forceinline__ double wave_tridiag_lmax(double ta, double tb, int m,
   const double bl_ = __shfl_up(bn, 1, 64);
   tp[lane] = make_double2(an, (lane > 0) ? bl_ * bl_ : 0.0);
   *conv = false;
-  double lo, hi;
-  if (th_prev > 0.0) {
-    const double t0 = th_prev * is;
-    const double x = t0 * (1.0 + ltol * (double)(lane + 1) / 64.0);
-    const unsigned long long mask = __ballot(sturm_count(tp, m, x) == m);
-    if (mask) {
-      *conv = true;
-      const int t = __ffsll((long long)mask) - 1;
-      return th_prev * (1.0 + ltol * (double)(t + 1) / 64.0);
-    }
-    lo = t0 * (1.0 + ltol);
-  } else {
-    lo = 1e300;
-  }
   // Gershgorin interval
   double glo = 1e300, ghi = -1e300;
   if (lane < m) {
@@ -271,8 +280,31 @@ __device__ __forceinline__ double wave_tridiag_lmax(double ta, double tb, int m,
   }
   glo = rlane(glo, 0);
   ghi = rlane(ghi, 0);
-  hi = ghi + fabs(ghi) * 1e-6 + 1e-300;
-  lo = (th_prev > 0.0) ? fmin(lo, hi) : glo;
+  double hi = ghi + fabs(ghi) * 1e-6 + 1e-300;
+  double lo = glo;
+  const double t0 = th_prev * is;
+  if (t0 > 0.0) {
+    // probe l: t0 (1 + f_l), f_l = ltol (l + 1) / 16 for l < 16, then
+    // ltol 2^(g (l - 15) / 48) with ltol 2^g = hi / t0 - 1 (g clamped to
+    // [2, 120]; probes above hi only confirm the bound)
+    const float g = fminf(fmaxf(__log2f((float)((hi / t0 - 1.0) / ltol)), 2.f), 120.f);
+    const double f = (lane < 16) ? ltol * (double)(lane + 1) * (1.0 / 16.0)
+                                 : ltol * (double)exp2f(g * (float)(lane - 15) * (1.0f / 48.0f));
+    const double x = t0 * (1.0 + f);
+    const unsigned long long mask = __ballot(sturm_count(tp, m, x) == m);
+    if (mask) {
+      const int t = __ffsll((long long)mask) - 1;
+      const double xt = rlane(x, t);
+      if (t < 16) {
+        *conv = true;
+        return xt * tmax;
+      }
+      hi = xt;
+      lo = (t > 0) ? rlane(x, t - 1) : t0;
+    } else {
+      lo = rlane(x, 63);
+    }
+  }
   for (int round = 0; round < 10; ++round) {
     const double w = hi - lo;
     if (!(w > fabs(hi) * rtol)) break;
@@ -626,9 +658,8 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
         break;
       }
       const zd y = (part[lane] + part[UN + lane]) + (part[2 * UN + lane] + part[3 * UN + lane]);
-      const double al = wave_sum_dpp(x.x * y.x + x.y * y.y);
-      const double yy = wave_sum_dpp(nrm2(y));
-      const double py = wave_sum_dpp(pp.x * y.x + pp.y * y.y);
+      double al = x.x * y.x + x.y * y.y, yy = nrm2(y), py = pp.x * y.x + pp.y * y.y;
+      wave_sum3_dpp(al, yy, py);
       const double bb = sqrt(fmax(yy - al * al - 2.0 * beta_prev * py + beta_prev * beta_prev, 0.0));
       if (lane == j) {
         ta = al;
