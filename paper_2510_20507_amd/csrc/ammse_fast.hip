@@ -305,18 +305,28 @@ __device__ __forceinline__ double wave_tridiag_lmax(double ta, double tb, int m,
       lo = rlane(x, 63);
     }
   }
+  const double fr = (double)(lane + 1) * (1.0 / 65.0);
   for (int round = 0; round < 10; ++round) {
     const double w = hi - lo;
     if (!(w > fabs(hi) * rtol)) break;
-    const double x = lo + w * (double)(lane + 1) / 65.0;
+    const double x = lo + w * fr;
     const unsigned long long mask = __ballot(sturm_count(tp, m, x) == m);
     const int t = mask ? (__ffsll((long long)mask) - 1) : 64;
-    const double nhi = (t < 64) ? lo + w * (double)(t + 1) / 65.0 : hi;
-    const double nlo = (t > 0) ? lo + w * (double)t / 65.0 : lo;
+    const double nhi = (t < 64) ? rlane(x, t) : hi;
+    const double nlo = (t > 0) ? rlane(x, t - 1) : lo;
     lo = nlo;
     hi = nhi;
   }
   return hi * tmax;
+}
+
+// Position of entry (row, col) of G inside the 4 x 4 block of its row group
+// when col is one of the row's own streams (block-diagonal packing of the
+// users' N x d own blocks, N = d), else -1.
+__device__ __forceinline__ int own_entry(int row, int col, int lgN, int lgd) {
+  const int u = row >> lgN, c = col - (u << lgd);
+  const int u0 = (row & ~3) >> lgN;
+  return (c >= 0 && c < (1 << lgd)) ? (row & 3) * 4 + ((u - u0) << lgN) + c : -1;
 }
 
 // Value of lane (lane ^ BIT) within the 16-lane row, BIT in {1, 2, 4, 8}.
@@ -765,12 +775,23 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
     const float om = p.extrapolate ? (float)fmax((t - 2.0) / (t + 1.0), 0.0) : 0.f;
 #pragma unroll
     for (int i = 0; i < S::GRB; ++i) {
-      const int row0 = 16 * (wave + 4 * i) + 4 * lk, g4 = row0 >> 2, u0 = row0 >> lgN;
+      const int row0 = 16 * (wave + 4 * i) + 4 * lk, g4 = row0 >> 2;
       float2 dm[4][4];
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int k = 0; k < 4; ++k) dm[r][k] = Ds[g4 * 16 + r * 4 + k];
+      // Y is nonzero only on the own entries, which lie in column block jo
+      // (N = d here); the lane's four candidates are loaded up front
+      const int jo = wave + 4 * i;
+      bool own[4];
+      float2 yo[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int e = own_entry(row0 + r, 16 * jo + li, lgN, lgd);
+        own[r] = e >= 0;
+        yo[r] = Ys[g4 * 16 + max(e, 0)];
+      }
 #pragma unroll
       for (int j = 0; j < S::UDB; ++j) {
         float2 gh[4];
@@ -787,13 +808,9 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
             zx += dm[r][k].x * gh[k].x - dm[r][k].y * gh[k].y;
             zy += dm[r][k].x * gh[k].y + dm[r][k].y * gh[k].x;
           }
-          // Y is nonzero only on the own block; its load is issued for every
-          // entry (clamped index) so the loads are not serialised by branches
-          const int u = (row0 + r) >> lgN, c = col - (u << lgd);
-          const bool own = c >= 0 && c < d;
-          const float2 y = Ys[g4 * 16 + r * 4 + ((u - u0) << lgN) + min(max(c, 0), d - 1)];
-          zx = own ? zx - y.x : zx;
-          zy = own ? zy - y.y : zy;
+          const bool sub = (j == jo) && own[r];
+          zx = sub ? zx - yo[r].x : zx;
+          zy = sub ? zy - yo[r].y : zy;
           Bs[(row0 + r) * S::BLD + col] = c2(zx, zy);
         }
       }
@@ -842,21 +859,25 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
       c2s = c1;
       c1 = scd * ch;
 #pragma unroll
-      for (int i = 0; i < S::GRB; ++i)
+      for (int i = 0; i < S::GRB; ++i) {
 #pragma unroll
         for (int j = 0; j < S::UDB; ++j)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int row = 16 * (wave + 4 * i) + 4 * lk + r, col = 16 * j + li;
             Xp[i][j][r] = c2(sc * Xp[i][j][r].x, sc * Xp[i][j][r].y);
-            const float2 g = c2(sc * Gp[i][j][r].x, sc * Gp[i][j][r].y);
-            Gp[i][j][r] = g;
-            const int u = row >> lgN, c = col - (u << lgd);
-            if (c >= 0 && c < d) {
-              const int g4 = row >> 2, u0 = (g4 * 4) >> lgN;
-              Fs[g4 * 16 + r * 4 + ((u - u0) << lgN) + c] = g;
-            }
+            Gp[i][j][r] = c2(sc * Gp[i][j][r].x, sc * Gp[i][j][r].y);
           }
+        // own entries (column block jo, N = d) into Fs for the receivers
+        const int row0 = 16 * (wave + 4 * i) + 4 * lk, jo = wave + 4 * i;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float2 g = Gp[i][0][r];
+#pragma unroll
+          for (int j = 1; j < S::UDB; ++j) g = (j == jo) ? Gp[i][j][r] : g;
+          const int e = own_entry(row0 + r, 16 * jo + li, lgN, lgd);
+          if (e >= 0) Fs[(row0 >> 2) * 16 + e] = g;
+        }
+      }
     }
     prev_step_stage2 = stage2;
     iters_run = t;
