@@ -480,20 +480,25 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
       float2 s[16];
 #pragma unroll
       for (int e = 0; e < 16; ++e) s[e] = c2(0.f, 0.f);
+      // own columns (block jo, N = d) are left out by zeroing them; rows a and
+      // c pair only within one user (row0 is a multiple of 4)
+      const int jo = wave + 4 * i;
+      bool ownr[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) ownr[r] = own_entry(row0 + r, 16 * jo + li, lgN, lgd) >= 0;
 #pragma unroll
       for (int j = 0; j < S::UDB; ++j) {
-        const int col = 16 * j + li;
-        bool own[4];
+        float2 gz[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) own[r] = (col >> lgd) == ((row0 + r) >> lgN);
+        for (int r = 0; r < 4; ++r) gz[r] = (j == jo && ownr[r]) ? c2(0.f, 0.f) : Gp[i][j][r];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
           for (int c = a; c < 4; ++c) {
-            const bool use = ((row0 + a) >> lgN == (row0 + c) >> lgN) && !own[a];
-            const float2 ga = Gp[i][j][a], gc = Gp[i][j][c];
+            const bool same = (a >> lgN) == (c >> lgN);
+            const float2 ga = gz[a], gc = gz[c];
             const float2 t = c2(ga.x * gc.x + ga.y * gc.y, ga.y * gc.x - ga.x * gc.y);
-            if (use) s[a * 4 + c] = c2(s[a * 4 + c].x + t.x, s[a * 4 + c].y + t.y);
+            if (same) s[a * 4 + c] = c2(s[a * 4 + c].x + t.x, s[a * 4 + c].y + t.y);
           }
       }
 #pragma unroll
