@@ -213,28 +213,28 @@ __device__ __forceinline__ double block_sum4(double v, double* red) {
 }
 
 // Number of eigenvalues below x of the symmetric tridiagonal matrix held in
-// LDS as pairs tp[k] = (a_k, b_{k-1}^2) (entries of magnitude <= 1; entries
-// from m on padded with a = 8, b = 0, which adds eigenvalues above every
-// probe and leaves the count unchanged).  Sign changes of the leading
-// principal minors p_k(x) = det(T_k - x I), computed without divisions
-// (p_{k+1} = (a_k - x) p_k - b_{k-1}^2 p_{k-1}) and rescaled by powers of two
-// every four steps to stay in range.
+// LDS as 64 pairs tp[k] = (a_k, b_{k-1}^2) (entries of magnitude <= 1, b_{-1}
+// = 0; entries from m on padded with a = 8, b = 0, which adds eigenvalues
+// above every probe and leaves the count unchanged).  Sign changes of the
+// leading principal minors p_k(x) = det(T_k - x I), p_{-1} = 1, computed
+// without divisions (p_k = (a_k - x) p_{k-1} - b_{k-1}^2 p_{k-2}) in blocks
+// of eight steps (the eight pairs are loaded together; blocks past m read
+// padding) and rescaled by powers of two after each block to stay in range.
 __device__ __forceinline__ int sturm_count(const double2* tp, int m, double x) {
   const double big = 0x1p400, small = 0x1p-400;
-  double pm = 1.0, pc = tp[0].x - x;
+  double pm = 0.0, pc = 1.0;
   auto sgn = [](double v) { return (unsigned)((unsigned long long)__double_as_longlong(v) >> 63); };
-  unsigned cnt = sgn(pc);
-  for (int i = 1; i < m; i += 4) {
+  unsigned cnt = 0;
+  for (int i = 0; i < m; i += 8) {                // i <= 56: every k below 64
+    double2 e[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int k = i + u;
-      if (k < 64) {                              // uniform; steps from m on are padding
-        const double2 e = tp[k];
-        const double pn = fma(e.x - x, pc, -e.y * pm);
-        cnt += sgn(pn) ^ sgn(pc);
-        pm = pc;
-        pc = pn;
-      }
+    for (int u = 0; u < 8; ++u) e[u] = tp[i + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double pn = fma(e[u].x - x, pc, -e[u].y * pm);
+      cnt += sgn(pn) ^ sgn(pc);
+      pm = pc;
+      pc = pn;
     }
     const double mag = fmax(fabs(pc), fabs(pm));
     const double f = (mag > big) ? small : ((mag < small) ? big : 1.0);
@@ -242,6 +242,21 @@ __device__ __forceinline__ int sturm_count(const double2* tp, int m, double x) {
     pm *= f;
   }
   return (int)cnt;
+}
+
+__device__ __forceinline__ double wave_min_dpp(double v) {
+  v = fmin(v, dpp64<0xB1>(v));
+  v = fmin(v, dpp64<0x4E>(v));
+  v = fmin(v, dpp64<0x124>(v));
+  v = fmin(v, dpp64<0x128>(v));
+  return fmin(fmin(rlane(v, 0), rlane(v, 16)), fmin(rlane(v, 32), rlane(v, 48)));
+}
+__device__ __forceinline__ double wave_max_dpp(double v) {
+  v = fmax(v, dpp64<0xB1>(v));
+  v = fmax(v, dpp64<0x4E>(v));
+  v = fmax(v, dpp64<0x124>(v));
+  v = fmax(v, dpp64<0x128>(v));
+  return fmax(fmax(rlane(v, 0), rlane(v, 16)), fmax(rlane(v, 32), rlane(v, 48)));
 }
 
 // Largest eigenvalue, to relative width 1e-10, of the m x m symmetric
@@ -262,24 +277,14 @@ __device__ __forceinline__ double wave_tridiag_lmax(double ta, double tb, int m,
   const double is = 1.0 / tmax;
   const double an = (lane < m) ? ta * is : 8.0;
   const double bn = (lane < m - 1) ? tb * is : 0.0;
-  const double bl_ = __shfl_up(bn, 1, 64);
-  tp[lane] = make_double2(an, (lane > 0) ? bl_ * bl_ : 0.0);
+  const double bup = __shfl_up(bn, 1, 64);      // by every lane (no divergent shuffle)
+  const double bl_ = (lane > 0) ? bup : 0.0;    // b_{lane-1}
+  tp[lane] = make_double2(an, bl_ * bl_);
   *conv = false;
   // Gershgorin interval
-  double glo = 1e300, ghi = -1e300;
-  if (lane < m) {
-    const double bl = (lane > 0) ? fabs(bl_) : 0.0;
-    const double br = (lane < m - 1) ? fabs(bn) : 0.0;
-    glo = an - bl - br;
-    ghi = an + bl + br;
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    glo = fmin(glo, __shfl_xor(glo, off, 64));
-    ghi = fmax(ghi, __shfl_xor(ghi, off, 64));
-  }
-  glo = rlane(glo, 0);
-  ghi = rlane(ghi, 0);
+  const double rad = fabs(bl_) + fabs(bn);
+  const double glo = wave_min_dpp((lane < m) ? an - rad : 1e300);
+  const double ghi = wave_max_dpp((lane < m) ? an + rad : -1e300);
   double hi = ghi + fabs(ghi) * 1e-6 + 1e-300;
   double lo = glo;
   const double t0 = th_prev * is;
