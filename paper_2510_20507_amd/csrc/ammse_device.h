@@ -121,16 +121,43 @@ __device__ __forceinline__ void trsm_lower_h(const zd* L, zd* X) {
 // Largest eigenvalue of a symmetric tridiagonal matrix by multisection on
 // Sturm counts (256 probe points per round, all threads cooperate).
 // ---------------------------------------------------------------------------
-__device__ inline int sturm_below(const double* a, const double* b, int m, double x) {
-  int cnt = 0;
-  double q = a[0] - x;
-  if (q < 0) ++cnt;
-  for (int i = 1; i < m; ++i) {
-    if (q == 0.0) q = 1e-300;
-    q = a[i] - x - b[i - 1] * b[i - 1] / q;
-    if (q < 0) ++cnt;
+// Number of eigenvalues below x of the symmetric tridiagonal matrix with
+// diagonal a and off-diagonal b (LDS arrays of AMMSE_MAX_LANCZOS entries, m of
+// them used): sign changes of the leading principal minors of s (T - x I),
+// p_k = (a_k - x) p_{k-1} - b_{k-1}^2 p_{k-2} with p_{-1} = 1, computed
+// without divisions (s scales the entries to magnitude <= 1) in blocks of
+// eight steps whose loads are issued together (steps from m on are skipped),
+// rescaled by powers of two after each block.
+__device__ inline int sturm_below(const double* a, const double* b, int m, double x, double s) {
+  static_assert(AMMSE_MAX_LANCZOS % 8 == 0, "blocks of eight stay inside the arrays");
+  const double big = 0x1p400, small = 0x1p-400;
+  const double xs = x * s;
+  double pm = 0.0, pc = 1.0;
+  unsigned cnt = 0;
+  for (int i = 0; i < m; i += 8) {
+    double av[8], bv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      av[u] = a[i + u];
+      bv[u] = b[(i + u > 0) ? i + u - 1 : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double bs = bv[u] * s;
+      const double pn = fma(av[u] * s - xs, pc, -(bs * bs) * pm);
+      const bool act = i + u < m;
+      const unsigned ch = (unsigned)(((unsigned long long)__double_as_longlong(pn) ^
+                                      (unsigned long long)__double_as_longlong(pc)) >> 63);
+      cnt += act ? ch : 0u;
+      pm = act ? pc : pm;
+      pc = act ? pn : pc;
+    }
+    const double mag = fmax(fabs(pc), fabs(pm));
+    const double f = (mag > big) ? small : ((mag < small) ? big : 1.0);
+    pc *= f;
+    pm *= f;
   }
-  return cnt;
+  return (int)cnt;
 }
 
 // la, lb: diagonal and off-diagonal in LDS; imin: an LDS int used for the
@@ -144,13 +171,19 @@ __device__ inline double tridiag_lmax(const double* la, const double* lb, int m,
                                      double ltol = 0.0, bool* conv = nullptr) {
   double lo = 1e300, hi = -1e300;
   if (conv) *conv = false;
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? fabs(lb[i - 1]) : 0.0) + (i < m - 1 ? fabs(lb[i]) : 0.0);
+    lo = fmin(lo, la[i] - r);
+    hi = fmax(hi, la[i] + r);
+  }
+  const double sc = 1.0 / fmax(fmax(fabs(lo), fabs(hi)), 1e-300);
   double qlo = -1e300;
   if (conv && th_prev > 0.0) {
     const double n1 = (double)blockDim.x;
     if (threadIdx.x == 0) *imin = blockDim.x;
     __syncthreads();
     const double x = th_prev * (1.0 + ltol * (double)(threadIdx.x + 1) / n1);
-    if (sturm_below(la, lb, m, x) == m) atomicMin(imin, (int)threadIdx.x);
+    if (sturm_below(la, lb, m, x, sc) == m) atomicMin(imin, (int)threadIdx.x);
     __syncthreads();
     const int t = *imin;
     __syncthreads();
@@ -160,11 +193,6 @@ __device__ inline double tridiag_lmax(const double* la, const double* lb, int m,
     }
     qlo = th_prev * (1.0 + ltol);
   }
-  for (int i = 0; i < m; ++i) {
-    const double r = (i > 0 ? fabs(lb[i - 1]) : 0.0) + (i < m - 1 ? fabs(lb[i]) : 0.0);
-    lo = fmin(lo, la[i] - r);
-    hi = fmax(hi, la[i] + r);
-  }
   hi += 1e-300 + fabs(hi) * 1e-15;
   if (qlo > lo) lo = fmin(qlo, hi);
   for (int round = 0; round < 8; ++round) {
@@ -173,7 +201,7 @@ __device__ inline double tridiag_lmax(const double* la, const double* lb, int m,
     if (threadIdx.x == 0) *imin = blockDim.x;
     __syncthreads();
     const double x = lo + w * (double)(threadIdx.x + 1) / (double)(blockDim.x + 1);
-    if (sturm_below(la, lb, m, x) == m) atomicMin(imin, (int)threadIdx.x);
+    if (sturm_below(la, lb, m, x, sc) == m) atomicMin(imin, (int)threadIdx.x);
     __syncthreads();
     const int t = *imin;
     const double nhi = (t < (int)blockDim.x) ? lo + w * (double)(t + 1) / (double)(blockDim.x + 1) : hi;
