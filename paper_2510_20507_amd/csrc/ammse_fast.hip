@@ -502,8 +502,9 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
           for (int c = a; c < 4; ++c) {
             const bool same = (a >> lgN) == (c >> lgN);
             const float2 ga = gz[a], gc = gz[c];
-            const float2 t = c2(ga.x * gc.x + ga.y * gc.y, ga.y * gc.x - ga.x * gc.y);
-            if (same) s[a * 4 + c] = c2(s[a * 4 + c].x + t.x, s[a * 4 + c].y + t.y);
+            const float2 sn = c2(fmaf(ga.y, gc.y, fmaf(ga.x, gc.x, s[a * 4 + c].x)),
+                                 fmaf(-ga.x, gc.y, fmaf(ga.y, gc.x, s[a * 4 + c].y)));
+            if (same) s[a * 4 + c] = sn;
           }
       }
 #pragma unroll
@@ -658,8 +659,8 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
           float2& acc = (k & 1) ? yb : ya;
-          acc.x += kv[k].x * xv[k].x - kv[k].y * xv[k].y;
-          acc.y += kv[k].x * xv[k].y + kv[k].y * xv[k].x;
+          acc.x = fmaf(-kv[k].y, xv[k].y, fmaf(kv[k].x, xv[k].x, acc.x));
+          acc.y = fmaf(kv[k].y, xv[k].x, fmaf(kv[k].x, xv[k].y, acc.y));
         }
       }
       const zd yw = {(double)ya.x + (double)yb.x, (double)ya.y + (double)yb.y};
@@ -815,8 +816,8 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
           float zx = 0.f, zy = 0.f;
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
-            zx += dm[r][k].x * gh[k].x - dm[r][k].y * gh[k].y;
-            zy += dm[r][k].x * gh[k].y + dm[r][k].y * gh[k].x;
+            zx = fmaf(-dm[r][k].y, gh[k].y, fmaf(dm[r][k].x, gh[k].x, zx));
+            zy = fmaf(dm[r][k].y, gh[k].x, fmaf(dm[r][k].x, gh[k].y, zy));
           }
           const bool sub = (j == jo) && own[r];
           zx = sub ? zx - yo[r].x : zx;
