@@ -357,12 +357,13 @@ __device__ __forceinline__ zd l4_colk(zd v) {
 // whole, so row K above the diagonal still holds conj(column K) and supplies
 // L[b][K] = conj(A[K][b]) / l without a transposed read.
 template <int K>
-__device__ __forceinline__ void chol16_step(const Lane4& L, zd& A, bool& ok) {
+__device__ __forceinline__ void chol16_step(const Lane4& L, zd& A, bool& ok, double& ik) {
   const double dkk = l4_diag<K>(A).x;
   const zd rk = l4_colk<K>(A);                  // A[K][b]
   ok = ok && (dkk > 0.0) && isfinite(dkk);
   const double l = sqrt(fmax(dkk, 1e-300));
   const double il = 1.0 / l;
+  ik = il;
   // lane-dependent updates as selects (no divergent branches)
   const zd sa = scal(il, A);
   A = sel(L.b == K && L.a > K, sa, A);
@@ -374,12 +375,17 @@ __device__ __forceinline__ void chol16_step(const Lane4& L, zd& A, bool& ok) {
 
 // In place Cholesky (lower) of a Hermitian matrix; ok is cleared when a pivot
 // is not positive/finite.
-__device__ __forceinline__ zd chol16(const Lane4& L, zd A, bool& ok) {
-  chol16_step<0>(L, A, ok);
-  chol16_step<1>(L, A, ok);
-  chol16_step<2>(L, A, ok);
-  chol16_step<3>(L, A, ok);
+// id: the reciprocals of the diagonal of the factor (for the solves below).
+__device__ __forceinline__ zd chol16(const Lane4& L, zd A, bool& ok, double (&id)[4]) {
+  chol16_step<0>(L, A, ok, id[0]);
+  chol16_step<1>(L, A, ok, id[1]);
+  chol16_step<2>(L, A, ok, id[2]);
+  chol16_step<3>(L, A, ok, id[3]);
   return sel(L.b > L.a, zd{0.0, 0.0}, A);
+}
+__device__ __forceinline__ zd chol16(const Lane4& L, zd A, bool& ok) {
+  double id[4];
+  return chol16(L, A, ok, id);
 }
 
 template <int K>
@@ -391,10 +397,10 @@ __device__ __forceinline__ void trsm16_step(const Lane4& L, const zd& lq, double
   X = sel(L.a > K, up, X);
 }
 
-// X <- Lo^{-1} X (forward substitution, Lo lower with real diagonal)
-__device__ __forceinline__ zd trsm16(const Lane4& L, zd Lo, zd X) {
-  const double i0 = 1.0 / l4_diag<0>(Lo).x, i1 = 1.0 / l4_diag<1>(Lo).x;
-  const double i2 = 1.0 / l4_diag<2>(Lo).x, i3 = 1.0 / l4_diag<3>(Lo).x;
+// X <- Lo^{-1} X (forward substitution, Lo lower with real diagonal whose
+// reciprocals are id)
+__device__ __forceinline__ zd trsm16(const Lane4& L, zd Lo, const double (&id)[4], zd X) {
+  const double i0 = id[0], i1 = id[1], i2 = id[2], i3 = id[3];
   const zd q0 = l4_rowq<0>(Lo), q1 = l4_rowq<1>(Lo), q2 = l4_rowq<2>(Lo);
   trsm16_step<0>(L, q0, i0, X);
   trsm16_step<1>(L, q1, i1, X);
@@ -413,15 +419,31 @@ __device__ __forceinline__ void trsm16h_step(const Lane4& L, const zd& lka, doub
 }
 
 // X <- Lo^{-H} X (back substitution with the conjugate transpose)
-__device__ __forceinline__ zd trsm16h(const Lane4& L, zd Lo, zd X) {
-  const double i0 = 1.0 / l4_diag<0>(Lo).x, i1 = 1.0 / l4_diag<1>(Lo).x;
-  const double i2 = 1.0 / l4_diag<2>(Lo).x, i3 = 1.0 / l4_diag<3>(Lo).x;
+__device__ __forceinline__ zd trsm16h(const Lane4& L, zd Lo, const double (&id)[4], zd X) {
+  const double i0 = id[0], i1 = id[1], i2 = id[2], i3 = id[3];
   const zd t1 = L.at(Lo, 1, L.a), t2 = L.at(Lo, 2, L.a), t3 = L.at(Lo, 3, L.a);   // Lo[k][a]
   trsm16h_step<3>(L, t3, i3, X);
   trsm16h_step<2>(L, t2, i2, X);
   trsm16h_step<1>(L, t1, i1, X);
   const zd sx = scal(i0, X);
   return sel(L.a == 0, sx, X);
+}
+
+__device__ __forceinline__ void diag_recip(zd Lo, double (&id)[4]) {
+  id[0] = 1.0 / l4_diag<0>(Lo).x;
+  id[1] = 1.0 / l4_diag<1>(Lo).x;
+  id[2] = 1.0 / l4_diag<2>(Lo).x;
+  id[3] = 1.0 / l4_diag<3>(Lo).x;
+}
+__device__ __forceinline__ zd trsm16(const Lane4& L, zd Lo, zd X) {
+  double id[4];
+  diag_recip(Lo, id);
+  return trsm16(L, Lo, id, X);
+}
+__device__ __forceinline__ zd trsm16h(const Lane4& L, zd Lo, zd X) {
+  double id[4];
+  diag_recip(Lo, id);
+  return trsm16h(L, Lo, id, X);
 }
 
 // A^H B, A B, A B^H

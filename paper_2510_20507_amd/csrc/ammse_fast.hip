@@ -521,17 +521,18 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
       if (L4.a == L4.b) J = {J.x + 1.0, 0.0};
       const float2 fo = Fs[(row0 >> 2) * 16 + li];
       zd F = {(double)fo.x, (double)fo.y};
-      const zd Lo = chol16(L4, J, ok);
-      F = trsm16(L4, Lo, F);                      // L^{-1} G_own
+      double io[4], iw[4];                        // reciprocal diagonals of the factors
+      const zd Lo = chol16(L4, J, ok, io);
+      F = trsm16(L4, Lo, io, F);                  // L^{-1} G_own
       zd X = mm_hn(L4, F, F);                     // I + F^H F
       if (L4.a == L4.b) X = {X.x + 1.0, 0.0};
-      UWr[i] = trsm16h(L4, Lo, F);                // J-^{-1} G_own
-      const zd Lw = chol16(L4, X, ok);
+      UWr[i] = trsm16h(L4, Lo, io, F);            // J-^{-1} G_own
+      const zd Lw = chol16(L4, X, ok, iw);
       // rate term 2 log Lw_aa in float (the WSR enters only the stage and stop
       // tests and the reported value, all at FP32 accuracy here)
       if (with_rate && L4.a == L4.b)
         rsum += alpha[row0 + L4.a] * (double)(2.0f * __logf((float)Lw.x));
-      const zd Li = trsm16(L4, Lw, zd{(L4.a == L4.b) ? 1.0 : 0.0, 0.0});
+      const zd Li = trsm16(L4, Lw, iw, zd{(L4.a == L4.b) ? 1.0 : 0.0, 0.0});
       Lir[i] = Li;                                // E = Li^H Li (formed where needed)
     }
     if (!ok) atomicOr(&misc[0], AMMSE_INST_CHOLESKY);
@@ -858,7 +859,8 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
             const float2 xt = c2((1.f + om) * xp.x - om * xq.x - g2 * z.x,
                                  (1.f + om) * xp.y - om * xq.y - g2 * z.y);
             const float2 g0 = G0S[e];
-            acc += chf * (g0.x * xt.x + g0.y * xt.y) + (xt.x * gt.x + xt.y * gt.y);
+            acc = fmaf(xt.x, fmaf(chf, g0.x, gt.x), acc);   // Re<X~, c G^0 + G~>
+            acc = fmaf(xt.y, fmaf(chf, g0.y, gt.y), acc);
             XqS[e] = xp;             // X^{t-1} becomes X^{t-2}
             Xp[i][j][r] = xt;        // temporarily X~
             Gq[i][j][r] = gp;

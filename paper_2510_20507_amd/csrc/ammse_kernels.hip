@@ -226,13 +226,14 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
         F = scal(gscale, to_d(G[(long)un * sm.colOff[c] + (long)(uu * N + ea) * nc + j0 + eb]));
       }
       bool oku = true;
-      const zd Lo = chol16(L4, J, oku);
-      F = trsm16(L4, Lo, F);                      // L^{-1} G_own
+      double io[4], iw[4];                        // reciprocal diagonals of the factors
+      const zd Lo = chol16(L4, J, oku, io);
+      F = trsm16(L4, Lo, io, F);                  // L^{-1} G_own
       zd X = mm_hn(L4, F, F);                     // I + F^H F
       if (ea == eb) X = {X.x + 1.0, 0.0};
-      const zd UWv = trsm16h(L4, Lo, F);          // J-^{-1} G_own
-      const zd Lw = chol16(L4, X, oku);
-      const zd Li = trsm16(L4, Lw, zd{(ea == eb) ? 1.0 : 0.0, 0.0});
+      const zd UWv = trsm16h(L4, Lo, io, F);      // J-^{-1} G_own
+      const zd Lw = chol16(L4, X, oku, iw);
+      const zd Li = trsm16(L4, Lw, iw, zd{(ea == eb) ? 1.0 : 0.0, 0.0});
       const zd Ev = mm_hn(L4, Li, Li);            // E = Lw^{-H} Lw^{-1}
       if (act) {
         if (ea == eb) rsum += sm.alpha[u] * 2.0 * log(Lw.x);

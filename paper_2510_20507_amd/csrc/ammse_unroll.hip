@@ -189,13 +189,14 @@ __device__ double u_receivers(const UView<R>& w, USmem<R>& sm, const cx<R>* G, z
     zd F = {0.0, 0.0};
     if (L4.a < N && L4.b < d) F = to_d(G[(long)(uu * N + L4.a) * ud + uu * d + L4.b]);
     bool oku = true;
-    const zd Lo = chol16(L4, J, oku);
-    F = trsm16(L4, Lo, F);
+    double io[4], iw[4];                        // reciprocal diagonals of the factors
+    const zd Lo = chol16(L4, J, oku, io);
+    F = trsm16(L4, Lo, io, F);
     zd X = mm_hn(L4, F, F);
     if (L4.a == L4.b) X = {X.x + 1.0, 0.0};
-    const zd UWv = trsm16h(L4, Lo, F);
-    const zd Lw = chol16(L4, X, oku);
-    const zd Li = trsm16(L4, Lw, zd{(L4.a == L4.b) ? 1.0 : 0.0, 0.0});
+    const zd UWv = trsm16h(L4, Lo, io, F);
+    const zd Lw = chol16(L4, X, oku, iw);
+    const zd Li = trsm16(L4, Lw, iw, zd{(L4.a == L4.b) ? 1.0 : 0.0, 0.0});
     const zd Ev = mm_hn(L4, Li, Li);
     if (act) {
       if (L4.a == L4.b) rsum += sm.alpha[u] * 2.0 * log(Lw.x);
