@@ -691,7 +691,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
       tmax = fmax(tmax, fabs(al) + bb);
       const bool breakdown = !(bb > 1e-12 * tmax);
       // only wave 0's decision is used (shared through LDS above)
-      if (wave == 0 && (breakdown || (msz >= 16 && (msz % 4) == 0) || msz == m)) {
+      if (wave == 0 && (breakdown || (msz >= 14 && (msz % 2) == 0) || msz == m)) {
         bool conv = false;
         theta = (tmax > 0.0) ? wave_tridiag_lmax(ta, tb, msz, tmax, theta, ltol, tp, &conv) : 0.0;
         stop = breakdown || conv || msz == m;

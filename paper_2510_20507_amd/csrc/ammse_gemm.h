@@ -91,16 +91,27 @@ __device__ void block_gemm(int m, int n, int k, const cx<R>* __restrict__ A, lon
             row = e / KC;
           }
           const int gi = i0 + row, gk = k0 + kk;
-          cx<R> v = {R(0), R(0)};
-          if (gi < m && gk < k) v = CONJA ? cj(A[(long)gk * lda + gi]) : A[(long)gi * lda + gk];
-          As[kk * (TM + 1) + row] = v;
+          // scalar parts, so that the staged value stays in registers
+          R vx = R(0), vy = R(0);
+          if (gi < m && gk < k) {
+            const cx<R> t = CONJA ? A[(long)gk * lda + gi] : A[(long)gi * lda + gk];
+            vx = t.x;
+            vy = CONJA ? -t.y : t.y;
+          }
+          As[kk * (TM + 1) + row].x = vx;
+          As[kk * (TM + 1) + row].y = vy;
         }
         for (int e = tid; e < KC * TN; e += AMMSE_BLOCK) {
           const int col = CONJB ? e / KC : e % TN, kk = CONJB ? e % KC : e / TN;
           const int gj = j0 + col, gk = k0 + kk;
-          cx<R> v = {R(0), R(0)};
-          if (gj < n && gk < k) v = CONJB ? cj(B[(long)gj * ldb + gk]) : B[(long)gk * ldb + gj];
-          Bs[kk * (TN + 1) + col] = v;
+          R vx = R(0), vy = R(0);
+          if (gj < n && gk < k) {
+            const cx<R> t = CONJB ? B[(long)gj * ldb + gk] : B[(long)gk * ldb + gj];
+            vx = t.x;
+            vy = CONJB ? -t.y : t.y;
+          }
+          Bs[kk * (TN + 1) + col].x = vx;
+          Bs[kk * (TN + 1) + col].y = vy;
         }
         __syncthreads();
 #pragma unroll 4
