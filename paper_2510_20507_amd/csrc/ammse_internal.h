@@ -30,6 +30,7 @@ struct ammse_ws_layout_t {
                               // double complex)
   size_t Qm;                  // S H H^H S ((U N) x (U N), storage precision), see below
   size_t Hb, Xb, Zb;          // bfloat16 copies of H, X and Z (mixed precision only)
+  size_t Dmf, Ymf;            // float copies of Dm, Ym (float storage only)
   size_t Lwm, Lim, Cm;        // per-user Lw, Lw^{-1}, C (double complex 4 x 4): WMMSE,
                               // and Lw^{-1}, C for the Q- and Gram-based Lanczos
   size_t Rg, Kg;              // Gram-based Lanczos: R = C^H S H_{:,c} ((U d) x M) and
@@ -143,6 +144,10 @@ __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int
   L.Hb = o;  o += ammse_align256(bb * (size_t)C * un * M);
   L.Xb = o;  o += ammse_align256(bb * (size_t)M * ud);
   L.Zb = o;  o += ammse_align256(bb * un * ud);
+  // float storage: float copies of D and Y for the Z build
+  const size_t fz = (real_bytes == 4) ? 8 : 0;
+  L.Dmf = o; o += ammse_align256((size_t)U * 16 * fz);
+  L.Ymf = o; o += ammse_align256((size_t)U * 16 * fz);
   L.total = o;
   return L;
 }

@@ -114,6 +114,8 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   zd* Em = (zd*)(ws + L.Em);
   zd* Dm = (zd*)(ws + L.Dm);
   zd* Ym = (zd*)(ws + L.Ym);
+  cx<float>* Dmf = (cx<float>*)(ws + L.Dmf);   // float copies (float storage)
+  cx<float>* Ymf = (cx<float>*)(ws + L.Ymf);
   zd* Lq = (zd*)(ws + L.Lq);
   zd* Lw = (zd*)(ws + L.Lw);
   zd* Ly1 = (zd*)(ws + L.Ly1);
@@ -271,6 +273,10 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       if (act) {
         Dm[u * 16 + li] = scal(al, Dv);
         Ym[u * 16 + li] = scal(al, Ur);
+        if constexpr (sizeof(R) == 4) {
+          Dmf[u * 16 + li] = from_d<float>(scal(al, Dv));
+          Ymf[u * 16 + li] = from_d<float>(scal(al, Ur));
+        }
       }
       if (wm || qpath || gpath) {   // D = C C^H: C = sqrt(alpha) UW Lw^{-H} (stage II) or sqrt(alpha) U (stage I)
         const zd Cv = scal(sqrt(al), stage2 ? mm_nh(L4, UWv, Lim[uu * 16 + li]) : T);
@@ -969,9 +975,21 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     // Z = S (D G^ - Y), G^ = (1+w) G^{t-1} - w G^{t-2}: one thread per
     // (user, column), consecutive threads along the columns; the N rows of
     // the user's block of G^ are read once and give the N rows of Z.
+    // Arithmetic in the storage precision's working type: float with float
+    // storage (D and Y from their float copies), double otherwise.
+    using T = typename std::conditional<sizeof(R) == 4, float, double>::type;
+    const cx<T>* DmT;
+    const cx<T>* YmT;
+    if constexpr (sizeof(R) == 4) {
+      DmT = Dmf;
+      YmT = Ymf;
+    } else {
+      DmT = Dm;
+      YmT = Ym;
+    }
     const double om = p.extrapolate ? fmax((t - 2.0) / (t + 1.0), 0.0) : 0.0;
-    const double ga1 = (1.0 + om) * gsp, ga2 = om * gsq;
-    const double xa1 = (1.0 + om) * xs1, xa2 = om * xs2, gz = 2.0 * sm.gamma[0];
+    const T ga1 = (T)((1.0 + om) * gsp), ga2 = (T)(om * gsq);
+    const T xa1 = (T)((1.0 + om) * xs1), xa2 = (T)(om * xs2), gz = (T)(2.0 * sm.gamma[0]);
     for (int c = 0; c < C; ++c) {
       const int nc = sm.cu[c] * d;
       const long base = (long)un * sm.colOff[c];
@@ -980,37 +998,36 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       for (int e = tid; e < ne; e += AMMSE_BLOCK) {
         const int u = e / nc, j = e - u * nc;
         const long g0 = base + (long)(u * N) * nc + j;
-        zd gh[AMMSE_MAX_RX];
+        cx<T> gh[AMMSE_MAX_RX];
 #pragma unroll
         for (int k = 0; k < AMMSE_MAX_RX; ++k) {
-          gh[k] = {0.0, 0.0};
+          gh[k] = {T(0), T(0)};
           if (k < N) {
             const cx<R> a = Gp[g0 + (long)k * nc], q = Gq[g0 + (long)k * nc];
-            gh[k] = {ga1 * (double)a.x - ga2 * (double)q.x, ga1 * (double)a.y - ga2 * (double)q.y};
+            gh[k] = {ga1 * (T)a.x - ga2 * (T)q.x, ga1 * (T)a.y - ga2 * (T)q.y};
           }
         }
         const int j0 = sm.local[u] * d;
         const bool own = sm.cellOf[u] == c && j >= j0 && j < j0 + d;
-        const double is = sm.invsig[u];
+        const T is = (T)sm.invsig[u];
 #pragma unroll
         for (int n = 0; n < AMMSE_MAX_RX; ++n) {
           if (n < N) {
-            zd acc = {0.0, 0.0};
+            cx<T> acc = {T(0), T(0)};
 #pragma unroll
             for (int k = 0; k < AMMSE_MAX_RX; ++k)
-              if (k < N) acc = acc + Dm[u * 16 + n * 4 + k] * gh[k];
-            if (own) acc = acc - Ym[u * 16 + n * 4 + (j - j0)];
+              if (k < N) acc = acc + DmT[u * 16 + n * 4 + k] * gh[k];
+            if (own) acc = acc - YmT[u * 16 + n * 4 + (j - j0)];
             if (rpath) {
               // implicit precoder: Z' = D G^ - Y (the gradient is 2 H^H S Z'),
               // X~ = X^ - 2 gamma Z' over X^{t-2}
               const long e = g0 + (long)n * nc;
               const cx<R> x1 = X1[e], x2 = X2[e];
-              const cx<R> xt = from_d<R>(zd{xa1 * (double)x1.x - xa2 * (double)x2.x - gz * acc.x,
-                                            xa1 * (double)x1.y - xa2 * (double)x2.y - gz * acc.y});
-              X2[e] = xt;
+              X2[e] = cx<R>{(R)(xa1 * (T)x1.x - xa2 * (T)x2.x - gz * acc.x),
+                            (R)(xa1 * (T)x1.y - xa2 * (T)x2.y - gz * acc.y)};
               continue;
             }
-            const cx<R> zv = from_d<R>(scal(is, acc));
+            const cx<R> zv = {(R)(is * acc.x), (R)(is * acc.y)};
             if constexpr (sizeof(R) == 4) {
               if (lowp && copies) {
                 Zb[g0 + (long)n * nc] = to_bfc(zv);
