@@ -359,8 +359,10 @@ __device__ __forceinline__ void rs_level(float2 (&s)[16], int li) {
   }
 }
 
-template <class S>
-__global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
+// The kernel body for N = d = 2^LGN (compile-time, so that the user and
+// own-stream index arithmetic folds).
+template <class S, int LGN>
+__device__ __forceinline__ void fast_body(const ammse_kparams_t& p) {
   extern __shared__ __align__(16) char smem[];
   float2* Hs = (float2*)(smem + S::oH);
   float2* Bs = (float2*)(smem + S::oB);
@@ -379,8 +381,7 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
 
   constexpr int M = S::M, UN = S::UN, UD = S::UD;
   const ammse_desc_t Dd = p.desc[blockIdx.x];
-  const int N = Dd.N, d = Dd.d;
-  const int lgN = __builtin_ctz(N), lgd = __builtin_ctz(d);   // N, d in {1, 2, 4}
+  constexpr int lgN = LGN, lgd = LGN, N = 1 << LGN, d = 1 << LGN;   // N = d in {1, 2, 4}
   const int b = Dd.b;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
@@ -971,6 +972,14 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
                          ? T : iters_run;
     for (int k = last + 1 + tid; k <= T; k += 256) p.trace[(long)b * p.trace_len + k] = NAN;
   }
+}
+
+template <class S>
+__global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
+  const int N = p.desc[blockIdx.x].N;   // uniform over the workgroup
+  if (N == 4) fast_body<S, 2>(p);
+  else if (N == 2) fast_body<S, 1>(p);
+  else fast_body<S, 0>(p);
 }
 
 using Shape64 = Shape<4, 4, 4>;   // M = 64, U*N = 64, U*d = 64
