@@ -40,11 +40,34 @@ __device__ __forceinline__ zd to_d(cx<R> a) { return {(double)a.x, (double)a.y};
 template <class R>
 __device__ __forceinline__ cx<R> from_d(zd a) { return {(R)a.x, (R)a.y}; }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v) {
+  const long long u = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)u, CTRL, 0xF, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)u, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes of a wave (all lanes active); every lane receives the
+// same value: DPP moves within each 16-lane row, then the four row sums.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp64<0xB1>(v);     // quad_perm [1,0,3,2]
+  v += dpp64<0x4E>(v);     // quad_perm [2,3,0,1]
+  v += dpp64<0x124>(v);    // row_ror 4
+  v += dpp64<0x128>(v);    // row_ror 8
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
 // Sum over the block (a multiple of 64 threads, at most 512); every thread
 // receives the same value.
 __device__ inline double block_sum(double v, double* red) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  v = wave_sum(v);
   const int w = threadIdx.x >> 6;
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[w] = v;
@@ -54,11 +77,6 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 // ---------------------------------------------------------------------------
 // 4 x 4 complex double helpers (row-major, fully unrolled)
@@ -321,13 +339,6 @@ struct Lane4 {
   __device__ __forceinline__ zd at(zd v, int r, int c) const { return shz(v, base + 4 * r + c); }
 };
 
-template <int CTRL>
-__device__ __forceinline__ double dpp64(double v) {
-  const long long u = __double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)u, CTRL, 0xF, 0xF, false);
-  const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
 template <int PAT>
 __device__ __forceinline__ double swz64(double v) {
   const long long u = __double_as_longlong(v);
