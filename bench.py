@@ -208,6 +208,37 @@ def gpu_wmmse(batch, ref, max_iters: int = 500, eps: float = 1e-6):
             "precision": "fp32 products, fp64 M x M solves"}
 
 
+def single_instance(reps: int = 20):
+    """The single small instance (M = 8, 4 users, N = d = 2, 10 dB), FP64,
+    200 iterations, A-MMMSE and WMMSE through the same library: time per solve
+    and per iteration (HIP events; one workgroup, latency-bound, no roofline
+    claim) and the WSR reached."""
+    import torch
+    from paper_2510_20507_amd import ammse, synth
+    b = synth.single_small()
+    db = ammse.to_device(b, ammse.PREC_FP64)
+    out = {"workload": b.name, "iters": 200, "precision": "fp64"}
+    for name, algo in (("ammmse", ammse.ALGO_AMMMSE), ("wmmse", ammse.ALGO_WMMSE)):
+        opts = ammse.Options(precision=ammse.PREC_FP64, algorithm=algo, max_iters=200)
+        plan = ammse.Plan(db.table, db.cell_users, opts)
+        ws = plan.workspace()
+        V = db.V0.clone()
+        wsr = torch.empty(1, dtype=torch.float64, device="cuda")
+        plan.solve(db.H, db.sigma2, db.alpha, db.P, V, wsr, workspace=ws)   # warm-up
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            V.copy_(db.V0)
+            plan.solve(db.H, db.sigma2, db.alpha, db.P, V, wsr, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms_per_solve": ms, "us_per_iter": ms * 1e3 / 200, "wsr": float(wsr.item())}
+        plan.close()
+    return out
+
+
 def unrolled_leg(B: int = 1024, T: int = 20, K: int = 5, reps: int = 3):
     """Differentiable unrolled A-MMMSE on the 1024-instance 64-antenna batch
     (16 users, N=d=4, P=20 dB): forward with checkpoints every K iterations
@@ -385,6 +416,7 @@ def main():
     ap.add_argument("--no-wmmse", action="store_true")
     ap.add_argument("--no-unrolled", action="store_true")
     ap.add_argument("--no-early-exit", action="store_true")
+    ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help=f"also run a {CALIB_COPY_MIB} MiB device copy (counter calibration)")
     ap.add_argument("--parse-pmc", nargs="+", metavar="DIR")
@@ -501,6 +533,8 @@ def main():
         line["gpu_wmmse"] = gpu_wmmse(batch, ref)
     if not a.no_unrolled:
         line["unrolled"] = unrolled_leg()
+    if not a.no_single:
+        line["single_instance"] = single_instance()
     if not a.no_early_exit:
         line["early_exit"] = early_exit(batch, ref)
     if a.calib_copy:

@@ -375,13 +375,16 @@ __device__ __forceinline__ void chol16_step(const Lane4& L, zd& A, bool& ok, dou
   const double l = sqrt(fmax(dkk, 1e-300));
   const double il = 1.0 / l;
   ik = il;
-  // lane-dependent updates as selects (no divergent branches)
-  const zd sa = scal(il, A);
-  A = sel(L.b == K && L.a > K, sa, A);
-  A = sel(L.a == K && L.b == K, zd{l, 0.0}, A);
+  // lane-dependent updates through per-lane factors (no divergent branches):
+  // column K from the diagonal down is scaled by 1/l (the diagonal becomes
+  // dkk / l = l, made real), the trailing block loses L[a][K] conj(L[b][K])
+  const double f = (L.b == K && L.a >= K) ? il : 1.0;
+  A = scal(f, A);
+  A.y = (L.a == K && L.b == K) ? 0.0 : A.y;
   const zd lak = l4_rowq<K>(A);                 // L[a][K]
-  const zd up = A - scal(il, lak * rk);
-  A = sel(L.a > K && L.b > K, up, A);
+  const zd pr = lak * rk;
+  const double g = (L.a > K && L.b > K) ? il : 0.0;
+  A = {fma(-g, pr.x, A.x), fma(-g, pr.y, A.y)};
 }
 
 // In place Cholesky (lower) of a Hermitian matrix; ok is cleared when a pivot
@@ -399,45 +402,44 @@ __device__ __forceinline__ zd chol16(const Lane4& L, zd A, bool& ok) {
   return chol16(L, A, ok, id);
 }
 
+// lq: entry (a, K) of the factor with its diagonal zeroed (so rows a <= K
+// are left alone by the update).
 template <int K>
 __device__ __forceinline__ void trsm16_step(const Lane4& L, const zd& lq, double ik, zd& X) {
-  const zd sx = scal(ik, X);
-  X = sel(L.a == K, sx, X);
+  X = scal((L.a == K) ? ik : 1.0, X);
   const zd xkb = l4_colk<K>(X);
-  const zd up = X - lq * xkb;
-  X = sel(L.a > K, up, X);
+  X = X - lq * xkb;
 }
 
 // X <- Lo^{-1} X (forward substitution, Lo lower with real diagonal whose
 // reciprocals are id)
 __device__ __forceinline__ zd trsm16(const Lane4& L, zd Lo, const double (&id)[4], zd X) {
   const double i0 = id[0], i1 = id[1], i2 = id[2], i3 = id[3];
-  const zd q0 = l4_rowq<0>(Lo), q1 = l4_rowq<1>(Lo), q2 = l4_rowq<2>(Lo);
+  const zd Lz = sel(L.a == L.b, zd{0.0, 0.0}, Lo);   // strictly lower part
+  const zd q0 = l4_rowq<0>(Lz), q1 = l4_rowq<1>(Lz), q2 = l4_rowq<2>(Lz);
   trsm16_step<0>(L, q0, i0, X);
   trsm16_step<1>(L, q1, i1, X);
   trsm16_step<2>(L, q2, i2, X);
-  const zd sx = scal(i3, X);
-  return sel(L.a == 3, sx, X);
+  return scal((L.a == 3) ? i3 : 1.0, X);
 }
 
 template <int K>
+// lka: entry (K, a) of the factor with its diagonal zeroed (zero for rows a >= K).
 __device__ __forceinline__ void trsm16h_step(const Lane4& L, const zd& lka, double ik, zd& X) {
-  const zd sx = scal(ik, X);
-  X = sel(L.a == K, sx, X);
+  X = scal((L.a == K) ? ik : 1.0, X);
   const zd xkb = l4_colk<K>(X);
-  const zd up = X - cj(lka) * xkb;
-  X = sel(L.a < K, up, X);
+  X = X - cj(lka) * xkb;
 }
 
 // X <- Lo^{-H} X (back substitution with the conjugate transpose)
 __device__ __forceinline__ zd trsm16h(const Lane4& L, zd Lo, const double (&id)[4], zd X) {
   const double i0 = id[0], i1 = id[1], i2 = id[2], i3 = id[3];
-  const zd t1 = L.at(Lo, 1, L.a), t2 = L.at(Lo, 2, L.a), t3 = L.at(Lo, 3, L.a);   // Lo[k][a]
+  const zd Lz = sel(L.a == L.b, zd{0.0, 0.0}, Lo);   // strictly lower part
+  const zd t1 = L.at(Lz, 1, L.a), t2 = L.at(Lz, 2, L.a), t3 = L.at(Lz, 3, L.a);   // Lo[k][a]
   trsm16h_step<3>(L, t3, i3, X);
   trsm16h_step<2>(L, t2, i2, X);
   trsm16h_step<1>(L, t1, i1, X);
-  const zd sx = scal(i0, X);
-  return sel(L.a == 0, sx, X);
+  return scal((L.a == 0) ? i0 : 1.0, X);
 }
 
 __device__ __forceinline__ void diag_recip(zd Lo, double (&id)[4]) {
