@@ -447,6 +447,10 @@ __device__ __forceinline__ void fast_body(const ammse_kparams_t& p) {
     __syncthreads();
   }
 
+  // The projection factor is applied lazily: the registers Gp and Xp and the
+  // copies Gq and X^{t-2} hold their matrices divided by these scales.
+  float sgp = 1.f, sgq = 1.f, sxp = 1.f, sxq = 1.f;
+
   // G = S H V (V in Bs) into Gp (previous Gp to Gq); own blocks into Fs
   auto product_G = [&]() {
     floatx4 P[S::GRB][S::UDB][3];
@@ -469,6 +473,8 @@ __device__ __forceinline__ void fast_body(const ammse_kparams_t& p) {
             Fs[g4 * 16 + r * 4 + ((u - u0) << lgN) + c] = g;
           }
         }
+    sgq = sgp;
+    sgp = 1.f;
   };
 
   // Per block user (i = row block of this wave, group lk): J-, Cholesky,
@@ -518,7 +524,8 @@ __device__ __forceinline__ void fast_body(const ammse_kparams_t& p) {
       rs_level<4>(s, li);
       rs_level<2>(s, li);
       rs_level<1>(s, li);
-      zd J = {(double)s[0].x, (double)s[0].y};
+      const double sg2 = (double)sgp * (double)sgp;      // G = sgp Gp
+      zd J = {sg2 * (double)s[0].x, sg2 * (double)s[0].y};
       if (L4.a == L4.b) J = {J.x + 1.0, 0.0};
       const float2 fo = Fs[(row0 >> 2) * 16 + li];
       zd F = {(double)fo.x, (double)fo.y};
@@ -786,6 +793,7 @@ __device__ __forceinline__ void fast_body(const ammse_kparams_t& p) {
 
     // Z' = D G^ - Y from the registers, into Bs (the gradient is 2 H^H S Z')
     const float om = p.extrapolate ? (float)fmax((t - 2.0) / (t + 1.0), 0.0) : 0.f;
+    const float cgp = (1.f + om) * sgp, cgq = om * sgq;
 #pragma unroll
     for (int i = 0; i < S::GRB; ++i) {
       const int row0 = 16 * (wave + 4 * i) + 4 * lk, g4 = row0 >> 2;
@@ -807,11 +815,14 @@ __device__ __forceinline__ void fast_body(const ammse_kparams_t& p) {
       }
 #pragma unroll
       for (int j = 0; j < S::UDB; ++j) {
+        // G^ = (1 + w) G^{t-1} - w G^{t-2}, kept over G^{t-2} (no longer needed)
         float2 gh[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          gh[r] = c2((1.f + om) * Gp[i][j][r].x - om * Gq[i][j][r].x,
-                     (1.f + om) * Gp[i][j][r].y - om * Gq[i][j][r].y);
+        for (int r = 0; r < 4; ++r) {
+          gh[r] = c2(cgp * Gp[i][j][r].x - cgq * Gq[i][j][r].x,
+                     cgp * Gp[i][j][r].y - cgq * Gq[i][j][r].y);
+          Gq[i][j][r] = gh[r];
+        }
         const int col = 16 * j + li;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -834,7 +845,7 @@ __device__ __forceinline__ void fast_body(const ammse_kparams_t& p) {
       break;
     }
 
-    // G~ = G^ - 2 gamma Q Z', X~ = X^ - 2 gamma Z', and the projection:
+    // G~ = G^ - 2 gamma Q Z' (G^ in Gq), X~ = X^ - 2 gamma Z', and the projection:
     // ||V~||^2 = c^2 nu + c Re<G^0, X~> + Re<X~, G~>  (c = c^, exact algebra
     // of V~ = c V^0 + H^H S X~ with G~ = c G^0 + Q X~)
     {
@@ -843,6 +854,7 @@ __device__ __forceinline__ void fast_body(const ammse_kparams_t& p) {
       const float g2 = (float)(2.0 * gamma);
       const double ch = (1.0 + om) * c1 - om * c2s;
       const float chf = (float)ch;
+      const float cxp = (1.f + om) * sxp, cxq = om * sxq;
       float acc = 0.f;
 #pragma unroll
       for (int i = 0; i < S::GRB; ++i)
@@ -853,35 +865,31 @@ __device__ __forceinline__ void fast_body(const ammse_kparams_t& p) {
             const int e = ((i * S::UDB + j) * 4 + r) * 256 + tid;
             const int row = 16 * (wave + 4 * i) + 4 * lk + r, col = 16 * j + li;
             const float2 pq = cplx_at(P[i][j], r);
-            const float2 gp = Gp[i][j][r], gq = Gq[i][j][r];
-            const float2 gt = c2((1.f + om) * gp.x - om * gq.x - g2 * pq.x,
-                                 (1.f + om) * gp.y - om * gq.y - g2 * pq.y);
+            const float2 gp = Gp[i][j][r], gh = Gq[i][j][r];
+            const float2 gt = c2(fmaf(-g2, pq.x, gh.x), fmaf(-g2, pq.y, gh.y));
             const float2 xp = Xp[i][j][r], xq = XqS[e], z = Bs[row * S::BLD + col];
-            const float2 xt = c2((1.f + om) * xp.x - om * xq.x - g2 * z.x,
-                                 (1.f + om) * xp.y - om * xq.y - g2 * z.y);
+            const float2 xt = c2(cxp * xp.x - cxq * xq.x - g2 * z.x,
+                                 cxp * xp.y - cxq * xq.y - g2 * z.y);
             const float2 g0 = G0S[e];
             acc = fmaf(xt.x, fmaf(chf, g0.x, gt.x), acc);   // Re<X~, c G^0 + G~>
             acc = fmaf(xt.y, fmaf(chf, g0.y, gt.y), acc);
-            XqS[e] = xp;             // X^{t-1} becomes X^{t-2}
-            Xp[i][j][r] = xt;        // temporarily X~
-            Gq[i][j][r] = gp;
-            Gp[i][j][r] = gt;        // temporarily G~
+            XqS[e] = xp;             // X^{t-1} becomes X^{t-2} (scale sxp)
+            Xp[i][j][r] = xt;        // X~ (the projection factor becomes its scale)
+            Gq[i][j][r] = gp;        // G^{t-1} becomes G^{t-2} (scale sgp)
+            Gp[i][j][r] = gt;        // G~
           }
       const double pw = ch * ch * nu + block_sum4((double)acc, red + 8);
       const double scd = (pw > Pc) ? sqrt(Pc / pw) : 1.0;
       const float sc = (float)scd;
       c2s = c1;
       c1 = scd * ch;
+      sxq = sxp;
+      sxp = sc;
+      sgq = sgp;
+      sgp = sc;
 #pragma unroll
       for (int i = 0; i < S::GRB; ++i) {
-#pragma unroll
-        for (int j = 0; j < S::UDB; ++j)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            Xp[i][j][r] = c2(sc * Xp[i][j][r].x, sc * Xp[i][j][r].y);
-            Gp[i][j][r] = c2(sc * Gp[i][j][r].x, sc * Gp[i][j][r].y);
-          }
-        // own entries (column block jo, N = d) into Fs for the receivers
+        // own entries (column block jo, N = d), scaled, into Fs for the receivers
         const int row0 = 16 * (wave + 4 * i) + 4 * lk, jo = wave + 4 * i;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -889,7 +897,7 @@ __device__ __forceinline__ void fast_body(const ammse_kparams_t& p) {
 #pragma unroll
           for (int j = 1; j < S::UDB; ++j) g = (j == jo) ? Gp[i][j][r] : g;
           const int e = own_entry(row0 + r, 16 * jo + li, lgN, lgd);
-          if (e >= 0) Fs[(row0 >> 2) * 16 + e] = g;
+          if (e >= 0) Fs[(row0 >> 2) * 16 + e] = c2(sc * g.x, sc * g.y);
         }
       }
     }
@@ -910,7 +918,7 @@ __device__ __forceinline__ void fast_body(const ammse_kparams_t& p) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = 16 * (wave + 4 * i) + 4 * lk + r, col = 16 * j + li;
-          const float s = (float)invsig[row];
+          const float s = (float)invsig[row] * sxp;   // X = sxp Xp
           Bs[row * S::BLD + col] = c2(s * Xp[i][j][r].x, s * Xp[i][j][r].y);
         }
     __syncthreads();
