@@ -274,7 +274,7 @@ ammse_status_t ammse_plan_workspace_size(ammse_plan_t plan, size_t* bytes) {
 ammse_status_t ammse_plan_info(ammse_plan_t plan, int32_t* kernel, size_t* lds_bytes) {
   if (!plan) return AMMSE_ERR_NULL;
   if (kernel) *kernel = plan->use_fast ? AMMSE_KERNEL_LDS_MFMA : AMMSE_KERNEL_GENERAL;
-  if (lds_bytes) *lds_bytes = plan->use_fast ? ammse_fast_lds_bytes() : ammse_general_lds_bytes(plan->opt.precision);
+  if (lds_bytes) *lds_bytes = plan->use_fast ? ammse_fast_lds_bytes() : ammse_general_lds_bytes(plan->opt.precision, plan->opt.algorithm);
   return AMMSE_OK;
 }
 

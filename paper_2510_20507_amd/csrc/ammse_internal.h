@@ -80,6 +80,7 @@ struct ammse_kparams_t {
 #define AMMSE_BLOCK 256
 #define AMMSE_TILE_SHAPES 3   // output tile shapes of the MFMA channel products
 #define AMMSE_MAX_LANCZOS 64
+#define AMMSE_LANCZOS_LDS_N 512   // Lanczos vectors of up to this order in LDS (general kernel)
 
 // Workspace layout of one instance (bytes), for complex storage of
 // `real_bytes` per component (8 for FP64, 4 for FP32).  Every sub-buffer
@@ -206,7 +207,7 @@ struct ammse_unroll_params_t {
 hipError_t ammse_launch_unroll(const ammse_kparams_t& p, const ammse_unroll_params_t& q,
                                bool backward, hipStream_t s);
 hipError_t ammse_launch_fp64(const ammse_kparams_t& p, hipStream_t s);
-size_t ammse_general_lds_bytes(int precision);
+size_t ammse_general_lds_bytes(int precision, int algorithm);
 // LDS-resident MFMA kernel (FP32): shapes it serves, its LDS use, launch.
 bool ammse_fast_eligible(int C, int U, int M, int N, int d);
 size_t ammse_fast_lds_bytes();

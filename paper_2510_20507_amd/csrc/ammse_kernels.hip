@@ -297,11 +297,11 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   // re-orthogonalisation).  apply(q, w) writes w = Op q (vectors in the
   // workspace).  FP64 forms ||w - alpha q - beta p|| explicitly, FP32 uses
   // beta^2 = ||w||^2 - alpha^2 - 2 beta_prev Re(p^H w) + beta_prev^2.
+  // The three vectors live in the dynamic LDS area when they fit (order <=
+  // AMMSE_LANCZOS_LDS_N), else in the workspace.
   auto lanczos_core = [&](int nl, auto&& apply) __attribute__((always_inline)) {
+   auto run = [&](zd* qv, zd* pv, zd* wv) __attribute__((always_inline)) {
     const int tid = phase_tid();
-    zd* qv = Lq;
-    zd* pv = Lq + nl;
-    zd* wv = Lq + 2 * nl;
     for (int i = tid; i < nl; i += AMMSE_BLOCK) {
       qv[i] = {1.0 + 0.5 * sin(0.731 * i + 0.25), 0.3 * cos(1.37 * i + 0.5)};
       pv[i] = {0.0, 0.0};
@@ -384,6 +384,12 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     }
     __syncthreads();
     return theta;
+   };
+    if (nl <= AMMSE_LANCZOS_LDS_N) {
+      zd* v = (zd*)dyn_lds;
+      return run(v, v + nl, v + 2 * nl);
+    }
+    return run(Lq, Lq + nl, Lq + 2 * nl);
   };
 
   // lambda_max(A_c), A_c = H_c^H S D S H_c, on the M-dimensional operator:
@@ -1219,15 +1225,23 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
 
 }  // namespace
 
-size_t ammse_general_lds_bytes(int precision) {
-  return precision == AMMSE_PREC_FP64 ? sizeof(Smem<double>) : sizeof(Smem<float>);
+// Static plus dynamic LDS of one workgroup, as launched below.
+size_t ammse_general_lds_bytes(int precision, int algorithm) {
+  const bool f64 = precision == AMMSE_PREC_FP64;
+  const size_t st = f64 ? sizeof(Smem<double>) : sizeof(Smem<float>);
+  const size_t dyn = (algorithm != AMMSE_ALGO_AMMMSE) ? sizeof(zd) * 64 * 64 * (f64 ? 1 : 2)
+                                                      : sizeof(zd) * 3 * AMMSE_LANCZOS_LDS_N;
+  return st + dyn;
 }
 
-// Exact-V-step algorithms get 64 KiB of dynamic LDS for a factor of order <= 64.
+// Exact-V-step algorithms get 64 KiB of dynamic LDS for a factor of order <= 64
+// (128 KiB with FP32 storage: factor and solution); A-MMMSE gets the area of
+// the Lanczos vectors.
 template <class R>
 hipError_t launch_general(const ammse_kparams_t& p0, hipStream_t s) {
   ammse_kparams_t p = p0;
-  size_t dyn = 0;
+  // A-MMMSE: the Lanczos vectors (order <= AMMSE_LANCZOS_LDS_N)
+  size_t dyn = sizeof(zd) * 3 * AMMSE_LANCZOS_LDS_N;
   if (p.algorithm != AMMSE_ALGO_AMMMSE) {
     static bool attr_set = false;
     // FP32: factor and solution block (128 KiB); FP64 (larger static tiles): factor only
