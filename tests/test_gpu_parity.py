@@ -457,3 +457,21 @@ def test_lds_kernel_option_variants(variant):
         np.testing.assert_allclose(tr[:m], ref["trace"][:m], rtol=1e-4, err_msg=str(i))
         if variant == "eps2":
             assert abs(int(res.iters[i]) - ref["iters"]) <= 2, (i, res.iters[i], ref["iters"])
+
+
+def test_lanczos_order_beyond_the_lds_vectors():
+    """Single cell with U N = 520 <= M = 528, FP64: the step size runs Lanczos
+    of order 520, above the 512 whose vectors the general kernel keeps in LDS,
+    so its vectors stay in the workspace; the WSR trajectory over 12 iterations
+    (the adaptive step sizes of both windows) matches the oracle to 1e-9."""
+    b = synth.pack([random_instance(321, M=528, cell_users=[130], N=4, d=1, P=100.0)])
+    opts = ammse.Options(precision=ammse.PREC_FP64, max_iters=12, path=ammse.PATH_GENERAL)
+    say("case: Lanczos order 520, FP64")
+    res = ammse.solve(b, opts, want_trace=True)
+    assert res.status[0] == 0
+    ref = oracle_runs(b, [0], iters=12)[0]
+    tr = res.trace[0]
+    if res.switch_iter[0] != ref["switch_iter"]:
+        tr = ammse.solve(b, opts, want_trace=True,
+                         force_switch=np.array([ref["switch_iter"]], np.int32)).trace[0]
+    np.testing.assert_allclose(tr, ref["trace"], rtol=1e-9)
