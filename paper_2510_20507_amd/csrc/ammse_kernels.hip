@@ -317,9 +317,12 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     const double rtol = exact_beta ? 1e-16 : 1e-10;
     const int first = exact_beta ? 8 : 12, every = exact_beta ? 8 : 4;
     double beta_prev = 0.0, tmax = 0.0, theta = 0.0;
+    // apply() writes w[i] from thread i mod AMMSE_BLOCK (or ends with a
+    // barrier), so each thread reads back only its own entries below; the
+    // barrier after the partial sums also ends every read of q, p and w
+    // before the update writes them.
     for (int j = 0; j < m; ++j) {
       apply(qv, wv);
-      __syncthreads();
       double s0 = 0.0, s1 = 0.0, s2 = 0.0;
       for (int i = tid; i < nl; i += AMMSE_BLOCK) {
         const zd w = wv[i], q = qv[i], pp = pv[i];
@@ -372,7 +375,6 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
         theta = th;
       }
       if (stop) break;
-      __syncthreads();
       const double ib = 1.0 / bb;
       for (int i = tid; i < nl; i += AMMSE_BLOCK) {
         const zd w = exact_beta ? wv[i] : wv[i] - scal(al, qv[i]) - scal(beta_prev, pv[i]);
@@ -438,6 +440,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
           if (part == 0) wv[i] = acc;
         }
       }
+      __syncthreads();   // w written by other threads than those that read it
     });
   };
 
