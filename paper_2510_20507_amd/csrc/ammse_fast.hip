@@ -15,6 +15,8 @@
 // iteration state stays in registers in the MFMA output layout:
 //   G^{t-1}, G^{t-2}  (the extrapolated G follows by linearity)
 //   X^{t-1}           (X^{t-2} and G^0 in LDS, per lane)
+// each held divided by a per-matrix scale, so that the projection factor is
+// applied to scalars rather than to every entry.
 // A lane holds 4 consecutive rows of one column.  Four consecutive rows form
 // a "block user": one user for N = 4, two for N = 2, four for N = 1; its
 // N x N and d x d algebra is done as one block-diagonal 4 x 4 problem.
