@@ -483,4 +483,142 @@ __device__ __forceinline__ double rel_change(double a, double b) {
 }
 
 
+// ---------------------------------------------------------------------------
+// Wave-level Lanczos helpers: sums, Sturm counts and the largest eigenvalue of
+// the tridiagonal matrix, inside one wave (no block barriers)
+// ---------------------------------------------------------------------------
+
+// Three wave sums at once (the same additions as wave_sum for each value,
+// interleaved level by level).
+__device__ __forceinline__ void wave_sum3_dpp(double& a, double& b, double& c) {
+  a += dpp64<0xB1>(a);
+  b += dpp64<0xB1>(b);
+  c += dpp64<0xB1>(c);
+  a += dpp64<0x4E>(a);
+  b += dpp64<0x4E>(b);
+  c += dpp64<0x4E>(c);
+  a += dpp64<0x124>(a);
+  b += dpp64<0x124>(b);
+  c += dpp64<0x124>(c);
+  a += dpp64<0x128>(a);
+  b += dpp64<0x128>(b);
+  c += dpp64<0x128>(c);
+  a = (read_lane(a, 0) + read_lane(a, 16)) + (read_lane(a, 32) + read_lane(a, 48));
+  b = (read_lane(b, 0) + read_lane(b, 16)) + (read_lane(b, 32) + read_lane(b, 48));
+  c = (read_lane(c, 0) + read_lane(c, 16)) + (read_lane(c, 32) + read_lane(c, 48));
+}
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix held in
+// LDS as 64 pairs tp[k] = (a_k, b_{k-1}^2) (entries of magnitude <= 1, b_{-1}
+// = 0; entries from m on padded with a = 8, b = 0, which adds eigenvalues
+// above every probe and leaves the count unchanged).  Sign changes of the
+// leading principal minors p_k(x) = det(T_k - x I), p_{-1} = 1, computed
+// without divisions (p_k = (a_k - x) p_{k-1} - b_{k-1}^2 p_{k-2}) in blocks
+// of eight steps (the eight pairs are loaded together; blocks past m read
+// padding) and rescaled by powers of two after each block to stay in range.
+__device__ __forceinline__ int sturm_count(const double2* tp, int m, double x) {
+  const double big = 0x1p400, small = 0x1p-400;
+  double pm = 0.0, pc = 1.0;
+  auto sgn = [](double v) { return (unsigned)((unsigned long long)__double_as_longlong(v) >> 63); };
+  unsigned cnt = 0;
+  for (int i = 0; i < m; i += 8) {                // i <= 56: every k below 64
+    double2 e[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) e[u] = tp[i + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double pn = fma(e[u].x - x, pc, -e[u].y * pm);
+      cnt += sgn(pn) ^ sgn(pc);
+      pm = pc;
+      pc = pn;
+    }
+    const double mag = fmax(fabs(pc), fabs(pm));
+    const double f = (mag > big) ? small : ((mag < small) ? big : 1.0);
+    pc *= f;
+    pm *= f;
+  }
+  return (int)cnt;
+}
+
+__device__ __forceinline__ double wave_min_dpp(double v) {
+  v = fmin(v, dpp64<0xB1>(v));
+  v = fmin(v, dpp64<0x4E>(v));
+  v = fmin(v, dpp64<0x124>(v));
+  v = fmin(v, dpp64<0x128>(v));
+  return fmin(fmin(read_lane(v, 0), read_lane(v, 16)), fmin(read_lane(v, 32), read_lane(v, 48)));
+}
+__device__ __forceinline__ double wave_max_dpp(double v) {
+  v = fmax(v, dpp64<0xB1>(v));
+  v = fmax(v, dpp64<0x4E>(v));
+  v = fmax(v, dpp64<0x124>(v));
+  v = fmax(v, dpp64<0x128>(v));
+  return fmax(fmax(read_lane(v, 0), read_lane(v, 16)), fmax(read_lane(v, 32), read_lane(v, 48)));
+}
+
+// Largest eigenvalue, to relative width 1e-10, of the m x m symmetric
+// tridiagonal matrix with diagonal ta and off-diagonal tb (lane i: entry i),
+// by multisection inside one wave (64 probes per round on Sturm counts of the
+// matrix scaled by 1/tmax, tmax >= every |a_i| + |b_i|; tp: 64 pairs of LDS
+// owned by the calling wave).  With a previous estimate th_prev > 0 (the
+// value for a leading block, which bounds the new one from below) the first
+// round places 16 probes ltol/16 apart above th_prev and 48 in geometric
+// progression up to the Gershgorin bound, so that a small and a large move of
+// the value are bracketed in one round; when the value lies within
+// th_prev (1 + ltol), *conv reports convergence.
+__device__ __forceinline__ double wave_tridiag_lmax(double ta, double tb, int m, double tmax,
+                                                    double th_prev, double ltol, double2* tp,
+                                                    bool* conv) {
+  const int lane = threadIdx.x & 63;
+  const double rtol = 1e-10;
+  const double is = 1.0 / tmax;
+  const double an = (lane < m) ? ta * is : 8.0;
+  const double bn = (lane < m - 1) ? tb * is : 0.0;
+  const double bup = __shfl_up(bn, 1, 64);      // by every lane (no divergent shuffle)
+  const double bl_ = (lane > 0) ? bup : 0.0;    // b_{lane-1}
+  tp[lane] = make_double2(an, bl_ * bl_);
+  *conv = false;
+  // Gershgorin interval
+  const double rad = fabs(bl_) + fabs(bn);
+  const double glo = wave_min_dpp((lane < m) ? an - rad : 1e300);
+  const double ghi = wave_max_dpp((lane < m) ? an + rad : -1e300);
+  double hi = ghi + fabs(ghi) * 1e-6 + 1e-300;
+  double lo = glo;
+  const double t0 = th_prev * is;
+  if (t0 > 0.0) {
+    // probe l: t0 (1 + f_l), f_l = ltol (l + 1) / 16 for l < 16, then
+    // ltol 2^(g (l - 15) / 48) with ltol 2^g = hi / t0 - 1 (g clamped to
+    // [2, 120]; probes above hi only confirm the bound)
+    const float g = fminf(fmaxf(__log2f((float)((hi / t0 - 1.0) / ltol)), 2.f), 120.f);
+    const double f = (lane < 16) ? ltol * (double)(lane + 1) * (1.0 / 16.0)
+                                 : ltol * (double)exp2f(g * (float)(lane - 15) * (1.0f / 48.0f));
+    const double x = t0 * (1.0 + f);
+    const unsigned long long mask = __ballot(sturm_count(tp, m, x) == m);
+    if (mask) {
+      const int t = __ffsll((long long)mask) - 1;
+      const double xt = read_lane(x, t);
+      if (t < 16) {
+        *conv = true;
+        return xt * tmax;
+      }
+      hi = xt;
+      lo = (t > 0) ? read_lane(x, t - 1) : t0;
+    } else {
+      lo = read_lane(x, 63);
+    }
+  }
+  const double fr = (double)(lane + 1) * (1.0 / 65.0);
+  for (int round = 0; round < 10; ++round) {
+    const double w = hi - lo;
+    if (!(w > fabs(hi) * rtol)) break;
+    const double x = lo + w * fr;
+    const unsigned long long mask = __ballot(sturm_count(tp, m, x) == m);
+    const int t = mask ? (__ffsll((long long)mask) - 1) : 64;
+    const double nhi = (t < 64) ? read_lane(x, t) : hi;
+    const double nlo = (t > 0) ? read_lane(x, t - 1) : lo;
+    lo = nlo;
+    hi = nhi;
+  }
+  return hi * tmax;
+}
+
 }  // namespace ammse_dev

@@ -81,6 +81,7 @@ struct ammse_kparams_t {
 #define AMMSE_TILE_SHAPES 3   // output tile shapes of the MFMA channel products
 #define AMMSE_MAX_LANCZOS 64
 #define AMMSE_LANCZOS_LDS_N 512   // Lanczos vectors of up to this order in LDS (general kernel)
+#define AMMSE_GRAM_WAVE_N 192     // Gram-matrix Lanczos of up to this order: one wave per BS
 
 // Workspace layout of one instance (bytes), for complex storage of
 // `real_bytes` per component (8 for FP64, 4 for FP32).  Every sub-buffer
@@ -135,7 +136,10 @@ __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int
   L.Lim = o; o += ammse_align256((w | qp | gp) * (size_t)U * 16 * zs);
   L.Cm = o;  o += ammse_align256((w | qp | gp) * (size_t)U * 16 * zs);
   L.Rg = o;  o += ammse_align256(gp * ud * (size_t)M * cs);
-  L.Kg = o;  o += ammse_align256(gp * ud * ud * cs);
+  // one K_c per BS when the per-BS iterations run one wave each (order <=
+  // AMMSE_GRAM_WAVE_N), else one K at a time
+  const size_t gk = (ud <= (size_t)AMMSE_GRAM_WAVE_N) ? (size_t)C : 1;
+  L.Kg = o;  o += ammse_align256(gp * gk * ud * ud * cs);
   const size_t rp = (qp && real_bytes == 4) ? 1 : 0;
   L.X1 = o;  o += ammse_align256(rp * un * ud * cs);
   L.X2 = o;  o += ammse_align256(rp * un * ud * cs);

@@ -55,6 +55,108 @@ struct Smem {
   int imin;
 };
 
+// Largest eigenvalue of the Hermitian float matrix K of order n <=
+// AMMSE_GRAM_WAVE_N (row-major; row r of K is read as column r, conj(K[c n + r])
+// = K(r, c), coalesced over r) by the three-term Lanczos iteration inside one
+// wave, with no block barriers: lane l holds entries l, l + 64, l + 128 of the
+// vectors, q is broadcast through qs (n + 16 float pairs of wave-private LDS,
+// zero past n) and the products run in float over 8 columns at a time,
+// combined in double.  tp: 64 pairs of wave-private LDS for the Sturm counts.
+// The start vector, the step limit and the stopping rule are those of the
+// block-wide iteration for float storage (beta from the norms; checks from step
+// 12 on every 4 steps and at the last; converged when the value moves by less
+// than 1e-8 relative).
+__device__ double wave_lanczos_lmax(const cx<float>* __restrict__ K, int n, int steps,
+                                    float2* qs, double2* tp) {
+  const int lane = threadIdx.x & 63;
+  const int nk = (n + 63) >> 6;                  // row blocks (1..3), uniform
+  zd x[3], pp[3];
+  double nn = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int i = lane + 64 * k;
+    x[k] = (i < n) ? zd{1.0 + 0.5 * sin(0.731 * i + 0.25), 0.3 * cos(1.37 * i + 0.5)}
+                   : zd{0.0, 0.0};
+    pp[k] = {0.0, 0.0};
+    nn += nrm2(x[k]);
+  }
+  const double i0 = 1.0 / sqrt(wave_sum(nn));
+#pragma unroll
+  for (int k = 0; k < 3; ++k) x[k] = scal(i0, x[k]);
+  if (lane < 16) qs[n + lane] = make_float2(0.f, 0.f);
+  const int m = max(1, min(steps, n));
+  const double ltol = 1e-8;
+  double ta = 0.0, tb = 0.0;                     // T entries, lane j holds entry j
+  double beta_prev = 0.0, tmax = 0.0, theta = 0.0;
+  for (int j = 0;; ++j) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (k < nk && lane + 64 * k < n) qs[lane + 64 * k] = make_float2((float)x[k].x, (float)x[k].y);
+    __builtin_amdgcn_wave_barrier();
+    zd w[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (k >= nk) continue;
+      const int r = min(lane + 64 * k, n - 1);     // rows past n: discarded below
+      for (int c0 = 0; c0 < n; c0 += 8) {
+        float2 qv[8];
+        cx<float> kv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          qv[u] = qs[c0 + u];
+          kv[u] = K[(long)min(c0 + u, n - 1) * n + r];
+        }
+        float ax = 0.f, ay = 0.f, bx = 0.f, by = 0.f;
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {          // K(r, c) q_c, K(r, c) = conj(kv)
+          ax = fmaf(kv[u].x, qv[u].x, fmaf(kv[u].y, qv[u].y, ax));
+          ay = fmaf(kv[u].x, qv[u].y, fmaf(-kv[u].y, qv[u].x, ay));
+          bx = fmaf(kv[u + 1].x, qv[u + 1].x, fmaf(kv[u + 1].y, qv[u + 1].y, bx));
+          by = fmaf(kv[u + 1].x, qv[u + 1].y, fmaf(-kv[u + 1].y, qv[u + 1].x, by));
+        }
+        w[k].x += (double)ax + (double)bx;
+        w[k].y += (double)ay + (double)by;
+      }
+    }
+    double al = 0.0, yy = 0.0, py = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (lane + 64 * k >= n) w[k] = {0.0, 0.0};
+      al += x[k].x * w[k].x + x[k].y * w[k].y;
+      yy += nrm2(w[k]);
+      py += pp[k].x * w[k].x + pp[k].y * w[k].y;
+    }
+    wave_sum3_dpp(al, yy, py);
+    const double bb = sqrt(fmax(yy - al * al - 2.0 * beta_prev * py + beta_prev * beta_prev, 0.0));
+    if (lane == j) {
+      ta = al;
+      tb = bb;
+    }
+    const int msz = j + 1;
+    tmax = fmax(tmax, fabs(al) + bb);
+    const bool breakdown = !(bb > 1e-13 * tmax);
+    bool stop = breakdown || msz == m;
+    if (breakdown || (msz >= 12 && (msz % 4) == 0) || msz == m) {
+      bool conv = false;
+      theta = (tmax > 0.0) ? wave_tridiag_lmax(ta, tb, msz, tmax, theta, ltol, tp, &conv) : 0.0;
+      stop = stop || conv;
+    }
+    if (stop) break;
+    const double ib = 1.0 / bb;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const zd xn = scal(ib, w[k] - scal(al, x[k]) - scal(beta_prev, pp[k]));
+      pp[k] = x[k];
+      x[k] = xn;
+    }
+    beta_prev = bb;
+  }
+  return theta;
+}
+static_assert((AMMSE_BLOCK / 64) * ((AMMSE_GRAM_WAVE_N + 16) * sizeof(float2) + 64 * sizeof(double2)) <=
+                  3 * AMMSE_LANCZOS_LDS_N * sizeof(zd),
+              "the per-wave Gram Lanczos buffers fit the A-MMMSE dynamic LDS");
+
 // ---------------------------------------------------------------------------
 // The fused kernel
 // ---------------------------------------------------------------------------
@@ -478,7 +580,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   // lambda_max(A_c) = lambda_max(K_c), K_c = R_c R_c^H ((U d) x (U d)).  R_c is
   // formed in one pass over H_{:,c}, K_c by one MFMA product (made exactly
   // Hermitian), and each Lanczos step reads K_c once instead of H_{:,c} twice.
-  auto lanczos_gram = [&](int c) {
+  auto gram_form = [&](int c, cx<R>* __restrict__ Kc) {
     const int tid = phase_tid();
     const cx<R>* __restrict__ Hc = H + (long)c * un * M;
     const int ud = U * d;
@@ -493,20 +595,24 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     }
     __syncthreads();
     channel_gemm<R, false, true>(ud, ud, M, Rg, M, Rg, M, sm.tiles, false, tile,
-                                 [&](int i, int j, cx<R> v) { Kg[(long)i * ud + j] = v; });
+                                 [&](int i, int j, cx<R> v) { Kc[(long)i * ud + j] = v; });
     __syncthreads();
     for (int e = tid; e < ud * ud; e += AMMSE_BLOCK) {   // exactly Hermitian
       const int i = e / ud, j = e - i * ud;
       if (i < j) {
-        const cx<R> x = Kg[e], y = Kg[(long)j * ud + i];
+        const cx<R> x = Kc[e], y = Kc[(long)j * ud + i];
         const cx<R> mm = {(R)0.5 * (x.x + y.x), (R)0.5 * (x.y - y.y)};
-        Kg[e] = mm;
-        Kg[(long)j * ud + i] = {mm.x, -mm.y};
+        Kc[e] = mm;
+        Kc[(long)j * ud + i] = {mm.x, -mm.y};
       } else if (i == j) {
-        Kg[e].y = (R)0;
+        Kc[e].y = (R)0;
       }
     }
     __syncthreads();
+  };
+  auto lanczos_gram = [&]() {   // on the K formed last (at Kg)
+    const int tid = phase_tid();
+    const int ud = U * d;
     // w = K q with K Hermitian (column r read for row r, coalesced over r):
     // nparts threads per row, each over every nparts-th column, partial sums
     // combined through LDS (the product tiles, free here)
@@ -968,13 +1074,32 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     const bool adaptive = t <= p.T_c || (p.rearm && switch_iter >= 1 && t >= switch_iter &&
                                          t < switch_iter + p.T_c);
     if (adaptive) {
+      // Gram path with order <= AMMSE_GRAM_WAVE_N: every K_c first (the whole
+      // block on each), then one wave per BS runs its Lanczos iteration
+      const bool gw = gpath && U * d <= AMMSE_GRAM_WAVE_N;
       for (int c = 0; c < C; ++c) {
+        if (sm.cu[c] != 0 && gpath) gram_form(c, gw ? Kg + (long)c * U * d * U * d : Kg);
+        if (gw) continue;
         const double lm = (sm.cu[c] == 0) ? 0.0
                           : qpath ? lanczos_q()
-                          : gpath ? lanczos_gram(c)
+                          : gpath ? lanczos_gram()
                                   : lanczos_lmax(c);
         if (tid == 0) sm.gamma[c] = (lm > 0.0) ? 1.0 / (2.0 * lm) : 0.0;
         __syncthreads();
+      }
+      if constexpr (sizeof(R) == 4) {
+        if (gw) {
+          const int lane = tid & 63, wave = tid >> 6;
+          float2* qs = (float2*)dyn_lds + wave * (AMMSE_GRAM_WAVE_N + 16);
+          double2* tp = (double2*)((float2*)dyn_lds + 4 * (AMMSE_GRAM_WAVE_N + 16)) + wave * 64;
+          for (int c = wave; c < C; c += AMMSE_BLOCK / 64) {
+            const int n = U * d;
+            const double lm = (sm.cu[c] == 0) ? 0.0
+                              : wave_lanczos_lmax(Kg + (long)c * n * n, n, p.lanczos_steps, qs, tp);
+            if (lane == 0) sm.gamma[c] = (lm > 0.0) ? 1.0 / (2.0 * lm) : 0.0;
+          }
+          __syncthreads();
+        }
       }
     } else if (p.gamma_c > 0.0) {
       if (tid < C) sm.gamma[tid] = p.gamma_c;

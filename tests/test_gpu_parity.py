@@ -475,3 +475,21 @@ def test_lanczos_order_beyond_the_lds_vectors():
         tr = ammse.solve(b, opts, want_trace=True,
                          force_switch=np.array([ref["switch_iter"]], np.int32)).trace[0]
     np.testing.assert_allclose(tr, ref["trace"], rtol=1e-9)
+
+
+@pytest.mark.parametrize("cells,M", [([10, 12, 8], 64), ([50, 50], 128)])
+def test_fp32_gram_step_size_orders(cells, M):
+    """FP32 multi-cell instances whose step size comes from the Lanczos
+    iteration on the stream-space Gram matrices K_c = R_c R_c^H: order
+    U d = 60 runs one wave per BS, order 200 (above the 192 the per-wave
+    iteration holds) the block-wide one; the WSR trajectory over 30
+    iterations matches the oracle's to the FP32 bound."""
+    b = synth.pack([random_instance(700 + M, M=M, cell_users=cells, N=2, d=2, P=10.0)])
+    ud = un = 2 * sum(cells)
+    assert ud * ud < 2 * un * M   # the Gram form is the cheaper step-size operator
+    opts = ammse.Options(precision=ammse.PREC_FP32, max_iters=30, path=ammse.PATH_GENERAL)
+    say("case: gram step size", cells, M, "order", ud)
+    res = ammse.solve(b, opts, want_trace=True)
+    assert res.status[0] == 0
+    refs = oracle_runs(b, [0], iters=30)
+    compare_traces(b, res, refs, [0], opts, 1e-4, 30)
