@@ -62,10 +62,11 @@ struct Smem {
 // vectors, q is broadcast through qs (n + 16 float pairs of wave-private LDS,
 // zero past n) and the products run in float over 8 columns at a time,
 // combined in double.  tp: 64 pairs of wave-private LDS for the Sturm counts.
-// The start vector, the step limit and the stopping rule are those of the
-// block-wide iteration for float storage (beta from the norms; checks from step
-// 12 on every 4 steps and at the last; converged when the value moves by less
-// than 1e-8 relative).
+// The start vector, the step limit and the convergence test are those of the
+// block-wide iteration for float storage (beta from the norms; converged when
+// the value moves by less than 1e-8 relative); a check here costs a fraction
+// of a step (which reads K from memory), so checks run from step 12 on every
+// 2 steps (block-wide: every 4) and at the last.
 __device__ double wave_lanczos_lmax(const cx<float>* __restrict__ K, int n, int steps,
                                     float2* qs, double2* tp) {
   const int lane = threadIdx.x & 63;
@@ -136,7 +137,7 @@ __device__ double wave_lanczos_lmax(const cx<float>* __restrict__ K, int n, int 
     tmax = fmax(tmax, fabs(al) + bb);
     const bool breakdown = !(bb > 1e-13 * tmax);
     bool stop = breakdown || msz == m;
-    if (breakdown || (msz >= 12 && (msz % 4) == 0) || msz == m) {
+    if (breakdown || (msz >= 12 && (msz % 2) == 0) || msz == m) {
       bool conv = false;
       theta = (tmax > 0.0) ? wave_tridiag_lmax(ta, tb, msz, tmax, theta, ltol, tp, &conv) : 0.0;
       stop = stop || conv;
