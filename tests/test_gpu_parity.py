@@ -477,15 +477,17 @@ def test_lanczos_order_beyond_the_lds_vectors():
     np.testing.assert_allclose(tr, ref["trace"], rtol=1e-9)
 
 
-@pytest.mark.parametrize("cells,M", [([10, 12, 8], 64), ([50, 50], 128)])
-def test_fp32_gram_step_size_orders(cells, M):
+@pytest.mark.parametrize("cells,M,N,d", [([10, 12, 8], 64, 2, 2), ([30, 40, 20], 64, 1, 1),
+                                         ([48, 48], 128, 2, 2), ([50, 50], 128, 2, 2)])
+def test_fp32_gram_step_size_orders(cells, M, N, d):
     """FP32 multi-cell instances whose step size comes from the Lanczos
-    iteration on the stream-space Gram matrices K_c = R_c R_c^H: order
-    U d = 60 runs one wave per BS, order 200 (above the 192 the per-wave
-    iteration holds) the block-wide one; the WSR trajectory over 30
-    iterations matches the oracle's to the FP32 bound."""
-    b = synth.pack([random_instance(700 + M, M=M, cell_users=cells, N=2, d=2, P=10.0)])
-    ud = un = 2 * sum(cells)
+    iteration on the stream-space Gram matrices K_c = R_c R_c^H: orders
+    U d = 60, 90 (a ragged second row block, not a multiple of the 8-column
+    chunks) and 192 (three full row blocks) run one wave per BS, order 200
+    (above the 192 the per-wave iteration holds) the block-wide one; the WSR
+    trajectory over 30 iterations matches the oracle's to the FP32 bound."""
+    b = synth.pack([random_instance(700 + M + 7 * N, M=M, cell_users=cells, N=N, d=d, P=10.0)])
+    ud, un = d * sum(cells), N * sum(cells)
     assert ud * ud < 2 * un * M   # the Gram form is the cheaper step-size operator
     opts = ammse.Options(precision=ammse.PREC_FP32, max_iters=30, path=ammse.PATH_GENERAL)
     say("case: gram step size", cells, M, "order", ud)
