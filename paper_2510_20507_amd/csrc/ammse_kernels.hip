@@ -95,29 +95,45 @@ __device__ double wave_lanczos_lmax(const cx<float>* __restrict__ K, int n, int 
       if (k < nk && lane + 64 * k < n) qs[lane + 64 * k] = make_float2((float)x[k].x, (float)x[k].y);
     __builtin_amdgcn_wave_barrier();
     zd w[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      if (k >= nk) continue;
-      const int r = min(lane + 64 * k, n - 1);     // rows past n: discarded below
+    // w = K x over chunks of 8 columns; the chunk's loads for NK row blocks from
+    // block K0 on are issued together (rows past n read row n - 1 and are
+    // discarded below)
+    auto matvec = [&](auto k0c, auto nkc) __attribute__((always_inline)) {
+      constexpr int K0 = decltype(k0c)::value, NK = decltype(nkc)::value;
       for (int c0 = 0; c0 < n; c0 += 8) {
         float2 qv[8];
-        cx<float> kv[8];
+        cx<float> kv[NK][8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          qv[u] = qs[c0 + u];
-          kv[u] = K[(long)min(c0 + u, n - 1) * n + r];
-        }
-        float ax = 0.f, ay = 0.f, bx = 0.f, by = 0.f;
+        for (int k = 0; k < NK; ++k) {
+          const int r = min(lane + 64 * (K0 + k), n - 1);
 #pragma unroll
-        for (int u = 0; u < 8; u += 2) {          // K(r, c) q_c, K(r, c) = conj(kv)
-          ax = fmaf(kv[u].x, qv[u].x, fmaf(kv[u].y, qv[u].y, ax));
-          ay = fmaf(kv[u].x, qv[u].y, fmaf(-kv[u].y, qv[u].x, ay));
-          bx = fmaf(kv[u + 1].x, qv[u + 1].x, fmaf(kv[u + 1].y, qv[u + 1].y, bx));
-          by = fmaf(kv[u + 1].x, qv[u + 1].y, fmaf(-kv[u + 1].y, qv[u + 1].x, by));
+          for (int u = 0; u < 8; ++u) kv[k][u] = K[(long)min(c0 + u, n - 1) * n + r];
         }
-        w[k].x += (double)ax + (double)bx;
-        w[k].y += (double)ay + (double)by;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) qv[u] = qs[c0 + u];
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+          float ax = 0.f, ay = 0.f, bx = 0.f, by = 0.f;
+#pragma unroll
+          for (int u = 0; u < 8; u += 2) {        // K(r, c) q_c, K(r, c) = conj(kv)
+            ax = fmaf(kv[k][u].x, qv[u].x, fmaf(kv[k][u].y, qv[u].y, ax));
+            ay = fmaf(kv[k][u].x, qv[u].y, fmaf(-kv[k][u].y, qv[u].x, ay));
+            bx = fmaf(kv[k][u + 1].x, qv[u + 1].x, fmaf(kv[k][u + 1].y, qv[u + 1].y, bx));
+            by = fmaf(kv[k][u + 1].x, qv[u + 1].y, fmaf(-kv[k][u + 1].y, qv[u + 1].x, by));
+          }
+          w[K0 + k].x += (double)ax + (double)bx;
+          w[K0 + k].y += (double)ay + (double)by;
+        }
       }
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    if (nk == 1) {
+      matvec(I0{}, I1{});
+    } else {                                       // two row blocks at a time at most
+      matvec(I0{}, I2{});
+      if (nk == 3) matvec(I2{}, I1{});
     }
     double al = 0.0, yy = 0.0, py = 0.0;
 #pragma unroll
