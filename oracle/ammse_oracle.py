@@ -27,10 +27,17 @@ same way on the GPU; the list is kept with the design notes):
 * R5  The fixed step gamma_c is never given numerically.  The adaptive step
       is computed in the first T_c iterations and again in the first T_c
       iterations of stage II (the weighted problem has a larger Lipschitz
-      constant than the unweighted one, and a step frozen in stage I makes
-      stage II diverge); afterwards gamma_c is the last adaptive value of each
-      BS unless a positive gamma_c is supplied.  ``rearm_at_switch=False``
-      gives the literal single window t <= T_c.
+      constant than the unweighted one).  In stage I the later iterations
+      keep the last adaptive value of each BS.  In stage II the later
+      iterations use gamma_c = 1 / Lhat_c with Lhat_c = 2 lambda_max(sum_u
+      (alpha_u / sigma2_u) H_{u,c}^H H_{u,c}), an upper bound of the gradient's
+      Lipschitz constant ||2 A_c||_2 at every iterate of either stage (Section
+      VI, proof of Lemma 3: lambda_max(W U^H U) <= 1 / sigma2, applied to the
+      stacked channel of BS c instead of term by term), so every stage-II step
+      meets the descent condition of Theorem 1 (step_rule = "bound").
+      step_rule = "frozen" keeps the last adaptive value in stage II as well;
+      a positive gamma_c overrides both; rearm_at_switch = False gives the
+      single window t <= T_c.
 * R6  The step size is one scalar per BS (its expression depends only on the
       BS index).
 * R8  The extrapolation counter t is not restarted at the stage switch.
@@ -54,8 +61,8 @@ LN2 = math.log(2.0)
 __all__ = [
     "Problem", "from_instance", "split_v", "join_v", "cross_terms", "user_rates", "wsr_bits",
     "mmse_receivers", "mse_matrices", "mse_at_mmse", "objective_f", "transmit_hessians",
-    "gradient_v", "step_sizes", "project_spc", "omega_schedule", "rel_change", "ammmse",
-    "wmmse", "wmmse_precoder", "mmmse", "kkt_residual", "kappa", "solve_batch",
+    "gradient_v", "step_sizes", "step_bound", "project_spc", "omega_schedule", "rel_change",
+    "ammmse", "wmmse", "wmmse_precoder", "mmmse", "kkt_residual", "kappa", "solve_batch",
 ]
 
 
@@ -244,6 +251,23 @@ def step_sizes(A: np.ndarray) -> np.ndarray:
     return out
 
 
+def step_bound(prob: Problem) -> np.ndarray:
+    """Lhat_c = 2 lambda_max(sum_u (alpha_u / sigma2_u) H_{u,c}^H H_{u,c}) per BS,
+    the sum running over every user (all cells).  With U_u W_u U_u^H <= I /
+    sigma2_u (Section VI, proof of Lemma 3, for W = E^{-1}; for W = I from
+    sigma2 U^H U <= E <= I at the MMSE receiver), A_c <= sum_u (alpha_u /
+    sigma2_u) H_{u,c}^H H_{u,c} in the Loewner order, so ||2 A_c||_2 <= Lhat_c
+    for every iterate; Lhat_c <= 2 alpha_max U kappa / sigma2_min (Lemma 3)."""
+    out = np.zeros(prob.C)
+    for c in range(prob.C):
+        B = np.zeros((prob.M, prob.M), np.complex128)
+        for u in range(prob.U):
+            Huc = prob.Hs[u, c]
+            B += (prob.alpha[u] / prob.sigma2[u]) * (Huc.conj().T @ Huc)
+        out[c] = 2.0 * np.linalg.eigvalsh(0.5 * (B + B.conj().T)).max()
+    return out
+
+
 def project_spc(prob: Problem, Vu: np.ndarray) -> np.ndarray:
     """Projection onto each BS's sum-power ball (projection equation, Section V-A):
     unchanged if sum_{u in c} ||V_u||_F^2 <= P_c, else scaled by sqrt(P_c / power)."""
@@ -277,7 +301,7 @@ def _inv_hermitian(E: np.ndarray) -> np.ndarray:
 def ammmse(prob: Problem, V0u: np.ndarray, iters: int, eps1: float = 0.1, eps2: float = 0.0,
            Tc: int = 3, gamma_c: Optional[float] = None, extrapolate: bool = True,
            warm_start: bool = True, force_switch_iter: Optional[int] = None,
-           rearm_at_switch: bool = True, perturb=None) -> dict:
+           rearm_at_switch: bool = True, step_rule: str = "bound", perturb=None) -> dict:
     """A-MMMSE (Algorithm 3), FP64, one instance.
 
     Per iteration t = 1..iters:
@@ -288,7 +312,9 @@ def ammmse(prob: Problem, V0u: np.ndarray, iters: int, eps1: float = 0.1, eps2: 
          V^{t-1} and V^{t-2} is <= eps1 (R3, R4);
       4. W^t = (I - U^H H V^{t-1})^{-1} in stage II, I in stage I;
       5. for t <= Tc (and the first Tc stage-II iterations, R5),
-         gamma_c = 1/||2 A_c||_2 per BS; afterwards fixed (R5, R6);
+         gamma_c = 1/||2 A_c||_2 per BS; afterwards the last adaptive value
+         in stage I and 1 / Lhat_c (``step_bound``) in stage II, or the last
+         adaptive value in both stages with step_rule="frozen" (R5, R6);
       6. V^t = Pi_P(V^ - gamma grad f(U^t, W^t, V^)) (R2).
     Returns the final precoders, the WSR trace WSR(V^0..V^T) in bits, the
     iteration of the stage switch (-1 if none) and the number of iterations run.
@@ -299,6 +325,9 @@ def ammmse(prob: Problem, V0u: np.ndarray, iters: int, eps1: float = 0.1, eps2: 
     strongly a trajectory amplifies rounding-sized perturbations."""
     if Tc <= 0 and not (gamma_c is not None and gamma_c > 0):
         raise ValueError("Tc = 0 needs a positive fixed step gamma_c")
+    if step_rule not in ("bound", "frozen"):
+        raise ValueError("step_rule must be 'bound' or 'frozen'")
+    bound = None
     V_prev = V0u.copy()
     V_prev2 = V0u.copy()
     trace = [wsr_bits(prob, V_prev)]
@@ -338,6 +367,10 @@ def ammmse(prob: Problem, V0u: np.ndarray, iters: int, eps1: float = 0.1, eps2: 
             gamma = step_sizes(A)
         elif gamma_c is not None and gamma_c > 0:
             gamma = np.full(prob.C, float(gamma_c))
+        elif stage2 and step_rule == "bound":
+            if bound is None:
+                bound = step_bound(prob)
+            gamma = np.where(bound > 0, 1.0 / np.where(bound > 0, bound, 1.0), 0.0)
         gammas.append(gamma.copy())
         grad = gradient_v(prob, Uu, Wu, Vhat, A)
         V_new = project_spc(prob, Vhat - gamma[prob.cell][:, None, None] * grad)

@@ -104,6 +104,29 @@ def unrolled_wsr(H, sigma2, alpha, P: float, V0, gammas, switch_iter: int,
     return wsr_bits(H, sigma2, alpha, Vp), Vp, trace
 
 
+def switch_iter(H: np.ndarray, sigma2: Sequence[float], alpha: Sequence[float], P: float,
+                V0: np.ndarray, gammas: Sequence[float], eps1: float = 0.1,
+                extrapolate: bool = True) -> int:
+    """The stage-switch iteration the eps1 rule of Algorithm 3 picks for the
+    unrolled solver with these step sizes: the first t >= 2 whose relative WSR
+    change between V^{t-1} and V^{t-2} is <= eps1 (T + 1 if none).  Before the
+    switch the iterates equal those of a run that stays in stage I, so the
+    rule is applied to the trace of that run."""
+    T = len(gammas)
+    with torch.no_grad():
+        _, _, trace = unrolled_wsr(torch.tensor(H, dtype=torch.complex128),
+                                   torch.tensor(np.asarray(sigma2, float)),
+                                   torch.tensor(np.asarray(alpha, float)), float(P),
+                                   torch.tensor(V0, dtype=torch.complex128),
+                                   torch.tensor(np.asarray(gammas, float)), T + 1, extrapolate)
+    for t in range(2, T + 1):
+        a, b = trace[t - 1], trace[t - 2]
+        rel = abs(a - b) / b if b > 0 else (0.0 if a == b else float("inf"))
+        if rel <= eps1:
+            return t
+    return T + 1
+
+
 def value_and_grad(H: np.ndarray, sigma2: Sequence[float], alpha: Sequence[float], P: float,
                    V0: np.ndarray, gammas: Sequence[float], switch_iter: int,
                    extrapolate: bool = True):

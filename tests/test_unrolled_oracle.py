@@ -77,3 +77,15 @@ def test_projection_branch_is_active_in_the_pins():
     _, _, _, VT, _ = UR.value_and_grad(H, prob.sigma2, prob.alpha, prob.P[0], V0,
                                        np.linspace(0.03, 0.06, 8), 3)
     assert np.sum(np.abs(VT) ** 2) == pytest.approx(prob.P[0], rel=1e-12)
+
+
+def test_switch_iteration_matches_the_numpy_oracle():
+    """The eps1 rule on the unrolled solver with a fixed step picks the same
+    switch iteration as Algorithm 3 in the NumPy oracle with that fixed step."""
+    prob, H, V0 = _inst(seed=37)
+    T, g = 20, 0.05
+    ref = O.ammmse(prob, V0, T, Tc=0, gamma_c=g)
+    s = UR.switch_iter(H, prob.sigma2, prob.alpha, prob.P[0], V0, [g] * T)
+    assert 2 <= ref["switch_iter"] <= T
+    assert s == ref["switch_iter"]
+    assert UR.switch_iter(H, prob.sigma2, prob.alpha, prob.P[0], V0, [g] * T, eps1=0.0) == T + 1
