@@ -14,7 +14,9 @@
  * factorisations), W = I during the warm-start stage (Section V-B) until the
  * relative WSR change drops to eps1, then one projected-gradient step for V
  * (Section V-A: gradient, projection onto the sum-power ball, adaptive step
- * for the first T_c iterations, extrapolation weight omega^t).
+ * for the first T_c iterations, extrapolation weight omega^t).  The fixed
+ * step after the adaptive window is not given by the paper; by default the
+ * second stage uses the bound of Section VI (ammse_options_t.step_rule).
  *
  * Conventions for every entry point:
  *   - All data buffers are caller-owned DEVICE memory unless stated; the
@@ -40,7 +42,7 @@
 extern "C" {
 #endif
 
-#define AMMSE_VERSION 1
+#define AMMSE_VERSION 2
 
 /* Return codes. */
 typedef int32_t ammse_status_t;
@@ -126,6 +128,21 @@ typedef struct ammse_instance_t {
                                 warm_start = 0 or force_switch_iter as for
                                 Algorithm 3; otherwise as AMMSE_ALGO_WMMSE. */
 
+/* Fixed step after the adaptive window (ammse_options_t.step_rule); the
+ * paper leaves gamma_c as an input of Algorithm 3 without a value.
+ *   AMMSE_STEP_BOUND: stage I keeps the last adaptive step of each BS; stage
+ *     II (after its own re-armed window, see rearm_at_switch) uses
+ *     gamma_c = 1 / Lhat_c, Lhat_c = 2 lambda_max(sum_u (alpha_u / sigma2_u)
+ *     H_{u,c}^H H_{u,c}) over all users u.  Section VI (proof of Lemma 3)
+ *     gives lambda_max(W_u U_u^H U_u) <= 1 / sigma2_u, so Lhat_c bounds the
+ *     Lipschitz constant ||2 A_c||_2 of the V-gradient at every iterate and
+ *     every stage-II step meets the descent condition of Theorem 1.  Lhat_c
+ *     is computed once per solve (Lanczos), when the first such step needs it.
+ *   AMMSE_STEP_FROZEN: the last adaptive step of each BS in both stages.
+ * A positive gamma_c overrides either rule. */
+#define AMMSE_STEP_BOUND 0
+#define AMMSE_STEP_FROZEN 1
+
 /* Solver options (Algorithm 3 inputs). */
 typedef struct ammse_options_t {
   int32_t precision;         /* AMMSE_PREC_* */
@@ -149,10 +166,11 @@ typedef struct ammse_options_t {
                                 (shape 0 until ammse_autotune picks one per shape
                                 class); 1, 2, 3 = force shape 0, 1, 2 (64 x 64,
                                 128 x 16, 64 x 32) for every instance */
+  int32_t step_rule;         /* AMMSE_STEP_BOUND (default) or AMMSE_STEP_FROZEN */
   double eps1;               /* stage-switch tolerance (paper: 0.1) */
   double eps2;               /* stop tolerance (0: run exactly max_iters) */
-  double gamma_c;            /* > 0: fixed step after the adaptive window;
-                                <= 0: keep the last adaptive step of each BS */
+  double gamma_c;            /* > 0: fixed step after the adaptive windows (both
+                                stages); <= 0: the step rule above */
 } ammse_options_t;
 
 /* Opaque plan: validated copy of the instance table on the device, the
@@ -169,8 +187,8 @@ int32_t ammse_version(void);
 const char* ammse_status_string(ammse_status_t s);
 
 /* Fill *opt with the paper's defaults: FP32, T = 100, T_c = 3, warm start,
- * extrapolation, re-armed step, eps1 = 0.1, eps2 = 0, gamma_c = 0 (keep),
- * refine_iters = 10, algorithm = AMMSE_ALGO_AMMMSE. */
+ * extrapolation, re-armed step, step_rule = AMMSE_STEP_BOUND, eps1 = 0.1,
+ * eps2 = 0, gamma_c = 0, refine_iters = 10, algorithm = AMMSE_ALGO_AMMMSE. */
 void ammse_default_options(ammse_options_t* opt);
 
 /*

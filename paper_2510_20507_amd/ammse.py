@@ -28,6 +28,8 @@ PATH_GENERAL = 1
 ALGO_AMMMSE = 0
 ALGO_WMMSE = 1
 ALGO_MMMSE = 2
+STEP_BOUND = 0
+STEP_FROZEN = 1
 INST_NONFINITE = 1
 INST_CHOLESKY = 2
 INST_ZERO_POWER = 4
@@ -54,7 +56,8 @@ class AmmseOptions(ctypes.Structure):
                 ("force_switch_iter", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32),
                 ("path", ctypes.c_int32), ("refine_iters", ctypes.c_int32),
                 ("algorithm", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("eps1", ctypes.c_double), ("eps2", ctypes.c_double), ("gamma_c", ctypes.c_double)]
+                ("step_rule", ctypes.c_int32), ("eps1", ctypes.c_double),
+                ("eps2", ctypes.c_double), ("gamma_c", ctypes.c_double)]
 
 
 class AmmseError(RuntimeError):
@@ -142,6 +145,7 @@ class Options:
     refine_iters: int = 10
     algorithm: int = ALGO_AMMMSE
     tile: int = 0            # 0: plan's (autotuned) tile shapes; v + 1: force shape v
+    step_rule: int = 0       # STEP_BOUND (stage-II step 1/Lhat) or STEP_FROZEN
     eps1: float = 0.1
     eps2: float = 0.0
     gamma_c: float = 0.0
@@ -341,8 +345,9 @@ class Result:
 
 
 def solve(batch, options: Optional[Options] = None, device: int = 0, want_trace: bool = False,
-          force_switch: Optional[np.ndarray] = None) -> Result:
-    """Convenience wrapper: upload a synth.Batch, run ammse_solve, download."""
+          force_switch: Optional[np.ndarray] = None, autotune: bool = False) -> Result:
+    """Convenience wrapper: upload a synth.Batch, run ammse_solve, download
+    (with ``autotune``, ammse_autotune picks the plan's tile shapes first)."""
     import torch
     options = options or Options()
     db = to_device(batch, options.precision, device)
@@ -358,6 +363,8 @@ def solve(batch, options: Optional[Options] = None, device: int = 0, want_trace:
              if want_trace else None)
     fs = (torch.from_numpy(np.ascontiguousarray(force_switch, np.int32)).to(dev)
           if force_switch is not None else None)
+    if autotune:
+        plan.autotune(db.H, db.sigma2, db.alpha, db.P, V)
     plan.solve(db.H, db.sigma2, db.alpha, db.P, V, wsr, iters, sw, st, trace, fs)
     torch.cuda.synchronize(device)
     out = Result(V=V.cpu().numpy().astype(np.complex128), wsr=wsr.cpu().numpy(),

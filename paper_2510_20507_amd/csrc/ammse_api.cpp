@@ -49,6 +49,7 @@ ammse_status_t check_options(const ammse_options_t& o) {
   if (o.path != AMMSE_PATH_AUTO && o.path != AMMSE_PATH_GENERAL) return AMMSE_ERR_OPTION;
   if (o.refine_iters < 0) return AMMSE_ERR_OPTION;
   if (o.tile < 0 || o.tile > 3) return AMMSE_ERR_OPTION;
+  if (o.step_rule != AMMSE_STEP_BOUND && o.step_rule != AMMSE_STEP_FROZEN) return AMMSE_ERR_OPTION;
   if (o.algorithm != AMMSE_ALGO_AMMMSE && o.algorithm != AMMSE_ALGO_WMMSE &&
       o.algorithm != AMMSE_ALGO_MMMSE)
     return AMMSE_ERR_OPTION;
@@ -95,6 +96,7 @@ void ammse_default_options(ammse_options_t* opt) {
   opt->refine_iters = 10;
   opt->algorithm = AMMSE_ALGO_AMMMSE;
   opt->tile = 0;
+  opt->step_rule = AMMSE_STEP_BOUND;
   opt->eps1 = 0.1;
   opt->eps2 = 0.0;
   opt->gamma_c = 0.0;
@@ -316,6 +318,7 @@ static void fill_common(ammse_plan_t plan, ammse_kparams_t& k) {
   k.algorithm = o.algorithm;
   k.bf16_copies = o.precision == AMMSE_PREC_BF16;
   k.tile_force = o.tile;
+  k.step_rule = o.step_rule;
 }
 
 ammse_status_t ammse_solve(ammse_plan_t plan, const void* H, const double* sigma2,

@@ -30,7 +30,9 @@
 // Per iteration t (Algorithm 3):
 //   J- from registers (reduce-scatter over the 16 lanes of a row group);
 //   Cholesky, U, W per block user; WSR(V^{t-1}) when a test needs it; stage
-//   latch; adaptive step by Lanczos on K = C^H Q C (formed in LDS);
+//   latch; adaptive step by Lanczos on K = C^H Q C (formed in LDS), after the
+//   adaptive windows of stage II 1/Lhat from the same Lanczos with
+//   C = diag(sqrt(alpha)) (once per solve);
 //   Z' = D G^ - Y -> LDS;  P = Q Z' (MFMA);  in the epilogue
 //   G~ = G^ - 2 gamma P, X~ = X^ - 2 gamma Z', the projection norm, and the
 //   projection factor applied to G~, X~ and c.
@@ -617,6 +619,8 @@ __device__ __forceinline__ void fast_body(const ammse_kparams_t& p) {
   int switch_iter = stage2 ? 1 : -1;
   bool prev_step_stage2 = false;
   double wsr_prev = 0.0, wsr_prev2 = 0.0, gamma = 0.0;
+  double gbound = 0.0;        // 1 / Lhat, the stage-II step of the bound rule
+  bool have_bound = false;    // computed once per solve, when first needed
   int iters_run = 0, status = 0;
 
   for (int t = 1; t <= T; ++t) {
@@ -652,12 +656,29 @@ __device__ __forceinline__ void fast_body(const ammse_kparams_t& p) {
     }
     const bool adaptive = t <= p.T_c || (p.rearm && switch_iter >= 1 && t >= switch_iter &&
                                          t < switch_iter + p.T_c);
+    const bool use_bound = stage2 && !adaptive && !(p.gamma_c > 0.0) &&
+                           p.step_rule == AMMSE_STEP_BOUND;
+    if (use_bound && !have_bound) {
+      // Lhat / 2 = lambda_max(H^H S diag(alpha) S H) = lambda_max of the same
+      // K = C^H Q C with C = diag(sqrt(alpha)) per block user (C is rewritten
+      // by weights() below)
+      {
+        const int g = tid >> 4, e = tid & 15, a = e >> 2;
+        Cs[g * S::CST + e] = ((e & 3) == a) ? zd{sqrt(alpha[4 * g + a]), 0.0} : zd{0.0, 0.0};
+      }
+      __syncthreads();
+      const double lm = lanczos();
+      gbound = (lm > 0.0) ? 1.0 / (2.0 * lm) : 0.0;
+      have_bound = true;
+    }
     weights(stage2, adaptive);
     if (adaptive) {
       const double lm = lanczos();
       gamma = (lm > 0.0) ? 1.0 / (2.0 * lm) : 0.0;
     } else if (p.gamma_c > 0.0) {
       gamma = p.gamma_c;
+    } else if (use_bound) {
+      gamma = gbound;
     }
 
     // Z' = D G^ - Y from the registers, into Bs (the gradient is 2 H^H S Z')

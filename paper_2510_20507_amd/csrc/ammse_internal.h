@@ -74,6 +74,7 @@ struct ammse_kparams_t {
   int32_t lowp_iters;    // BF16 mode: iterations 1..lowp_iters use bfloat16 products
                          // (and G^0 when lowp_iters >= 1); -1: float products only
   int32_t tile_force;    // 0: per-instance tile shape from the descriptor; v + 1: shape v
+  int32_t step_rule;     // AMMSE_STEP_BOUND / AMMSE_STEP_FROZEN
   double eps1, eps2, gamma_c;
 };
 

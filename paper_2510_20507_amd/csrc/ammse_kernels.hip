@@ -8,7 +8,9 @@
 //                                     which normalises every user to unit noise)
 //   per user: interference-plus-noise covariance J-_u, Cholesky, rate, E, U, W
 //   WSR(V^{t-1}) = sum alpha_u R_u    -> stage latch (eps1), optional eps2 stop
-//   step size 1/||2 A_c||_2 by Lanczos on A_c = H^H S D S H (adaptive window)
+//   step size 1/||2 A_c||_2 by Lanczos on A_c = H^H S D S H (adaptive window);
+//                                     after it, in stage II, 1/Lhat_c with Lhat_c/2 =
+//                                     lambda_max(H_c^H S diag(alpha) S H_c), once per solve
 //   Z_c  = S (D G^_c - Y_c)          with G^ = (1+w) G^{t-1} - w G^{t-2} (linearity)
 //   Grad = 2 H_{:,c}^H Z_c            second channel product per BS
 //   V^t  = Pi_P(V^ - gamma Grad)      extrapolated step and projection per BS
@@ -44,6 +46,7 @@ struct Smem {
   int colOff[AMMSE_MAX_CELLS + 1];
   double Pc[AMMSE_MAX_CELLS];
   double gamma[AMMSE_MAX_CELLS];
+  double gbound[AMMSE_MAX_CELLS];  // 1 / Lhat_c, the stage-II step of the bound rule
   double scur[AMMSE_MAX_CELLS];    // projection factor of the current iterate per BS
   double sprev[AMMSE_MAX_CELLS];   // and of the previous one
   double mu[AMMSE_MAX_CELLS];      // WMMSE: dual variable of each BS (warm start)
@@ -1037,6 +1040,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   double wsr_prev = 0.0, wsr_prev2 = 0.0;   // WSR(V^{t-1}), WSR(V^{t-2})
   int iters_run = 0;
   int status = 0;
+  bool have_bound = false;   // sm.gbound computed (once per solve, when first needed)
 
   for (int t = 1; t <= T; ++t) {
     const bool lowp = t <= p.lowp_iters;   // bfloat16 products in this iteration
@@ -1071,6 +1075,26 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
         switch_iter = t;
       }
     }
+    // step size of this iteration: adaptive in the windows, otherwise fixed
+    const bool adaptive = t <= p.T_c || (p.rearm && switch_iter >= 1 && t >= switch_iter &&
+                                         t < switch_iter + p.T_c);
+    const bool use_bound = !wm && stage2 && !adaptive && !(p.gamma_c > 0.0) &&
+                           p.step_rule == AMMSE_STEP_BOUND;
+    if (use_bound && !have_bound) {
+      // Lhat_c / 2 = lambda_max(H_c^H S diag(alpha) S H_c) by the same Lanczos
+      // on the operator with D = alpha_u I (D is rewritten by weights() below)
+      for (int e = tid; e < U * 16; e += AMMSE_BLOCK) {
+        const int u = e >> 4, a = (e >> 2) & 3, bb = e & 3;
+        Dm[e] = (a == bb && a < N) ? zd{sm.alpha[u], 0.0} : zd{0.0, 0.0};
+      }
+      __syncthreads();
+      for (int c = 0; c < C; ++c) {
+        const double lm = (sm.cu[c] == 0) ? 0.0 : lanczos_lmax(c);
+        if (tid == 0) sm.gbound[c] = (lm > 0.0) ? 1.0 / (2.0 * lm) : 0.0;
+        __syncthreads();
+      }
+      have_bound = true;
+    }
     weights(stage2);
 
     if (wm) {   // Algorithm 2 / MMMSE: exact V minimiser, then G^t
@@ -1088,8 +1112,6 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     }
 
     // step size
-    const bool adaptive = t <= p.T_c || (p.rearm && switch_iter >= 1 && t >= switch_iter &&
-                                         t < switch_iter + p.T_c);
     if (adaptive) {
       // Gram path with order <= AMMSE_GRAM_WAVE_N: every K_c first (the whole
       // block on each), then one wave per BS runs its Lanczos iteration
@@ -1120,6 +1142,9 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       }
     } else if (p.gamma_c > 0.0) {
       if (tid < C) sm.gamma[tid] = p.gamma_c;
+      __syncthreads();
+    } else if (use_bound) {
+      if (tid < C) sm.gamma[tid] = sm.gbound[tid];
       __syncthreads();
     }
 
@@ -1412,3 +1437,4 @@ hipError_t ammse_launch_fp64(const ammse_kparams_t& p, hipStream_t s) {
 hipError_t ammse_launch_fp32(const ammse_kparams_t& p, hipStream_t s) {
   return launch_general<float>(p, s);
 }
+

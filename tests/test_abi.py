@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_version_and_status_strings(L):
-    assert L.ammse_version() == 1
+    assert L.ammse_version() == 2
     for code in range(0, 9):
         s = L.ammse_status_string(code)
         assert isinstance(s, bytes) and len(s) > 0
@@ -44,10 +44,11 @@ def test_version_and_status_strings(L):
 def test_struct_layout_matches_header():
     assert ctypes.sizeof(ammse.AmmseInstance) == 56
     assert ammse.AmmseInstance.h_off.offset == 24
-    assert ctypes.sizeof(ammse.AmmseOptions) == 72
+    assert ctypes.sizeof(ammse.AmmseOptions) == 80
     assert ammse.AmmseOptions.algorithm.offset == 40
     assert ammse.AmmseOptions.tile.offset == 44
-    assert ammse.AmmseOptions.eps1.offset == 48
+    assert ammse.AmmseOptions.step_rule.offset == 48
+    assert ammse.AmmseOptions.eps1.offset == 56
 
 
 def test_default_options_match_paper(L):
@@ -56,6 +57,7 @@ def test_default_options_match_paper(L):
     assert (o.precision, o.max_iters, o.T_c, o.warm_start, o.extrapolate) == (1, 100, 3, 1, 1)
     assert o.eps1 == pytest.approx(0.1) and o.eps2 == 0.0 and o.force_switch_iter == -1
     assert o.refine_iters == 10 and o.algorithm == ammse.ALGO_AMMMSE and o.tile == 0
+    assert o.step_rule == ammse.STEP_BOUND and o.gamma_c == 0.0 and o.rearm_at_switch == 1
 
 
 def test_validate_reports_buffer_lengths(L):
@@ -98,7 +100,7 @@ def test_validate_rejects_overlapping_precoders(L):
     dict(precision=7), dict(max_iters=-1), dict(T_c=-1), dict(lanczos_steps=65),
     dict(force_switch_iter=0), dict(eps1=-0.1), dict(T_c=0), dict(eps2=float("nan")),
     dict(path=2), dict(refine_iters=-1), dict(precision=3), dict(algorithm=3),
-    dict(tile=4), dict(tile=-1),
+    dict(tile=4), dict(tile=-1), dict(step_rule=2), dict(step_rule=-1),
 ])
 def test_validate_rejects_bad_options(L, opt):
     table, cu = _one()

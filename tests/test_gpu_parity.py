@@ -3,7 +3,8 @@
 Tolerances:
   * FP64 path: WSR trajectories agree to 1e-9 relative per iteration and the
     precoders to 1e-7 of their norm (only rounding order differs).
-  * FP32 path: final WSR within 1e-4 relative of the FP64 oracle.
+  * FP32 path: WSR trajectory, final WSR included, within 1e-4 relative of the
+    FP64 oracle at every iteration.
 The stage switch is an integer decided by comparing a floating-point change
 with eps1; where the two sides decide differently on a borderline case the
 GPU run is repeated with the oracle's switch iteration forced, so that both
@@ -74,31 +75,10 @@ def compare_wsr(batch, res, refs, idx, opts, tol, force_retry=True):
     return len(bad)
 
 
-def stable_horizon(batch, i, ref, iters, rel=1e-6, bound=1e-5):
-    """Last iteration up to which the oracle's own trajectory is well
-    conditioned: rerun with every iterate V^t multiplied elementwise by
-    (1 + rel * noise) (seeded; about the rounding an FP32 iteration injects)
-    and the same stage switch, its WSR stays within `bound` of the
-    unperturbed run for every t up to the returned horizon."""
-    inst = batch.instance(int(i))
-    prob = O.from_instance(inst)
-    V0 = O.split_v(prob, inst["V0"])
-    rng = np.random.default_rng(12345 + int(i))
-
-    def perturb(t, V):
-        return V * (1.0 + rel * rng.standard_normal(V.shape))
-
-    r1 = O.ammmse(prob, V0, iters, force_switch_iter=ref["switch_iter"], perturb=perturb)
-    dev = np.abs(r1["trace"] - ref["trace"]) / np.abs(ref["trace"])
-    over = np.nonzero(dev > bound)[0]
-    return iters if over.size == 0 else int(over[0]) - 1
-
-
-def compare_traces(batch, res, refs, idx, opts, tol, iters):
-    """WSR trajectories against the oracle up to each instance's stable
-    horizon (the final WSR too when the whole run is well conditioned);
-    borderline stage switches are re-run with the oracle's switch."""
-    horizons = []
+def compare_traces(batch, res, refs, idx, opts, tol):
+    """Whole WSR trajectories (WSR(V^0) .. WSR(V^T), the final WSR included)
+    against the oracle at every iteration; borderline stage switches are re-run
+    with the oracle's switch."""
     for k, i in enumerate(idx):
         ref = refs[k]
         tr = res.trace[i]
@@ -106,11 +86,16 @@ def compare_traces(batch, res, refs, idx, opts, tol, iters):
             r2 = ammse.solve(batch.subset([i]), opts, want_trace=True,
                              force_switch=np.array([ref["switch_iter"]], np.int32))
             tr = r2.trace[0]
-        h = stable_horizon(batch, i, ref, iters)
-        horizons.append(h)
-        assert h >= 10, (i, h)
-        np.testing.assert_allclose(tr[:h + 1], ref["trace"][:h + 1], rtol=tol, err_msg=str(i))
-    return horizons
+        rt = np.asarray(ref["trace"])
+        err = np.abs(tr - rt) / np.abs(rt)
+        assert err.max() <= tol, (i, int(err.argmax()), float(err.max()))
+
+
+def golden(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as f:
+        return json.load(f)
 
 
 # ---------------------------------------------------------------------------
@@ -149,10 +134,10 @@ def test_fp64_ragged_shapes_iterates():
     """Uneven shapes spanning several 64-wide tiles with ragged tails, empty
     cells, N = 1..4, d < N, M < N*U, in one launch."""
     b = _ragged_batch()
-    T = 40
+    T = 60
     refs = oracle_runs(b, range(b.batch), iters=T)
     fs = np.array([r["switch_iter"] for r in refs], np.int32)
-    say("case: ragged fp64 T=40", b.batch)
+    say("case: ragged fp64 T=60", b.batch)
     res = ammse.solve(b, ammse.Options(precision=ammse.PREC_FP64, max_iters=T), want_trace=True,
                       force_switch=fs)
     for i, ref in enumerate(refs):
@@ -166,15 +151,17 @@ def test_fp64_ragged_shapes_iterates():
 
 @pytest.mark.parametrize("kw", [dict(warm_start=0), dict(extrapolate=0),
                                 dict(T_c=2, gamma_c=0.01, rearm_at_switch=0),
-                                dict(rearm_at_switch=0)])
+                                dict(rearm_at_switch=0), dict(step_rule=1),
+                                dict(step_rule=1, rearm_at_switch=0)])
 def test_fp64_option_variants(kw):
-    """A-WMMSE, no extrapolation, fixed gamma_c, single adaptive window."""
+    """A-WMMSE, no extrapolation, fixed gamma_c, single adaptive window, the
+    frozen step rule (with and without the re-armed window)."""
     b = synth.pack([random_instance(110, M=8, cell_users=[2, 2], N=2, d=2, P=[4.0, 6.0]),
                     random_instance(111, M=12, cell_users=[4], N=2, d=1, P=3.0)])
-    # with the single adaptive window the frozen stage-I step makes stage II
-    # oscillate; rounding differences then grow geometrically, so that variant
-    # is compared over a shorter horizon
-    T = 16 if kw == dict(rearm_at_switch=0) else 30
+    # the frozen rule keeps a step from a smaller curvature in stage II and
+    # oscillates there; rounding differences then grow geometrically, so those
+    # variants are compared over a shorter run
+    T = 16 if kw.get("step_rule") == 1 else 60
     okw = dict(iters=T)
     if "warm_start" in kw:
         okw["warm_start"] = False
@@ -184,6 +171,8 @@ def test_fp64_option_variants(kw):
         okw.update(Tc=kw["T_c"], gamma_c=kw["gamma_c"])
     if "rearm_at_switch" in kw:
         okw["rearm_at_switch"] = bool(kw["rearm_at_switch"])
+    if "step_rule" in kw:
+        okw["step_rule"] = "frozen"
     refs = oracle_runs(b, range(b.batch), **okw)
     fs = np.array([r["switch_iter"] if r["switch_iter"] > 0 else 0 for r in refs], np.int32)
     say("case: variants", kw)
@@ -247,6 +236,8 @@ def test_wsr_entry_point():
 # ---------------------------------------------------------------------------
 
 def test_fp32_rayleigh_sweep_subset():
+    """Eight instances of the benchmark sweep (two per SNR) in their own launch:
+    the whole WSR trajectory within 1e-4 of the oracle."""
     b = synth.rayleigh_sweep(B_per_p=3)
     idx = [0, 1, 3, 4, 6, 7, 9, 10]
     sub = b.subset(idx)
@@ -255,15 +246,13 @@ def test_fp32_rayleigh_sweep_subset():
     res = ammse.solve(sub, opts, want_trace=True)
     assert np.all(res.status == 0)
     refs = oracle_runs(sub, range(sub.batch), iters=100)
-    h = compare_traces(sub, res, refs, list(range(sub.batch)), opts, 1e-4, 100)
-    say("stable horizons", h)
-    assert sum(x == 100 for x in h) >= 4
+    compare_traces(sub, res, refs, list(range(sub.batch)), opts, 1e-4)
 
 
 def test_fp32_full_bench_batch_sampled():
     """The benchmarked launch (1024 instances, M=64, 16 users, N=d=4, all four
-    SNRs, T=100) in one call; sampled instances against the oracle and
-    properties on every instance."""
+    SNRs, T=100) in one call: 32 instances (8 per SNR, stored FP64 oracle runs)
+    to 1e-4 over the whole trajectory, properties on every instance."""
     b = synth.rayleigh_sweep(B_per_p=256)
     opts = ammse.Options(precision=ammse.PREC_FP32, max_iters=100)
     say("case: full 1024-instance fp32 launch")
@@ -275,44 +264,41 @@ def test_fp32_full_bench_batch_sampled():
     for i in range(b.batch):
         Vi = res.V[b.v_off[i]: b.v_off[i] + 64 * 64]
         assert np.vdot(Vi, Vi).real <= b.P[i] * (1 + 1e-5)
-    idx = [3, 300, 555, 1000]
-    refs = oracle_runs(b, idx, iters=100)
-    h = compare_traces(b, res, refs, idx, opts, 1e-4, 100)
-    say("stable horizons", h)
+    g = golden("wmmse_ref_rayleigh_sweep4x256.json")["ammmse"]
+    refs = [dict(trace=g["trace"][k], switch_iter=g["switch_iter"][k], wsr=g["wsr"][k])
+            for k in range(len(g["index"]))]
+    compare_traces(b, res, refs, g["index"], opts, 1e-4)
+    same = [res.switch_iter[i] == r["switch_iter"] for i, r in zip(g["index"], refs)]
+    say("switch agreement", sum(same), "of", len(same))
 
 
 def test_fp64_hexcell_iterates():
-    """Seven-cell instances with path loss (uneven users, M, N) in FP64.  These
-    trajectories are unstable under the fixed step: the FP64 oracle itself,
-    restarted from V0 perturbed by 1e-15, drifts by 1e-13 at t = 30 and 1e-7
-    at t = 60 (roughly x10 every 4 iterations after t = 25).  So the
-    trajectory is compared to 1e-9 up to t = 30 and to 1e-6 up to t = 40, and
-    the precoders after 20 iterations to 1e-10 of their norm."""
+    """Seven-cell instances with path loss (uneven users, M, N) in FP64: the
+    whole 100-iteration WSR trajectory to 1e-9 and the precoders after 20
+    iterations to 1e-10 of their norm."""
     b = synth.hexcell_batch(B=12)
     idx = [0, 3, 5, 8]
     sub = b.subset(idx)
-    refs = oracle_runs(sub, range(sub.batch), iters=40)
+    refs = oracle_runs(sub, range(sub.batch), iters=100)
     refs20 = oracle_runs(sub, range(sub.batch), iters=20)
     fs = np.array([r["switch_iter"] for r in refs], np.int32)
-    say("case: hexcell fp64 T=40")
-    res = ammse.solve(sub, ammse.Options(precision=ammse.PREC_FP64, max_iters=40),
+    say("case: hexcell fp64 T=100")
+    res = ammse.solve(sub, ammse.Options(precision=ammse.PREC_FP64, max_iters=100),
                       want_trace=True, force_switch=fs)
     res20 = ammse.solve(sub, ammse.Options(precision=ammse.PREC_FP64, max_iters=20),
                         force_switch=fs)
     assert np.all(res.status == 0)
     for i, ref in enumerate(refs):
-        np.testing.assert_allclose(res.trace[i, :31], ref["trace"][:31], rtol=1e-9)
-        np.testing.assert_allclose(res.trace[i], ref["trace"], rtol=1e-6)
+        np.testing.assert_allclose(res.trace[i], ref["trace"], rtol=1e-9)
         Vg = np.concatenate([x.ravel() for x in v_blocks(sub, res20.V, i)])
         Vr = np.concatenate([x.ravel() for x in
                              O.join_v(O.from_instance(sub.instance(i)), refs20[i]["V"])])
         assert np.linalg.norm(Vg - Vr) <= 1e-10 * np.linalg.norm(Vr)
 
 
-def test_fp32_hexcell_prefix():
-    """FP32 on the seven-cell layout against the oracle up to each
-    trajectory's stable horizon; the rest of the solve is checked for
-    validity (finite, feasible)."""
+def test_fp32_hexcell_small_batch():
+    """FP32 on four seven-cell instances in their own launch: the whole WSR
+    trajectory within 1e-4 of the oracle; finite and feasible precoders."""
     b = synth.hexcell_batch(B=12)
     idx = [0, 3, 5, 8]
     sub = b.subset(idx)
@@ -321,13 +307,34 @@ def test_fp32_hexcell_prefix():
     say("case: hexcell fp32 T=100")
     res = ammse.solve(sub, opts, want_trace=True)
     assert np.all(res.status == 0)
-    h = compare_traces(sub, res, refs, list(range(sub.batch)), opts, 1e-4, 100)
-    say("stable horizons", h)
+    compare_traces(sub, res, refs, list(range(sub.batch)), opts, 1e-4)
     for i in range(sub.batch):
         assert np.all(np.isfinite(res.trace[i])) and res.wsr[i] > 0
         inst = sub.instance(i)
         for c, Vc in enumerate(v_blocks(sub, res.V, i)):
             assert np.vdot(Vc, Vc).real <= inst["P"][c] * (1 + 1e-5)
+
+
+def test_fp32_hexcell_full_launch_sampled():
+    """The seven-cell launch the benchmark times: all 4096 uneven instances in
+    one persistent launch with the autotuned tile shapes.  32 stored oracle runs
+    (16 per tile-shape class present) to 1e-4 over the whole trajectory, status,
+    finiteness and feasibility on every instance."""
+    b = synth.hexcell_batch(4096)
+    opts = ammse.Options(precision=ammse.PREC_FP32, max_iters=100)
+    say("case: hexcell 4096 fp32 launch (autotuned)")
+    res = ammse.solve(b, opts, want_trace=True, autotune=True)
+    assert np.all(res.status == 0)
+    assert np.all(np.isfinite(res.wsr)) and np.all(res.wsr > 0)
+    for i in range(0, b.batch, 97):
+        inst = b.instance(i)
+        for c, Vc in enumerate(v_blocks(b, res.V, i)):
+            assert np.vdot(Vc, Vc).real <= inst["P"][c] * (1 + 1e-5)
+    g = golden("oracle_ref_hexcell7_b4096.json")["ammmse"]
+    assert set(g["shape_class"]) == {0, 1}
+    refs = [dict(trace=g["trace"][k], switch_iter=g["switch_iter"][k], wsr=g["wsr"][k])
+            for k in range(len(g["index"]))]
+    compare_traces(b, res, refs, g["index"], opts, 1e-4)
 
 
 def test_fp32_large_instance_sample():
@@ -347,9 +354,8 @@ def test_fp32_large_instance_sample():
 @pytest.mark.parametrize("U,N,d", [(16, 4, 4), (32, 2, 2), (64, 1, 1)])
 def test_fp32_lds_kernel_shapes_vs_oracle(U, N, d):
     """Single-cell M = 64, U*N = U*d = 64 for N = 4, 2, 1 (the shapes the
-    LDS-resident kernel serves), all four SNRs, against the oracle up to each
-    trajectory's stable horizon (at 30 dB some runs are chaotic after ~60
-    iterations: a 1e-7 change of V0 moves the oracle's own final WSR by 1e-2)."""
+    LDS-resident kernel serves), all four SNRs: the whole WSR trajectory
+    within 1e-4 of the oracle."""
     insts = [random_instance(200 + k, M=64, cell_users=[U], N=N, d=d, P=10.0 ** k,
                              alpha_range=(0.5, 1.5)) for k in range(4)]
     b = synth.pack(insts)
@@ -358,15 +364,13 @@ def test_fp32_lds_kernel_shapes_vs_oracle(U, N, d):
     res = ammse.solve(b, opts, want_trace=True)
     assert np.all(res.status == 0)
     refs = oracle_runs(b, range(b.batch), iters=100)
-    h = compare_traces(b, res, refs, list(range(b.batch)), opts, 1e-4, 100)
-    say("stable horizons", h)
-    assert sum(x == 100 for x in h) >= 2
+    compare_traces(b, res, refs, list(range(b.batch)), opts, 1e-4)
 
 
 def test_lds_kernel_matches_general_kernel():
-    """Both FP32 kernels on the same 64 instances: identical stage decisions
-    for nearly all, WSR trajectories within FP32 rounding over the first 20
-    iterations, and equal final WSR at 0 and 10 dB (well-conditioned runs)."""
+    """Both FP32 kernels on the same 64 instances (16 per SNR): identical stage
+    decisions for nearly all and, where they agree, whole WSR trajectories
+    within 2e-4 of each other (each within 1e-4 of the oracle)."""
     b = synth.rayleigh_sweep(B_per_p=16)
     say("case: lds vs general")
     fast = ammse.solve(b, ammse.Options(precision=ammse.PREC_FP32, max_iters=100),
@@ -375,9 +379,8 @@ def test_lds_kernel_matches_general_kernel():
                                        path=ammse.PATH_GENERAL), want_trace=True)
     same = fast.switch_iter == gen.switch_iter
     assert same.mean() >= 0.9
-    np.testing.assert_allclose(fast.trace[same, :21], gen.trace[same, :21], rtol=1e-4)
-    low = same & (np.arange(b.batch) < 32)
-    np.testing.assert_allclose(fast.wsr[low], gen.wsr[low], rtol=2e-4)
+    np.testing.assert_allclose(fast.trace[same], gen.trace[same], rtol=2e-4)
+    np.testing.assert_allclose(fast.wsr[same], gen.wsr[same], rtol=2e-4)
 
 
 def test_lds_kernel_without_trace_matches_traced_run():
@@ -422,8 +425,8 @@ def test_lds_kernel_option_variants(variant):
     """The LDS-resident kernel under the option variants (eps2 stop, omega = 0,
     A-WMMSE without warm start, a forced stage switch): the reported WSR is the
     WSR of the returned precoders (ammse_wsr), every precoder meets its budget,
-    and at 0 and 10 dB the WSR trajectory follows the oracle run with the same
-    options over the first 20 iterations."""
+    and at every SNR the WSR trajectory follows the oracle run with the same
+    options to 1e-4 (up to the stop iteration with eps2)."""
     okw, gkw = {"eps2": (dict(eps2=1e-4), dict(eps2=1e-4)),
                 "no_extrapolation": (dict(extrapolate=False), dict(extrapolate=0)),
                 "no_warm_start": (dict(warm_start=False), dict(warm_start=0)),
@@ -444,32 +447,33 @@ def test_lds_kernel_option_variants(variant):
     for i in range(b.batch):
         Vi = res.V[b.v_off[i]: b.v_off[i] + n]
         assert np.vdot(Vi, Vi).real <= b.P[i] * (1 + 1e-5)
-    idx = [0, 1, 2, 3]          # 0 dB and 10 dB
-    refs = oracle_runs(b, idx, iters=T, **okw)
-    for k, i in enumerate(idx):
-        ref = refs[k]
+    refs = oracle_runs(b, range(b.batch), iters=T, **okw)
+    for i, ref in enumerate(refs):
         tr = res.trace[i]
         if res.switch_iter[i] != ref["switch_iter"]:
             r2 = ammse.solve(b.subset([i]), opts, want_trace=True,
                              force_switch=np.array([ref["switch_iter"]], np.int32))
             tr = r2.trace[0]
-        m = min(21, len(ref["trace"]))
-        np.testing.assert_allclose(tr[:m], ref["trace"][:m], rtol=1e-4, err_msg=str(i))
         if variant == "eps2":
             assert abs(int(res.iters[i]) - ref["iters"]) <= 2, (i, res.iters[i], ref["iters"])
+            m = min(int(res.iters[i]), ref["iters"]) + 1
+        else:
+            m = T + 1
+        np.testing.assert_allclose(tr[:m], ref["trace"][:m], rtol=1e-4, err_msg=str(i))
 
 
 def test_lanczos_order_beyond_the_lds_vectors():
     """Single cell with U N = 520 <= M = 528, FP64: the step size runs Lanczos
     of order 520, above the 512 whose vectors the general kernel keeps in LDS,
-    so its vectors stay in the workspace; the WSR trajectory over 12 iterations
-    (the adaptive step sizes of both windows) matches the oracle to 1e-9."""
+    so its vectors stay in the workspace; the WSR trajectory over 20 iterations
+    (the adaptive step sizes of both windows, then the stage-II bound, whose
+    Lanczos on the antenna side has order 528) matches the oracle to 1e-9."""
     b = synth.pack([random_instance(321, M=528, cell_users=[130], N=4, d=1, P=100.0)])
-    opts = ammse.Options(precision=ammse.PREC_FP64, max_iters=12, path=ammse.PATH_GENERAL)
+    opts = ammse.Options(precision=ammse.PREC_FP64, max_iters=20, path=ammse.PATH_GENERAL)
     say("case: Lanczos order 520, FP64")
     res = ammse.solve(b, opts, want_trace=True)
     assert res.status[0] == 0
-    ref = oracle_runs(b, [0], iters=12)[0]
+    ref = oracle_runs(b, [0], iters=20)[0]
     tr = res.trace[0]
     if res.switch_iter[0] != ref["switch_iter"]:
         tr = ammse.solve(b, opts, want_trace=True,
@@ -494,4 +498,4 @@ def test_fp32_gram_step_size_orders(cells, M, N, d):
     res = ammse.solve(b, opts, want_trace=True)
     assert res.status[0] == 0
     refs = oracle_runs(b, [0], iters=30)
-    compare_traces(b, res, refs, [0], opts, 1e-4, 30)
+    compare_traces(b, res, refs, [0], opts, 1e-4)

@@ -2,12 +2,16 @@
 oracle of the unrolled solver (torch autograd on the paper's steps, pinned by
 finite differences in tests/test_unrolled_oracle.py).
 
-Bars: FP64 forward WSR and trace within 1e-10 of the oracle; FP64 gradients
-(step sizes and channel) within 1e-8 relative in norm; gradients independent
-of the checkpoint interval; at the M=64, 16-user, N=d=4, P=20 dB shape with
-the paper's step schedule, FP32 gradients within 2e-3 of the FP64 kernel's
-(relative, in norm) and the FP64 kernel's step-size gradient within 1e-5 of
-central differences with h = 1e-3 gamma_t.
+Bars: FP64 forward WSR and trace within 1e-10 of the oracle, with the stage
+switch the oracle's own eps1 rule picks; FP64 gradients (step sizes and
+channel) within 1e-8 relative in norm, at small shapes and at the M=64,
+16-user, N=d=4, P=20 dB, T=20 shape with the paper's step schedule; there
+FP32 gradients within 2e-3 of the oracle's (relative, in norm); gradients
+independent of the checkpoint interval; the FP64 kernel's step-size gradient
+within 1e-5 of central differences with h = 1e-3 gamma_t, and its channel
+gradient along a random direction within 1e-5 of central differences with
+h = 1e-3; a step schedule shared by the batch receives the sum of the
+per-instance gradients.
 """
 import numpy as np
 import pytest
@@ -100,7 +104,9 @@ def test_fp64_forward_and_gradients_match_oracle():
         inst = b.instance(i)
         prob = O.from_instance(inst)
         V0 = O.split_v(prob, inst["V0"])
-        sw = int(res["sw"][i]) if res["sw"][i] >= 1 else T + 1
+        sw = O_unrolled().switch_iter(prob.Hs[:, 0], prob.sigma2, prob.alpha, prob.P[0], V0,
+                                      gam[i])
+        assert (int(res["sw"][i]) if res["sw"][i] >= 1 else T + 1) == sw, (i, res["sw"][i], sw)
         w, gg, gH, VT, trace = O_unrolled().value_and_grad(prob.Hs[:, 0], prob.sigma2, prob.alpha,
                                                            prob.P[0], V0, gam[i], sw)
         say(f"instance {i}: switch {res['sw'][i]}, wsr gpu {res['wsr'][i]:.12f} oracle {w:.12f}")
@@ -176,6 +182,66 @@ def test_fp32_gradients_match_fp64_at_full_shape():
         assert eg <= 2e-3 and eh <= 2e-3
 
 
+@pytest.mark.parametrize("prec,tol", [(ammse.PREC_FP64, 1e-8), (ammse.PREC_FP32, 2e-3)])
+def test_gradients_match_oracle_at_full_shape(prec, tol):
+    """Two instances of the M=64, 16-user, N=d=4, P=20 dB batch, T=20 with the
+    paper's step schedule, checkpoints every 5: forward WSR, stage switch (the
+    oracle's own eps1 decision), step-size and channel gradients against the
+    oracle of the unrolled solver."""
+    b = _unroll_batch(2)
+    T = 20
+    gam, _ = _paper_steps(b, T)
+    res = _run(b, gam, prec, K=5)
+    for i in range(b.batch):
+        inst = b.instance(i)
+        prob = O.from_instance(inst)
+        V0 = O.split_v(prob, inst["V0"])
+        H = prob.Hs[:, 0]
+        sw = O_unrolled().switch_iter(H, prob.sigma2, prob.alpha, prob.P[0], V0, gam[i])
+        gsw = int(res["sw"][i]) if res["sw"][i] >= 1 else T + 1
+        r = res
+        if gsw != sw:   # a borderline eps1 decision in float: follow the oracle's branch
+            r = _run(b, gam, prec, K=5, force=np.array([sw] * b.batch, np.int32))
+        w, gg, gH, _, _ = O_unrolled().value_and_grad(H, prob.sigma2, prob.alpha, prob.P[0], V0,
+                                                      gam[i], sw)
+        eg = np.linalg.norm(r["dg"][i] - gg) / np.linalg.norm(gg)
+        eh = np.linalg.norm(_h_block(b, r["dH"], i) - gH) / np.linalg.norm(gH)
+        ew = abs(r["wsr"][i] - w) / w
+        say(f"instance {i} prec {prec}: switch gpu {gsw} oracle {sw}, wsr {ew:.2e}, "
+            f"dgamma {eg:.2e}, dH {eh:.2e}")
+        if prec == ammse.PREC_FP64:
+            assert gsw == sw
+        assert ew <= (1e-10 if prec == ammse.PREC_FP64 else 1e-4)
+        assert eg <= tol and eh <= tol
+
+
+def test_fp64_channel_gradient_matches_central_differences_at_full_shape():
+    """d/dh WSR(H + h Delta) at h = 0 by central differences (h = 1e-3, Delta a
+    random complex direction of unit norm per instance, stage switch held
+    fixed) against Re <dH, Delta> from the adjoint, at the full shape."""
+    b = _unroll_batch(2)
+    T = 20
+    gam, fs = _paper_steps(b, T)
+    base = _run(b, gam, ammse.PREC_FP64, K=5, force=fs)
+    rng = np.random.default_rng(77)
+    Dl = rng.standard_normal(b.H.shape) + 1j * rng.standard_normal(b.H.shape)
+    blocks = [slice(int(b.h_off[i]), int(b.h_off[i]) + int(b.U[i] * b.N[i] * b.M[i]))
+              for i in range(b.batch)]
+    for blk in blocks:
+        Dl[blk] /= np.linalg.norm(Dl[blk])
+    h = 1e-3
+
+    def shifted(sign):
+        bb = b.subset(range(b.batch))
+        bb.H = b.H + sign * h * Dl
+        return _run(bb, gam, ammse.PREC_FP64, K=5, force=fs)["wsr"]
+
+    fd = (shifted(+1) - shifted(-1)) / (2 * h)
+    adj = np.array([np.real(np.vdot(base["dH"][blk], Dl[blk])) for blk in blocks])
+    say(f"channel direction: adjoint {adj}, central difference {fd}")
+    np.testing.assert_allclose(adj, fd, rtol=1e-5)
+
+
 def test_fp64_step_gradient_matches_central_differences():
     b = _unroll_batch(2)
     T = 20
@@ -215,4 +281,8 @@ def test_autograd_function():
     wsr2, _, _, _ = unrolled_wsr(plan, db, gs, ckpt_every=2)
     wsr2.sum().backward()
     assert gs.grad.shape == (T,)
+    shared = np.tile(gam[0], (b.batch, 1))
+    per = _run(b, shared, ammse.PREC_FP64, K=2)
+    np.testing.assert_allclose(gs.grad.cpu().numpy(), per["dg"].sum(axis=0), rtol=1e-13,
+                               atol=1e-13 * np.abs(per["dg"]).max())
     plan.close()
