@@ -274,6 +274,29 @@ ammse_status_t ammse_solve(ammse_plan_t plan, const void* H, const double* sigma
                            size_t workspace_bytes, ammse_stream_t stream);
 
 /*
+ * Allocation-free ammse_solve, for callers that cannot allocate device memory
+ * around the call (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Arguments and results as ammse_solve,
+ * without the workspace: the kernels use the library's own static device
+ * array of AMMSE_SCRATCH_BYTES, one per device, whose address is resolved when
+ * the first plan on that device is created (ammse_plan_create).  The call
+ * itself allocates and frees nothing.
+ *   - Returns AMMSE_ERR_WORKSPACE, enqueuing nothing, when the plan needs more
+ *     workspace than AMMSE_SCRATCH_BYTES (ammse_plan_workspace_size).
+ *   - Every call on one device shares that device's array, which keeps the
+ *     last call's contents; the kernels write every workspace value before
+ *     they read it, so nothing needs clearing between calls.  Calls that
+ *     overlap in time on one device (several streams, several host threads)
+ *     race on the array and give undefined results: serialise them.
+ */
+#define AMMSE_SCRATCH_BYTES ((size_t)64 << 20)
+ammse_status_t ammse_solve_noalloc(ammse_plan_t plan, const void* H, const double* sigma2,
+                                   const double* alpha, const double* P, void* V, double* wsr,
+                                   int32_t* iters, int32_t* switch_iter, int32_t* status,
+                                   double* wsr_trace, const int32_t* force_switch,
+                                   ammse_stream_t stream);
+
+/*
  * Weighted sum rate (Section II rate definition, bits) of the precoders V for
  * every instance of the plan; same buffer conventions as ammse_solve.
  */

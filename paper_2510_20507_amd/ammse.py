@@ -37,7 +37,9 @@ INST_ZERO_POWER = 4
 EXPORTED = ("ammse_version", "ammse_status_string", "ammse_default_options", "ammse_validate",
             "ammse_plan_create", "ammse_plan_workspace_size", "ammse_plan_destroy",
             "ammse_solve", "ammse_wsr", "ammse_plan_info", "ammse_unrolled_workspace_size",
-            "ammse_unrolled_forward", "ammse_unrolled_backward", "ammse_autotune")
+            "ammse_unrolled_forward", "ammse_unrolled_backward", "ammse_autotune",
+            "ammse_solve_noalloc")
+SCRATCH_BYTES = 64 << 20   # AMMSE_SCRATCH_BYTES
 KERNEL_LDS_MFMA = 0
 KERNEL_GENERAL = 1
 
@@ -102,6 +104,8 @@ def lib() -> ctypes.CDLL:
     L.ammse_plan_destroy.argtypes = [vp]
     L.ammse_solve.restype = i32
     L.ammse_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.ammse_solve_noalloc.restype = i32
+    L.ammse_solve_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.ammse_wsr.restype = i32
     L.ammse_wsr.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.ammse_autotune.restype = i32
@@ -245,6 +249,19 @@ class Plan:
                                  _ptr(status), _ptr(trace), _ptr(force_switch), _ptr(workspace),
                                  workspace.numel() * workspace.element_size(), stream)
         _check(code, "ammse_solve")
+
+    def solve_noalloc(self, H, sigma2, alpha, P, V, wsr, iters=None, switch_iter=None,
+                      status=None, trace=None, force_switch=None, stream=None):
+        """ammse_solve_noalloc on device tensors: as solve(), with the library's
+        static workspace array instead of a caller workspace."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        code = lib().ammse_solve_noalloc(self._handle, _ptr(H), _ptr(sigma2), _ptr(alpha),
+                                         _ptr(P), _ptr(V), _ptr(wsr), _ptr(iters),
+                                         _ptr(switch_iter), _ptr(status), _ptr(trace),
+                                         _ptr(force_switch), stream)
+        _check(code, "ammse_solve_noalloc")
 
     def unrolled_sizes(self, ckpt_every: int) -> tuple:
         """(workspace bytes, checkpoint bytes) of the unrolled solver."""

@@ -27,6 +27,7 @@ struct ammse_plan_s {
   // the shape class of each launch position
   std::vector<ammse_desc_t> h_desc;
   std::vector<int8_t> tile_class;
+  void* scratch = nullptr;     // this device's static workspace array (ammse_solve_noalloc)
 };
 
 namespace {
@@ -248,6 +249,12 @@ ammse_status_t ammse_plan_create(ammse_plan_t* plan, int32_t device,
     for (int c = 0; c < t.C; ++c) n = std::max(n, cell_users[(int64_t)t.cell_off + c] * t.d);
     P->tile_class[k] = (int8_t)((n <= 16) ? 0 : (n <= 32) ? 1 : 2);
   }
+  // set-up of the allocation-free solve: this device's copy of the static
+  // workspace array (looked up once per device, with the device current)
+  if (ammse_scratch_resolve(device, &P->scratch) != hipSuccess) {
+    delete P;
+    return AMMSE_ERR_HIP;
+  }
   if (hipMalloc(&P->d_desc, sizeof(ammse_desc_t) * batch) != hipSuccess ||
       hipMalloc(&P->d_cell_users, sizeof(int32_t) * std::max<int64_t>(ncu, 1)) != hipSuccess) {
     if (P->d_desc) (void)hipFree(P->d_desc);
@@ -345,6 +352,18 @@ ammse_status_t ammse_solve(ammse_plan_t plan, const void* H, const double* sigma
   k.ws = (char*)workspace;
   k.wsr_only = 0;
   return launch(plan, k, (hipStream_t)stream);
+}
+
+ammse_status_t ammse_solve_noalloc(ammse_plan_t plan, const void* H, const double* sigma2,
+                                   const double* alpha, const double* P, void* V, double* wsr,
+                                   int32_t* iters, int32_t* switch_iter, int32_t* status,
+                                   double* wsr_trace, const int32_t* force_switch,
+                                   ammse_stream_t stream) {
+  if (!plan) return AMMSE_ERR_NULL;
+  if (plan->ws_bytes > AMMSE_SCRATCH_BYTES) return AMMSE_ERR_WORKSPACE;
+  if (!plan->scratch) return AMMSE_ERR_HIP;
+  return ammse_solve(plan, H, sigma2, alpha, P, V, wsr, iters, switch_iter, status, wsr_trace,
+                     force_switch, plan->scratch, AMMSE_SCRATCH_BYTES, stream);
 }
 
 ammse_status_t ammse_wsr(ammse_plan_t plan, const void* H, const double* sigma2,

@@ -218,3 +218,7 @@ bool ammse_fast_eligible(int C, int U, int M, int N, int d);
 size_t ammse_fast_lds_bytes();
 hipError_t ammse_launch_fast_fp32(const ammse_kparams_t& p, hipStream_t s);
 hipError_t ammse_launch_fp32(const ammse_kparams_t& p, hipStream_t s);
+// Device address of the calling thread's current device's copy of the
+// library's static workspace array (AMMSE_SCRATCH_BYTES), resolved once per
+// device and cached; call with `device` current.
+hipError_t ammse_scratch_resolve(int device, void** ptr);

@@ -25,6 +25,7 @@
 
 #include <math.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "ammse_internal.h"
@@ -1438,3 +1439,29 @@ hipError_t ammse_launch_fp32(const ammse_kparams_t& p, hipStream_t s) {
   return launch_general<float>(p, s);
 }
 
+// ---------------------------------------------------------------------------
+// Workspace of the allocation-free solve: a static device array (one copy per
+// device), whose device address is looked up once per device with that device
+// current.  Host code never passes the array's name to a kernel (in host code
+// it is a host-side stand-in); it passes the looked-up address.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[AMMSE_SCRATCH_BYTES];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+}  // namespace
+
+hipError_t ammse_scratch_resolve(int device, void** ptr) {
+  if (device < 0 || device >= kScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *ptr = g_scratch_ptr[device];
+  return hipSuccess;
+}

@@ -28,7 +28,7 @@ def L():
 
 def test_every_declared_symbol_is_exported(L):
     names = _declared_functions()
-    assert len(names) == 14
+    assert len(names) == 15
     assert set(names) == set(ammse.EXPORTED)
     for n in names:
         assert hasattr(L, n), n
