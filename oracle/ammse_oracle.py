@@ -62,7 +62,8 @@ __all__ = [
     "Problem", "from_instance", "split_v", "join_v", "cross_terms", "user_rates", "wsr_bits",
     "mmse_receivers", "mse_matrices", "mse_at_mmse", "objective_f", "transmit_hessians",
     "gradient_v", "step_sizes", "step_bound", "project_spc", "omega_schedule", "rel_change",
-    "ammmse", "wmmse", "wmmse_precoder", "mmmse", "kkt_residual", "kappa", "solve_batch",
+    "ammmse", "wmmse", "wmmse_precoder", "mmmse", "bcgd_wmmse", "receiver_gradient",
+    "schulz_step", "rx_covariances", "kkt_residual", "kappa", "solve_batch",
 ]
 
 
@@ -501,6 +502,85 @@ def mmmse(prob: Problem, V0u: np.ndarray, max_iters: int = 500, eps1: float = 0.
 
 
 # ---------------------------------------------------------------------------
+# BCGD-WMMSE (Section VII-F ablation): every block by one explicit step
+# ---------------------------------------------------------------------------
+
+def rx_covariances(prob: Problem, Vu: np.ndarray) -> np.ndarray:
+    """J_u = sum_l H_{u,c(l)} V_l V_l^H H_{u,c(l)}^H + sigma2_u I (all users l,
+    the matrix inverted by the receiver equation of Section IV): [U, N, N]."""
+    T = cross_terms(prob, Vu)
+    J = _covariances(T).sum(axis=1)
+    return J + prob.sigma2[:, None, None] * np.eye(prob.N)[None]
+
+
+def receiver_gradient(prob: Problem, Uu: np.ndarray, Wu: np.ndarray, Vu: np.ndarray) -> np.ndarray:
+    """Block gradient of f in U_u (Definition 1 inner product): f depends on
+    U_u through alpha_u Tr(W_u E_u) with E_u = I - U^H H V_u - V_u^H H^H U +
+    U^H J_u U, so grad_u = 2 alpha_u (J_u U_u W_u - H_{u,c(u)} V_u W_u)."""
+    J = rx_covariances(prob, Vu)
+    G = np.einsum("unm,umd->und", prob.H_serving(), Vu)
+    return 2.0 * prob.alpha[:, None, None] * (J @ Uu @ Wu - G @ Wu)
+
+
+def schulz_step(W: np.ndarray, E: np.ndarray) -> np.ndarray:
+    """Schulz iteration for E^{-1} (Section VII-F): W (2I - E W), symmetrised."""
+    I = np.eye(W.shape[-1])
+    Wn = W @ (2.0 * I - E @ W)
+    return 0.5 * (Wn + np.conj(np.swapaxes(Wn, -1, -2)))
+
+
+def bcgd_wmmse(prob: Problem, V0u: np.ndarray, iters: int, Tc: int = 3,
+               extrapolate: bool = True, step_rule: str = "bound") -> dict:
+    """BCGD-WMMSE, the full block-coordinate gradient method of the ablation
+    in Section VII-F: U, W and V each take one explicit step per iteration.
+    Readings (the section fixes only the W update):
+      * start: U^0 the MMSE receivers at V^0 and W^0 = E(U^0, V^0)^{-1};
+      * U step: U^t = U^{t-1} - gu_u grad_U f(U^{t-1}, W^{t-1}, V^{t-1}) with
+        gu_u = 1 / (2 alpha_u ||J_u||_F ||W_u||_F), J_u the receive covariance
+        at V^{t-1}; ||.||_F bounds the spectral norms of the block Lipschitz
+        constant 2 alpha_u lambda_max(J_u) lambda_max(W_u) without an
+        eigenvalue solve;
+      * W step: W^t = W^{t-1} (2I - E_u W^{t-1}) with E_u the MSE matrix of
+        (U^t, V^{t-1}) (general definition, Section IV);
+      * V step: as Algorithm 3's second stage, at the extrapolated point with
+        (U^t, W^t): adaptive step 1/||2 A_c|| for t <= Tc, then 1 / Lhat_c
+        (step_rule "bound") or the last adaptive value ("frozen").
+    Returns the final precoders and the WSR trace WSR(V^0..V^T) in bits."""
+    if step_rule not in ("bound", "frozen"):
+        raise ValueError("step_rule must be 'bound' or 'frozen'")
+    V_prev = V0u.copy()
+    V_prev2 = V0u.copy()
+    Uu = mmse_receivers(prob, V_prev)
+    Wu = _inv_hermitian(mse_matrices(prob, Uu, V_prev))
+    trace = [wsr_bits(prob, V_prev)]
+    gamma = np.zeros(prob.C)
+    bound = None
+    for t in range(1, iters + 1):
+        omega = omega_schedule(t) if extrapolate else 0.0
+        Vhat = V_prev + omega * (V_prev - V_prev2) if t >= 2 else V_prev.copy()
+        J = rx_covariances(prob, V_prev)
+        gU = receiver_gradient(prob, Uu, Wu, V_prev)
+        nJ = np.linalg.norm(J, axis=(1, 2))
+        nW = np.linalg.norm(Wu, axis=(1, 2))
+        den = 2.0 * prob.alpha * nJ * nW
+        gu = np.where(den > 0, 1.0 / np.where(den > 0, den, 1.0), 0.0)
+        Uu = Uu - gu[:, None, None] * gU
+        Wu = schulz_step(Wu, mse_matrices(prob, Uu, V_prev))
+        A = transmit_hessians(prob, Uu, Wu)
+        if t <= Tc:
+            gamma = step_sizes(A)
+        elif step_rule == "bound":
+            if bound is None:
+                bound = step_bound(prob)
+            gamma = np.where(bound > 0, 1.0 / np.where(bound > 0, bound, 1.0), 0.0)
+        grad = gradient_v(prob, Uu, Wu, Vhat, A)
+        V_new = project_spc(prob, Vhat - gamma[prob.cell][:, None, None] * grad)
+        V_prev2, V_prev = V_prev, V_new
+        trace.append(wsr_bits(prob, V_new))
+    return dict(V=V_prev, U=Uu, W=Wu, wsr=trace[-1], trace=np.array(trace), iters=iters)
+
+
+# ---------------------------------------------------------------------------
 # Stationarity and constants (Section VI)
 # ---------------------------------------------------------------------------
 
@@ -557,6 +637,8 @@ def _solve_one(args):
         r = wmmse(prob, V0, **kw)
     elif algo == "mmmse":
         r = mmmse(prob, V0, **kw)
+    elif algo == "bcgd_wmmse":
+        r = bcgd_wmmse(prob, V0, **kw)
     elif algo == "wsr":
         r = dict(wsr=wsr_bits(prob, V0), V=V0)
     else:
