@@ -127,6 +127,19 @@ typedef struct ammse_instance_t {
                                 E^{-1}; eps2 stops after a second-stage iteration.
                                 warm_start = 0 or force_switch_iter as for
                                 Algorithm 3; otherwise as AMMSE_ALGO_WMMSE. */
+#define AMMSE_ALGO_BCGD 3    /* BCGD-WMMSE, the full block-coordinate gradient
+                                method of the Section VII-F ablation: per
+                                iteration U_u takes one gradient step of f (step
+                                1 / (2 alpha_u ||J_u||_F ||W_u||_F), J_u the
+                                receive covariance), W_u one Schulz step
+                                W (2I - E_u W) with E_u the MSE matrix at the new
+                                U_u, and V Algorithm 3's second-stage projected
+                                step (extrapolation, T_c, step_rule, gamma_c as
+                                there); U and W start as the MMSE receivers and
+                                E^{-1} at V^0.  eps2 stops as for Algorithm 3's
+                                second stage; eps1, warm_start, force_switch_iter
+                                are ignored.  FP64 and FP32 storage; the general
+                                kernel only. */
 
 /* Fixed step after the adaptive window (ammse_options_t.step_rule); the
  * paper leaves gamma_c as an input of Algorithm 3 without a value.

@@ -530,7 +530,7 @@ def schulz_step(W: np.ndarray, E: np.ndarray) -> np.ndarray:
 
 
 def bcgd_wmmse(prob: Problem, V0u: np.ndarray, iters: int, Tc: int = 3,
-               extrapolate: bool = True, step_rule: str = "bound") -> dict:
+               extrapolate: bool = True, step_rule: str = "bound", eps2: float = 0.0) -> dict:
     """BCGD-WMMSE, the full block-coordinate gradient method of the ablation
     in Section VII-F: U, W and V each take one explicit step per iteration.
     Readings (the section fixes only the W update):
@@ -544,7 +544,10 @@ def bcgd_wmmse(prob: Problem, V0u: np.ndarray, iters: int, Tc: int = 3,
         (U^t, V^{t-1}) (general definition, Section IV);
       * V step: as Algorithm 3's second stage, at the extrapolated point with
         (U^t, W^t): adaptive step 1/||2 A_c|| for t <= Tc, then 1 / Lhat_c
-        (step_rule "bound") or the last adaptive value ("frozen").
+        (step_rule "bound") or the last adaptive value ("frozen");
+      * eps2 > 0: stop before iteration t >= 2 when the relative WSR change
+        between V^{t-1} and V^{t-2} is <= eps2 (every step is a second-stage
+        step here).
     Returns the final precoders and the WSR trace WSR(V^0..V^T) in bits."""
     if step_rule not in ("bound", "frozen"):
         raise ValueError("step_rule must be 'bound' or 'frozen'")
@@ -555,7 +558,10 @@ def bcgd_wmmse(prob: Problem, V0u: np.ndarray, iters: int, Tc: int = 3,
     trace = [wsr_bits(prob, V_prev)]
     gamma = np.zeros(prob.C)
     bound = None
+    iters_run = 0
     for t in range(1, iters + 1):
+        if eps2 > 0 and t >= 2 and rel_change(trace[t - 1], trace[t - 2]) <= eps2:
+            break
         omega = omega_schedule(t) if extrapolate else 0.0
         Vhat = V_prev + omega * (V_prev - V_prev2) if t >= 2 else V_prev.copy()
         J = rx_covariances(prob, V_prev)
@@ -577,7 +583,8 @@ def bcgd_wmmse(prob: Problem, V0u: np.ndarray, iters: int, Tc: int = 3,
         V_new = project_spc(prob, Vhat - gamma[prob.cell][:, None, None] * grad)
         V_prev2, V_prev = V_prev, V_new
         trace.append(wsr_bits(prob, V_new))
-    return dict(V=V_prev, U=Uu, W=Wu, wsr=trace[-1], trace=np.array(trace), iters=iters)
+        iters_run = t
+    return dict(V=V_prev, U=Uu, W=Wu, wsr=trace[-1], trace=np.array(trace), iters=iters_run)
 
 
 # ---------------------------------------------------------------------------

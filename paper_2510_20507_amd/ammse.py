@@ -28,6 +28,7 @@ PATH_GENERAL = 1
 ALGO_AMMMSE = 0
 ALGO_WMMSE = 1
 ALGO_MMMSE = 2
+ALGO_BCGD = 3
 STEP_BOUND = 0
 STEP_FROZEN = 1
 INST_NONFINITE = 1

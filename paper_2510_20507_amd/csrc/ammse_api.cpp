@@ -52,7 +52,7 @@ ammse_status_t check_options(const ammse_options_t& o) {
   if (o.tile < 0 || o.tile > 3) return AMMSE_ERR_OPTION;
   if (o.step_rule != AMMSE_STEP_BOUND && o.step_rule != AMMSE_STEP_FROZEN) return AMMSE_ERR_OPTION;
   if (o.algorithm != AMMSE_ALGO_AMMMSE && o.algorithm != AMMSE_ALGO_WMMSE &&
-      o.algorithm != AMMSE_ALGO_MMMSE)
+      o.algorithm != AMMSE_ALGO_MMMSE && o.algorithm != AMMSE_ALGO_BCGD)
     return AMMSE_ERR_OPTION;
   if (o.algorithm != AMMSE_ALGO_AMMMSE && o.precision == AMMSE_PREC_BF16)
     return AMMSE_ERR_UNSUPPORTED;
@@ -212,8 +212,9 @@ ammse_status_t ammse_plan_create(ammse_plan_t* plan, int32_t device,
     d.bs_off = t.bs_off;
     d.ws_off = (int64_t)off;
     if (!fast)
-      off += ammse_ws_layout(rb, t.C, t.U, t.M, t.N, t.d, ls, o.algorithm != AMMSE_ALGO_AMMMSE,
-                             o.precision == AMMSE_PREC_BF16)
+      off += ammse_ws_layout(rb, t.C, t.U, t.M, t.N, t.d, ls,
+                             o.algorithm == AMMSE_ALGO_WMMSE || o.algorithm == AMMSE_ALGO_MMMSE,
+                             o.precision == AMMSE_PREC_BF16, o.algorithm == AMMSE_ALGO_BCGD)
                  .total;
   }
 
@@ -240,6 +241,9 @@ ammse_status_t ammse_plan_create(ammse_plan_t* plan, int32_t device,
   P->use_fast = fast ? 1 : 0;
   P->opt = o;
   P->opt.lanczos_steps = ls;
+  // the LDS-resident kernel keeps its state on chip; its workspace holds the
+  // stage-II step bound of each instance (one double per launch position)
+  if (fast) off = ammse_align256(sizeof(double) * (size_t)batch);
   P->ws_bytes = std::max<size_t>(off, 256);
   P->h_desc = desc;
   P->tile_class.resize(batch);

@@ -64,6 +64,15 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
+// Sum over the 16 lanes of each DPP row (every lane of the row receives it).
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp64<0xB1>(v);     // quad_perm [1,0,3,2]
+  v += dpp64<0x4E>(v);     // quad_perm [2,3,0,1]
+  v += dpp64<0x124>(v);    // row_ror 4
+  v += dpp64<0x128>(v);    // row_ror 8
+  return v;
+}
+
 // Sum over the block (a multiple of 64 threads, at most 512); every thread
 // receives the same value.
 __device__ inline double block_sum(double v, double* red) {

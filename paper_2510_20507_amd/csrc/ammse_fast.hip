@@ -31,8 +31,8 @@
 //   J- from registers (reduce-scatter over the 16 lanes of a row group);
 //   Cholesky, U, W per block user; WSR(V^{t-1}) when a test needs it; stage
 //   latch; adaptive step by Lanczos on K = C^H Q C (formed in LDS), after the
-//   adaptive windows of stage II 1/Lhat from the same Lanczos with
-//   C = diag(sqrt(alpha)) (once per solve);
+//   adaptive windows of stage II 1/Lhat (computed before the solve by
+//   ammse_fast_bound_kernel);
 //   Z' = D G^ - Y -> LDS;  P = Q Z' (MFMA);  in the epilogue
 //   G~ = G^ - 2 gamma P, X~ = X^ - 2 gamma Z', the projection norm, and the
 //   projection factor applied to G~, X~ and c.
@@ -79,6 +79,8 @@ struct Shape {
   static_assert(sizeof(double) * 2 * AMMSE_MAX_LANCZOS >= 16 * 64, "tridiagonal pairs");
   static_assert(UN * UN + UN <= BROWS * BLD, "K and the Lanczos vector copy");
 };
+
+using Shape64 = Shape<4, 4, 4>;   // M = 64, U*N = 64, U*d = 64
 
 __device__ __forceinline__ float2 c2(float x, float y) { return make_float2(x, y); }
 
@@ -619,8 +621,9 @@ __device__ __forceinline__ void fast_body(const ammse_kparams_t& p) {
   int switch_iter = stage2 ? 1 : -1;
   bool prev_step_stage2 = false;
   double wsr_prev = 0.0, wsr_prev2 = 0.0, gamma = 0.0;
-  double gbound = 0.0;        // 1 / Lhat, the stage-II step of the bound rule
-  bool have_bound = false;    // computed once per solve, when first needed
+  // 1 / Lhat, the stage-II step of the bound rule, from ammse_fast_bound_kernel
+  // (launched before this kernel on the same stream)
+  const double gbound = p.gbound ? p.gbound[blockIdx.x] : 0.0;
   int iters_run = 0, status = 0;
 
   for (int t = 1; t <= T; ++t) {
@@ -658,19 +661,6 @@ __device__ __forceinline__ void fast_body(const ammse_kparams_t& p) {
                                          t < switch_iter + p.T_c);
     const bool use_bound = stage2 && !adaptive && !(p.gamma_c > 0.0) &&
                            p.step_rule == AMMSE_STEP_BOUND;
-    if (use_bound && !have_bound) {
-      // Lhat / 2 = lambda_max(H^H S diag(alpha) S H) = lambda_max of the same
-      // K = C^H Q C with C = diag(sqrt(alpha)) per block user (C is rewritten
-      // by weights() below)
-      {
-        const int g = tid >> 4, e = tid & 15, a = e >> 2;
-        Cs[g * S::CST + e] = ((e & 3) == a) ? zd{sqrt(alpha[4 * g + a]), 0.0} : zd{0.0, 0.0};
-      }
-      __syncthreads();
-      const double lm = lanczos();
-      gbound = (lm > 0.0) ? 1.0 / (2.0 * lm) : 0.0;
-      have_bound = true;
-    }
     weights(stage2, adaptive);
     if (adaptive) {
       const double lm = lanczos();
@@ -872,6 +862,80 @@ __device__ __forceinline__ void fast_body(const ammse_kparams_t& p) {
   }
 }
 
+// Stage-II step of the bound rule for the instances of the LDS-resident
+// kernel: gb[k] = 1 / (2 lambda_max(H^H S_a^2 H)) for the instance at launch
+// position k, S_a = diag(sqrt(alpha_u) / sigma_u) over the rows of H
+// (M = U N = 64).  One wave per instance, H staged in LDS; plain three-term
+// Lanczos on the antenna-side operator x -> H^H S_a^2 H x with lane i holding
+// entry i of the vectors (double), start vector, step limit and stopping rule
+// as the step-size Lanczos of the solve kernels (relative 1e-8 between checks
+// from step 12 on every second step).  The operator depends only on the
+// channel, so the value is computed once per solve, at an occupancy of
+// several instances per CU, instead of serially inside the solve.
+__global__ __launch_bounds__(64) void ammse_fast_bound_kernel(ammse_kparams_t p, double* gb) {
+  constexpr int M = Shape64::M, UN = Shape64::UN, LD = M + 1;
+  __shared__ float2 Hs[UN * LD];
+  __shared__ double2 xs[M];       // broadcast of the vector being multiplied
+  __shared__ double2 tp[64];      // tridiagonal pairs of the Ritz-value search
+  const ammse_desc_t D = p.desc[blockIdx.x];
+  const int lane = threadIdx.x;
+  const float2* Hg = (const float2*)p.H + D.h_off;
+  for (int e = lane; e < UN * M; e += 64) Hs[(e / M) * LD + (e % M)] = Hg[e];
+  const int u = lane / D.N;
+  const double sa = sqrt(p.alpha[D.user_off + u] / p.sigma2[D.user_off + u]);
+  const double s2 = sa * sa;
+  zd x = {1.0 + 0.5 * sin(0.731 * lane + 0.25), 0.3 * cos(1.37 * lane + 0.5)};
+  x = scal(1.0 / sqrt(wave_sum(nrm2(x))), x);
+  zd pp = {0.0, 0.0};
+  const int m = max(1, min(p.lanczos_steps, M));
+  const double ltol = 1e-8;
+  double ta = 0.0, tb = 0.0, beta_prev = 0.0, tmax = 0.0, theta = 0.0;
+  for (int j = 0;; ++j) {
+    // y_r = s_r^2 (H x)_r  (lane r), then w_i = (H^H y)_i  (lane i)
+    __syncthreads();
+    xs[lane] = make_double2(x.x, x.y);
+    __syncthreads();
+    zd y = {0.0, 0.0};
+    for (int k = 0; k < M; ++k) {
+      const float2 h = Hs[lane * LD + k];
+      const double2 xv = xs[k];
+      y = y + zd{(double)h.x, (double)h.y} * zd{xv.x, xv.y};
+    }
+    y = scal(s2, y);
+    __syncthreads();
+    xs[lane] = make_double2(y.x, y.y);
+    __syncthreads();
+    zd w = {0.0, 0.0};
+    for (int r = 0; r < UN; ++r) {
+      const float2 h = Hs[r * LD + lane];
+      const double2 yv = xs[r];
+      w = w + zd{(double)h.x, -(double)h.y} * zd{yv.x, yv.y};
+    }
+    double al = x.x * w.x + x.y * w.y, yy = nrm2(w), py = pp.x * w.x + pp.y * w.y;
+    wave_sum3_dpp(al, yy, py);
+    const double bb = sqrt(fmax(yy - al * al - 2.0 * beta_prev * py + beta_prev * beta_prev, 0.0));
+    if (lane == j) {
+      ta = al;
+      tb = bb;
+    }
+    const int msz = j + 1;
+    tmax = fmax(tmax, fabs(al) + bb);
+    const bool breakdown = !(bb > 1e-13 * tmax);
+    bool stop = breakdown || msz == m;
+    if (breakdown || (msz >= 12 && (msz % 2) == 0) || msz == m) {
+      bool conv = false;
+      theta = (tmax > 0.0) ? wave_tridiag_lmax(ta, tb, msz, tmax, theta, ltol, tp, &conv) : 0.0;
+      stop = stop || conv;
+    }
+    if (stop) break;
+    const zd xn = scal(1.0 / bb, w - scal(al, x) - scal(beta_prev, pp));
+    pp = x;
+    x = xn;
+    beta_prev = bb;
+  }
+  if (lane == 0) gb[blockIdx.x] = (theta > 0.0) ? 1.0 / (2.0 * theta) : 0.0;
+}
+
 template <class S>
 __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   const int N = p.desc[blockIdx.x].N;   // uniform over the workgroup
@@ -880,7 +944,6 @@ __global__ __launch_bounds__(256, 1) void ammse_fast_kernel(ammse_kparams_t p) {
   else fast_body<S, 0>(p);
 }
 
-using Shape64 = Shape<4, 4, 4>;   // M = 64, U*N = 64, U*d = 64
 
 }  // namespace
 
@@ -901,6 +964,14 @@ hipError_t ammse_launch_fast_fp32(const ammse_kparams_t& p, hipStream_t s) {
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(ammse_fast_kernel<Shape64>, dim3(p.batch), dim3(256), Shape64::bytes, s, p);
+  ammse_kparams_t q = p;
+  q.gbound = nullptr;
+  if (!p.wsr_only && p.step_rule == AMMSE_STEP_BOUND && !(p.gamma_c > 0.0) &&
+      p.max_iters > p.T_c) {
+    // the stage-II step bound, one double per launch position in the workspace
+    q.gbound = (double*)p.ws;
+    hipLaunchKernelGGL(ammse_fast_bound_kernel, dim3(p.batch), dim3(64), 0, s, p, q.gbound);
+  }
+  hipLaunchKernelGGL(ammse_fast_kernel<Shape64>, dim3(p.batch), dim3(256), Shape64::bytes, s, q);
   return hipGetLastError();
 }

@@ -38,6 +38,9 @@ struct ammse_ws_layout_t {
   size_t X1, X2, G0;          // Q recursion (single cell, U N <= M, float products): the
                               // implicit precoder's X^{t-1}, X^{t-2} and G^0 ((U N) x (U d),
                               // storage precision)
+  size_t Ubm, Wbm, Jbm, Fbm;  // BCGD-WMMSE: per-user U and W iterates, receive covariance J
+                              // and own-stream image G_own of the current V (double complex
+                              // 4 x 4 blocks)
   size_t total;
 };
 
@@ -76,6 +79,7 @@ struct ammse_kparams_t {
   int32_t tile_force;    // 0: per-instance tile shape from the descriptor; v + 1: shape v
   int32_t step_rule;     // AMMSE_STEP_BOUND / AMMSE_STEP_FROZEN
   double eps1, eps2, gamma_c;
+  double* gbound;        // LDS-resident kernel: 1 / Lhat per launch position (bound rule)
 };
 
 #define AMMSE_BLOCK 256
@@ -102,7 +106,8 @@ __host__ __device__ inline bool ammse_gram_path(int real_bytes, int C, int U, in
 
 __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int C, int U, int M,
                                                              int N, int d, int lanczos_steps,
-                                                             bool wmmse, bool bf16 = false) {
+                                                             bool wmmse, bool bf16 = false,
+                                                             bool bcgd = false) {
   const size_t cs = 2 * (size_t)real_bytes;      // storage complex
   const size_t zs = 16;                          // double complex
   const size_t un = (size_t)U * N, ud = (size_t)U * d;
@@ -116,7 +121,7 @@ __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int
   L.Em = o;  o += ammse_align256((size_t)U * 16 * zs);
   L.Dm = o;  o += ammse_align256((size_t)U * 16 * zs);
   L.Ym = o;  o += ammse_align256((size_t)U * 16 * zs);
-  const size_t gp = ammse_gram_path(real_bytes, C, U, M, N, d, wmmse) ? 1 : 0;
+  const size_t gp = ammse_gram_path(real_bytes, C, U, M, N, d, wmmse || bcgd) ? 1 : 0;
   const size_t nl = (gp && ud > (size_t)M) ? ud : (size_t)M;   // Lanczos order (at most)
   L.Lq = o;  o += ammse_align256((size_t)3 * nl * zs);   // three Lanczos vectors
   L.Lw = o;  o += ammse_align256((size_t)M * zs);
@@ -129,7 +134,7 @@ __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int
   L.Xm = o;  o += ammse_align256(w * (size_t)M * ud * zs);
   L.Tm = o;  o += ammse_align256(w * un * (size_t)M * zs);
   // Algorithm 3, single cell with U N <= M: Lanczos on Q = S H H^H S
-  const size_t qp = (!wmmse && C == 1 && un <= (size_t)M) ? 1 : 0;
+  const size_t qp = (!wmmse && !bcgd && C == 1 && un <= (size_t)M) ? 1 : 0;
   L.Qm = o;  o += ammse_align256(qp * un * un * cs);
   // Algorithm 3 otherwise, float storage, when the (U d) x (U d) Gram matrix
   // is smaller than two passes over H_{:,c}: Lanczos on K = R R^H (gp above)
@@ -154,6 +159,11 @@ __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int
   const size_t fz = (real_bytes == 4) ? 8 : 0;
   L.Dmf = o; o += ammse_align256((size_t)U * 16 * fz);
   L.Ymf = o; o += ammse_align256((size_t)U * 16 * fz);
+  const size_t bc = bcgd ? 1 : 0;
+  L.Ubm = o; o += ammse_align256(bc * (size_t)U * 16 * zs);
+  L.Wbm = o; o += ammse_align256(bc * (size_t)U * 16 * zs);
+  L.Jbm = o; o += ammse_align256(bc * (size_t)U * 16 * zs);
+  L.Fbm = o; o += ammse_align256(bc * (size_t)U * 16 * zs);
   L.total = o;
   return L;
 }

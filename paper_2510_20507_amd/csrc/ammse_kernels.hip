@@ -218,16 +218,18 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   }
   __syncthreads();
 
-  const bool wm = p.algorithm != AMMSE_ALGO_AMMMSE;   // exact V step (Algorithm 2 / MMMSE)
-  const bool qpath = C == 1 && un <= M && !wm;   // stream-space Lanczos with Q = S H H^H S
-  const bool gpath = ammse_gram_path((int)sizeof(R), C, U, M, N, d, wm);   // ... with K = R R^H
+  // exact V step (Algorithm 2 / MMMSE); BCGD-WMMSE (explicit steps for U, W, V)
+  const bool wm = p.algorithm == AMMSE_ALGO_WMMSE || p.algorithm == AMMSE_ALGO_MMMSE;
+  const bool bc = p.algorithm == AMMSE_ALGO_BCGD;
+  const bool qpath = C == 1 && un <= M && !wm && !bc;   // stream-space Lanczos with Q = S H H^H S
+  const bool gpath = ammse_gram_path((int)sizeof(R), C, U, M, N, d, wm || bc);   // ... K = R R^H
   // float products on the Q path: one product with Q per iteration, the
   // precoder carried implicitly as V = c V^0 + H^H S X (see the update below).
   // Not with bfloat16 products: the projection norm would then come from a
   // bfloat16 product and the iterates would leave the power sphere by ~1e-3.
   const bool rpath = qpath && sizeof(R) == 4 && p.lowp_iters <= 0;
   const ammse_ws_layout_t L =
-      ammse_ws_layout((int)sizeof(R), C, U, M, N, d, p.lanczos_steps, wm, p.bf16_copies != 0);
+      ammse_ws_layout((int)sizeof(R), C, U, M, N, d, p.lanczos_steps, wm, p.bf16_copies != 0, bc);
   char* ws = p.ws + D.ws_off;
   cx<R>* Gp = (cx<R>*)(ws + L.Gp);
   cx<R>* Gq = (cx<R>*)(ws + L.Gq);
@@ -258,6 +260,10 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   zd* Cm = (zd*)(ws + L.Cm);
   cx<R>* Rg = (cx<R>*)(ws + L.Rg);
   cx<R>* Kg = (cx<R>*)(ws + L.Kg);
+  zd* Ubm = (zd*)(ws + L.Ubm);       // BCGD-WMMSE: U, W iterates, J and G_own of V^{t-1}
+  zd* Wbm = (zd*)(ws + L.Wbm);
+  zd* Jbm = (zd*)(ws + L.Jbm);
+  zd* Fbm = (zd*)(ws + L.Fbm);
   cx<R>* X1 = (cx<R>*)(ws + L.X1);   // Q recursion: X^{t-1}, X^{t-2}, G^0
   cx<R>* X2 = (cx<R>*)(ws + L.X2);
   cx<R>* G0 = (cx<R>*)(ws + L.G0);
@@ -298,7 +304,9 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   //   UW = J-^{-1} G_own, E = Lw^{-H} Lw^{-1}
   // UW and E go to the workspace; returns the sum of alpha_u R_u (nats) over
   // the block.
-  auto receivers = [&](const cx<R>* G, double gscale) -> double {
+  // BCGD-WMMSE: the full J and G_own go to the workspace as well, and with
+  // bc_init the MMSE weights W = I + F^H F (zero outside d x d).
+  auto receivers = [&](const cx<R>* G, double gscale, bool bc_init = false) -> double {
     const int tid = phase_tid();
     const int lane = tid & 63, li = lane & 15;
     const Lane4 L4{lane & ~15, li >> 2, li & 3};
@@ -350,11 +358,17 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
         const int c = cown, nc = sm.cu[c] * d;
         F = scal(gscale, to_d(G[(long)un * sm.colOff[c] + (long)(uu * N + ea) * nc + j0 + eb]));
       }
+      if (bc && act) {                            // J = J- + G_own G_own^H
+        Jbm[u * 16 + li] = J + mm_nh(L4, F, F);
+        Fbm[u * 16 + li] = F;
+      }
       bool oku = true;
       double io[4], iw[4];                        // reciprocal diagonals of the factors
       const zd Lo = chol16(L4, J, oku, io);
       F = trsm16(L4, Lo, io, F);                  // L^{-1} G_own
       zd X = mm_hn(L4, F, F);                     // I + F^H F
+      if (bc_init && act)
+        Wbm[u * 16 + li] = (ea == eb && ea < d) ? zd{X.x + 1.0, 0.0} : X;
       if (ea == eb) X = {X.x + 1.0, 0.0};
       const zd UWv = trsm16h(L4, Lo, io, F);      // J-^{-1} G_own
       const zd Lw = chol16(L4, X, oku, iw);
@@ -404,6 +418,57 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       if (wm || qpath || gpath) {   // D = C C^H: C = sqrt(alpha) UW Lw^{-H} (stage II) or sqrt(alpha) U (stage I)
         const zd Cv = scal(sqrt(al), stage2 ? mm_nh(L4, UWv, Lim[uu * 16 + li]) : T);
         if (act) Cm[u * 16 + li] = Cv;
+      }
+    }
+    __syncthreads();
+  };
+
+  // BCGD-WMMSE (Section VII-F ablation), per user on the normalised channel
+  // (unit noise): U <- U - (J U W - G_own W) / (||J||_F ||W||_F) (one gradient
+  // step of f in U, the step bounding the block Lipschitz constant), then
+  // E = I - U^H G_own - G_own^H U + U^H J U at the new U and the Schulz step
+  // W <- W (2I - E W); D = alpha U W U^H and Y = alpha U W for the V step.
+  // init: U and W start as the MMSE receivers (U W E, U W from the receivers)
+  // and W = E^{-1}.  Blocks are zero outside N x d and d x d.
+  auto bcgd_update = [&](bool init) {
+    const int tid = phase_tid();
+    const int lane = tid & 63, li = lane & 15;
+    const Lane4 L4{lane & ~15, li >> 2, li & 3};
+    const int ea = L4.a, eb = L4.b;
+    const bool inN = ea < N && eb < N, inD = ea < d && eb < d;
+    for (int u0 = 0; u0 < U; u0 += AMMSE_BLOCK / 16) {
+      const int u = u0 + (tid >> 4);
+      const bool act = u < U;
+      const int uu = act ? u : U - 1;
+      const zd J = Jbm[uu * 16 + li], G = Fbm[uu * 16 + li];
+      const zd Ub = init ? mm_nn(L4, UWm[uu * 16 + li], Em[uu * 16 + li]) : Ubm[uu * 16 + li];
+      const zd Wb = Wbm[uu * 16 + li];
+      const zd Rg = mm_nn(L4, mm_nn(L4, J, Ub), Wb) - mm_nn(L4, G, Wb);
+      const double nj = row16_sum(inN ? nrm2(J) : 0.0), nw = row16_sum(inD ? nrm2(Wb) : 0.0);
+      const double al = sm.alpha[uu];
+      const double st = (al > 0.0 && nj * nw > 0.0) ? 1.0 / sqrt(nj * nw) : 0.0;
+      const zd Un = Ub - scal(st, Rg);
+      const zd UhG = mm_hn(L4, Un, G);
+      zd Eb = mm_hn(L4, Un, mm_nn(L4, J, Un)) - UhG - cj(L4.at(UhG, eb, ea));
+      if (ea == eb && ea < d) Eb.x += 1.0;
+      zd T2 = scal(-1.0, mm_nn(L4, Eb, Wb));
+      if (ea == eb && ea < d) T2.x += 2.0;
+      zd Wn = mm_nn(L4, Wb, T2);
+      const zd Wt = L4.at(Wn, eb, ea);
+      Wn = {0.5 * (Wn.x + Wt.x), 0.5 * (Wn.y - Wt.y)};   // Hermitian part
+      const zd UWn = mm_nn(L4, Un, Wn);
+      zd Dv = mm_nh(L4, UWn, Un);
+      const zd Dt = L4.at(Dv, eb, ea);
+      Dv = {0.5 * (Dv.x + Dt.x), 0.5 * (Dv.y - Dt.y)};
+      if (act) {
+        Ubm[u * 16 + li] = Un;
+        Wbm[u * 16 + li] = Wn;
+        Dm[u * 16 + li] = scal(al, Dv);
+        Ym[u * 16 + li] = scal(al, UWn);
+        if constexpr (sizeof(R) == 4) {
+          Dmf[u * 16 + li] = from_d<float>(scal(al, Dv));
+          Ymf[u * 16 + li] = from_d<float>(scal(al, UWn));
+        }
       }
     }
     __syncthreads();
@@ -1035,7 +1100,8 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
 
   int fsw = p.force_switch_iter;
   if (p.force_switch && p.force_switch[b] > 0) fsw = p.force_switch[b];
-  bool stage2 = p.algorithm == AMMSE_ALGO_WMMSE || ((fsw >= 1) ? (fsw <= 1) : (p.warm_start == 0));
+  bool stage2 = p.algorithm == AMMSE_ALGO_WMMSE || bc ||
+                ((fsw >= 1) ? (fsw <= 1) : (p.warm_start == 0));
   int switch_iter = stage2 ? 1 : -1;
   bool prev_step_stage2 = false;
   double wsr_prev = 0.0, wsr_prev2 = 0.0;   // WSR(V^{t-1}), WSR(V^{t-2})
@@ -1052,7 +1118,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       __syncthreads();
     }
     // receivers and rate of V^{t-1}
-    const double rs = receivers(Gp, gsp);
+    const double rs = receivers(Gp, gsp, bc && t == 1);
     wsr_prev2 = wsr_prev;
     wsr_prev = wsr_sum(rs);
     if (p.trace) {
@@ -1096,7 +1162,8 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       }
       have_bound = true;
     }
-    weights(stage2);
+    if (bc) bcgd_update(t == 1);
+    else weights(stage2);
 
     if (wm) {   // Algorithm 2 / MMMSE: exact V minimiser, then G^t
       wmmse_step(stage2);
@@ -1400,8 +1467,9 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
 size_t ammse_general_lds_bytes(int precision, int algorithm) {
   const bool f64 = precision == AMMSE_PREC_FP64;
   const size_t st = f64 ? sizeof(Smem<double>) : sizeof(Smem<float>);
-  const size_t dyn = (algorithm != AMMSE_ALGO_AMMMSE) ? sizeof(zd) * 64 * 64 * (f64 ? 1 : 2)
-                                                      : sizeof(zd) * 3 * AMMSE_LANCZOS_LDS_N;
+  const bool exact_v = algorithm == AMMSE_ALGO_WMMSE || algorithm == AMMSE_ALGO_MMMSE;
+  const size_t dyn = exact_v ? sizeof(zd) * 64 * 64 * (f64 ? 1 : 2)
+                             : sizeof(zd) * 3 * AMMSE_LANCZOS_LDS_N;
   return st + dyn;
 }
 
@@ -1413,7 +1481,7 @@ hipError_t launch_general(const ammse_kparams_t& p0, hipStream_t s) {
   ammse_kparams_t p = p0;
   // A-MMMSE: the Lanczos vectors (order <= AMMSE_LANCZOS_LDS_N)
   size_t dyn = sizeof(zd) * 3 * AMMSE_LANCZOS_LDS_N;
-  if (p.algorithm != AMMSE_ALGO_AMMMSE) {
+  if (p.algorithm == AMMSE_ALGO_WMMSE || p.algorithm == AMMSE_ALGO_MMMSE) {
     static bool attr_set = false;
     // FP32: factor and solution block (128 KiB); FP64 (larger static tiles): factor only
     dyn = sizeof(zd) * 64 * 64 * (sizeof(R) == 4 ? 2 : 1);

@@ -99,8 +99,8 @@ def test_validate_rejects_overlapping_precoders(L):
 @pytest.mark.parametrize("opt", [
     dict(precision=7), dict(max_iters=-1), dict(T_c=-1), dict(lanczos_steps=65),
     dict(force_switch_iter=0), dict(eps1=-0.1), dict(T_c=0), dict(eps2=float("nan")),
-    dict(path=2), dict(refine_iters=-1), dict(precision=3), dict(algorithm=3),
-    dict(tile=4), dict(tile=-1), dict(step_rule=2), dict(step_rule=-1),
+    dict(path=2), dict(refine_iters=-1), dict(precision=3),
+    dict(tile=4), dict(tile=-1), dict(step_rule=2), dict(step_rule=-1), dict(algorithm=4),
 ])
 def test_validate_rejects_bad_options(L, opt):
     table, cu = _one()
@@ -109,11 +109,11 @@ def test_validate_rejects_bad_options(L, opt):
     assert e.value.code == 3
 
 
-def test_wmmse_in_bfloat16_is_unsupported(L):
+@pytest.mark.parametrize("algo", [ammse.ALGO_WMMSE, ammse.ALGO_MMMSE, ammse.ALGO_BCGD])
+def test_other_algorithms_in_bfloat16_are_unsupported(L, algo):
     table, cu = _one()
     with pytest.raises(ammse.AmmseError) as e:
-        ammse.validate(table, cu, ammse.Options(algorithm=ammse.ALGO_WMMSE,
-                                                precision=ammse.PREC_BF16))
+        ammse.validate(table, cu, ammse.Options(algorithm=algo, precision=ammse.PREC_BF16))
     assert e.value.code == 6
 
 

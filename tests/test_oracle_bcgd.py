@@ -126,3 +126,18 @@ def test_default_rule_matches_ammmse_v_step_on_exact_blocks():
     a = O.ammmse(prob, V0, 1, warm_start=False)
     b = O.bcgd_wmmse(prob, V0, 1)
     np.testing.assert_allclose(b["V"], a["V"], rtol=1e-10, atol=1e-12)
+
+
+def test_eps2_stop_rule():
+    """eps2 > 0 ends the run before the first t >= 2 whose relative WSR change
+    between V^{t-1} and V^{t-2} is <= eps2; the run up to there is the run
+    without a stop test."""
+    inst = random_instance(46, M=8, cell_users=[3], N=2, d=2, P=10.0)
+    prob, V0 = _prob(inst)
+    full = O.bcgd_wmmse(prob, V0, 80)
+    tr = full["trace"]
+    for eps2 in (1e-2, 1e-4):
+        r = O.bcgd_wmmse(prob, V0, 80, eps2=eps2)
+        cand = [t for t in range(2, 81) if O.rel_change(tr[t - 1], tr[t - 2]) <= eps2]
+        assert cand and r["iters"] == cand[0] - 1
+        np.testing.assert_array_equal(r["trace"], tr[:r["iters"] + 1])
