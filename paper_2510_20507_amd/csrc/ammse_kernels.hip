@@ -223,11 +223,11 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   const bool bc = p.algorithm == AMMSE_ALGO_BCGD;
   const bool qpath = C == 1 && un <= M && !wm && !bc;   // stream-space Lanczos with Q = S H H^H S
   const bool gpath = ammse_gram_path((int)sizeof(R), C, U, M, N, d, wm || bc);   // ... K = R R^H
-  // float products on the Q path: one product with Q per iteration, the
-  // precoder carried implicitly as V = c V^0 + H^H S X (see the update below).
-  // Not with bfloat16 products: the projection norm would then come from a
-  // bfloat16 product and the iterates would leave the power sphere by ~1e-3.
-  const bool rpath = qpath && sizeof(R) == 4 && p.lowp_iters <= 0;
+  // float storage on the Q path: one product with Q per iteration, the
+  // precoder carried implicitly as V = c V^0 + H^H S X (see the update below);
+  // in bfloat16 iterations that product takes bfloat16 operands, and the
+  // refinement pass starts from G^{t-1}, G^{t-2} recomputed with float products.
+  const bool rpath = qpath && sizeof(R) == 4;
   const ammse_ws_layout_t L =
       ammse_ws_layout((int)sizeof(R), C, U, M, N, d, p.lanczos_steps, wm, p.bf16_copies != 0, bc);
   char* ws = p.ws + D.ws_off;
@@ -254,7 +254,10 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   bfc* Hb = (bfc*)(ws + L.Hb);     // bfloat16 operand copies (mixed precision)
   bfc* Xb = (bfc*)(ws + L.Xb);
   bfc* Zb = (bfc*)(ws + L.Zb);
-  const bool copies = sizeof(R) == 4 && p.bf16_copies && p.lowp_iters >= 1 && !p.wsr_only;
+  // bfloat16 copies of H, the precoder and Z for the two-product form (the Q
+  // path converts its operands while staging them)
+  const bool copies = sizeof(R) == 4 && p.bf16_copies && p.lowp_iters >= 1 && !p.wsr_only &&
+                      !rpath;
   zd* Lwm = (zd*)(ws + L.Lwm);
   zd* Lim = (zd*)(ws + L.Lim);
   zd* Cm = (zd*)(ws + L.Cm);
@@ -1070,7 +1073,9 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       __syncthreads();
     }
   }
-  channel_product(Gp, Xc, sm.scur, p.lowp_iters >= 1);
+  // G^0 (on the Q path it enters every iteration's G and projection norm, so it
+  // is formed with float products there)
+  channel_product(Gp, Xc, sm.scur, p.lowp_iters >= 1 && !rpath);
   __syncthreads();
   const int T = p.wsr_only ? 0 : p.max_iters;
   // Q recursion state: V^t = c_t V^0 + H^H S (xs_t X_t), G buffers carry
@@ -1113,8 +1118,28 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     const bool lowp = t <= p.lowp_iters;   // bfloat16 products in this iteration
     if (p.lowp_iters >= 1 && t == p.lowp_iters + 1) {
       // refinement pass: G^{t-1} and G^{t-2} again with float products
-      channel_product(Gp, Xc, sm.scur, false);
-      channel_product(Gq, Xp, sm.sprev, false);
+      if (rpath) {   // G^{t-k} = c_{t-k} G^0 + Q (xs_k X_k), k = 1, 2 (scales folded in)
+        const int ud = D.ud;
+        channel_gemm<R, false>(un, ud, un, Qm, un, X1, ud, sm.tiles, false, tile,
+                               [&](int i, int j, cx<R> pq) {
+                                 const long e = (long)i * ud + j;
+                                 const cx<R> g0 = G0[e];
+                                 Gp[e] = from_d<R>(zd{c1 * (double)g0.x + xs1 * (double)pq.x,
+                                                      c1 * (double)g0.y + xs1 * (double)pq.y});
+                               });
+        channel_gemm<R, false>(un, ud, un, Qm, un, X2, ud, sm.tiles, false, tile,
+                               [&](int i, int j, cx<R> pq) {
+                                 const long e = (long)i * ud + j;
+                                 const cx<R> g0 = G0[e];
+                                 Gq[e] = from_d<R>(zd{c2 * (double)g0.x + xs2 * (double)pq.x,
+                                                      c2 * (double)g0.y + xs2 * (double)pq.y});
+                               });
+        gsp = 1.0;
+        gsq = 1.0;
+      } else {
+        channel_product(Gp, Xc, sm.scur, false);
+        channel_product(Gq, Xp, sm.sprev, false);
+      }
       __syncthreads();
     }
     // receivers and rate of V^{t-1}
@@ -1301,7 +1326,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
                ((double)x.x * pq.x + (double)x.y * pq.y);
         Gq[e] = from_d<R>(zd{ch * (double)g0.x + (double)pq.x, ch * (double)g0.y + (double)pq.y});
       };
-      channel_gemm<R, false>(un, ud, un, Qm, un, X2, ud, sm.tiles, false, tile, epi);
+      channel_gemm<R, false>(un, ud, un, Qm, un, X2, ud, sm.tiles, lowp, tile, epi);
       const double pw = ch * ch * nu + block_sum(acc, sm.red);
       const double sc = (pw > sm.Pc[0]) ? sqrt(sm.Pc[0] / pw) : 1.0;
       cx<R>* tg = Gq;
