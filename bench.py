@@ -11,9 +11,12 @@ inputs.
 Metric: instances per second whose final WSR reaches 99 % of the FP64 WMMSE
 reference WSR of the same instance (stored by tests/golden/make_wmmse_reference.py
 from the CPU oracle).  Printed as one JSON line, with the roofline of the solve
-kernel (HIP events on the launch stream), the same count for the plain
-per-instance form (one launch per instance) on the same GPU, and the CPU
-oracle timed on a bounded sample.
+(HIP events on the launch stream), the same count for the plain per-instance
+form (one launch per instance) on the same GPU, the CPU oracle timed on a
+bounded sample, and further legs: the M = 256 batch in float and mixed
+precision, GPU WMMSE, the unrolled solver, the eps2 stop, the single FP64
+instance, and the seven-cell 4096-instance batch (its own count on a stored
+512-instance reference sample and its HBM roofline).
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2]
     python bench.py --parse-pmc DIR_FETCH DIR_WRITE   # HBM traffic from rocprofv3 --pmc
@@ -34,12 +37,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 REF_FILE = os.path.join(ROOT, "tests", "golden", "wmmse_ref_rayleigh_sweep4x256.json")
+HEX_REF_FILE = os.path.join(ROOT, "tests", "golden", "oracle_ref_hexcell7_b4096.json")
 LARGE_REF_FILE = os.path.join(ROOT, "tests", "golden", "oracle_ref_rayleigh_m256u64n2d2_b512.json")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ammse_solve_fp32_rayleigh_sweep1024_traffic.txt")
+HEX_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ammse_general_fp32_hexcell4096_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2510_20507_amd", "csrc", f)
                   for f in ("ammse_fast.hip", "ammse_kernels.hip", "ammse_device.h",
                             "ammse_internal.h", "ammse_gemm.h")]
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
 ITERS = 100
 CALIB_COPY_MIB = 1024
 
@@ -52,13 +58,14 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def read_traffic(path=None):
+    """HBM bytes per launch from a committed counter summary, if it was taken
+    on the current kernel source."""
+    path = path or TRAFFIC_FILE
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
@@ -175,6 +182,119 @@ def mixed_precision(reps: int = 2):
         plan.close()
     out["speedup_bf16_refined_vs_fp32"] = out["fp32"]["kernel_ms"] / out["bf16_refined"]["kernel_ms"]
     return out
+
+
+def hexcell_leg(reps: int = 3, cpu: bool = True, wmmse: bool = False):
+    """The seven-cell uneven batch: 4096 instances (7 cells, 2..12 users per
+    cell, M in {16,32,64,128}, N in {1,2,4}, d = min(N,2), path loss and
+    shadowing), FP32, 100 iterations, one persistent launch with the
+    autotuned tile shapes.  The stored FP64 WMMSE reference covers a fixed
+    512-instance sample (every 8th instance); instances reaching 99 % of it are
+    counted on that sample and scaled to the batch.  Roofline: HBM, the method
+    streaming H twice per iteration (both channel products) at 8 bytes per
+    complex entry.  Beside it the CPU oracle's A-MMMSE on a bounded part of the
+    sample and, with `wmmse` (about a minute of GPU time), GPU WMMSE (Algorithm
+    2, same stop rule as the reference) on the 512 sampled instances."""
+    import torch
+    from paper_2510_20507_amd import ammse, synth
+    if not os.path.exists(HEX_REF_FILE):
+        return None
+    with open(HEX_REF_FILE) as f:
+        refj = json.load(f)
+    if "wmmse" not in refj:
+        return None
+    batch = synth.hexcell_batch(4096)
+    assert refj["workload"] == batch.name
+    idx = np.asarray(refj["index"])
+    wref = np.asarray(refj["wmmse"]["wsr"])
+    opts = ammse.Options(precision=ammse.PREC_FP32, max_iters=ITERS)
+    db = ammse.to_device(batch, opts.precision)
+    plan = ammse.Plan(db.table, db.cell_users, opts)
+    ws = plan.workspace()
+    V = torch.empty_like(db.V0)
+    wsr = torch.empty(batch.batch, dtype=torch.float64, device="cuda")
+    st = torch.empty(batch.batch, dtype=torch.int32, device="cuda")
+    choice = plan.autotune(db.H, db.sigma2, db.alpha, db.P, db.V0, workspace=ws)
+    V.copy_(db.V0)
+    plan.solve(db.H, db.sigma2, db.alpha, db.P, V, wsr, None, None, st, workspace=ws)
+    ms = []
+    for _ in range(reps):
+        V.copy_(db.V0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.solve(db.H, db.sigma2, db.alpha, db.P, V, wsr, None, None, st, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    plan.close()
+    t = float(np.mean(ms))
+    w = wsr.cpu().numpy()
+    s = st.cpu().numpy()
+    ok = int(((w[idx] >= 0.99 * wref) & (s[idx] == 0)).sum())
+    ratio = w[idx] / wref
+    flops = float(batch.total_flops_per_iter().sum()) * ITERS
+    h_bytes = float(batch.H.size) * 8.0
+    alg_bytes = 2.0 * ITERS * h_bytes
+    out = {"workload": batch.name, "instances": batch.batch, "iters": ITERS, "precision": "fp32",
+           "autotuned_tile_shapes": choice, "kernel_ms": t,
+           "reached_99_sample": ok, "sample": int(idx.size),
+           "instances_per_s_reached_99": ok / idx.size * batch.batch / (t / 1e3),
+           "wsr_ratio_to_wmmse_sample": {"mean": float(ratio.mean()), "min": float(ratio.min()),
+                                         "max": float(ratio.max())},
+           "status_nonzero": int((s != 0).sum()),
+           "roofline": {"bound": "hbm", "achieved": alg_bytes / (t / 1e3) / 1e9,
+                        "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": alg_bytes / (t / 1e3) / 1e9 / PEAK_HBM_GBS,
+                        "traffic": read_traffic(HEX_TRAFFIC_FILE), "algorithmic_bytes": alg_bytes,
+                        "algorithmic_tflops": flops / (t / 1e3) / 1e12,
+                        "kernel": "ammse_solve_kernel<float> (general)"}}
+    if wmmse:   # GPU WMMSE on the sampled instances (the reference's algorithm)
+        out["gpu_wmmse_sample"] = hexcell_wmmse(batch.subset(idx), wref)
+    if cpu:
+        import oracle as O
+        workers = max(1, min(16, os.cpu_count() or 1))
+        n = 4 * workers
+        insts = [batch.instance(int(i)) for i in idx[:n]]
+        t0 = time.perf_counter()
+        res = O.solve_batch(insts, "ammmse", workers=workers, iters=ITERS)
+        dt = time.perf_counter() - t0
+        okc = sum(1 for r, x in zip(res, wref[:n]) if r["wsr"] >= 0.99 * x)
+        out["cpu_baseline"] = {"value": okc / dt, "unit": "instances/s", "cores": workers,
+                               "kind": "oracle", "reached_99": okc, "seconds": dt,
+                               "sample": f"the first {n} of the 512 sampled instances, "
+                                         f"{ITERS} iterations, FP64 NumPy, process pool of "
+                                         f"{workers}"}
+    return out
+
+
+def hexcell_wmmse(sub, wref):
+    """GPU WMMSE (Algorithm 2, FP32 products, double M x M solves, stop at
+    relative WSR change 1e-6 or 500 iterations) on the sampled seven-cell
+    instances: time and instances reaching 99 % of the FP64 reference."""
+    import torch
+    from paper_2510_20507_amd import ammse
+    wo = ammse.Options(precision=ammse.PREC_FP32, algorithm=ammse.ALGO_WMMSE, max_iters=500,
+                       eps2=1e-6)
+    sdb = ammse.to_device(sub, wo.precision)
+    wplan = ammse.Plan(sdb.table, sdb.cell_users, wo)
+    wws = wplan.workspace()
+    V2 = sdb.V0.clone()
+    w2 = torch.empty(sub.batch, dtype=torch.float64, device="cuda")
+    s2 = torch.empty(sub.batch, dtype=torch.int32, device="cuda")
+    it2 = torch.empty(sub.batch, dtype=torch.int32, device="cuda")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    wplan.solve(sdb.H, sdb.sigma2, sdb.alpha, sdb.P, V2, w2, it2, None, s2, workspace=wws)
+    e1.record()
+    torch.cuda.synchronize()
+    tw = e0.elapsed_time(e1)
+    okw = int(((w2.cpu().numpy() >= 0.99 * wref) & (s2.cpu().numpy() == 0)).sum())
+    wplan.close()
+    return {"kernel_ms": tw, "instances": sub.batch, "reached_99": okw,
+            "instances_per_s_reached_99": okw / (tw / 1e3),
+            "mean_iters": float(it2.cpu().numpy().mean())}
 
 
 def gpu_wmmse(batch, ref, max_iters: int = 500, eps: float = 1e-6):
@@ -320,7 +440,20 @@ def early_exit(batch, ref, eps_list=(1e-3, 1e-4, 1e-5)):
     return out
 
 
-def profile_leg(name: str, reps: int) -> int:
+def calib_copy_run():
+    """A CALIB_COPY_MIB MiB device-to-device copy (three times), whose FETCH_SIZE
+    and WRITE_SIZE counters scale the solve kernels' counters to bytes."""
+    import torch
+    n = CALIB_COPY_MIB * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    return n * 4
+
+
+def profile_leg(name: str, reps: int, calib: bool = False) -> int:
     """Launch one workload `reps` times and print its kernel times: the
     seven-cell uneven batch (4096 instances, FP32, 100 iterations), the M=256
     batch in float or bfloat16 mode, GPU WMMSE on the benchmark batch, or the
@@ -329,6 +462,8 @@ def profile_leg(name: str, reps: int) -> int:
     from paper_2510_20507_amd import ammse, synth
     if name == "unrolled":
         print(json.dumps(unrolled_leg(reps=reps)), flush=True)
+        if calib:
+            calib_copy_run()
         return 0
     if name == "hexcell":
         batch = synth.hexcell_batch(4096)
@@ -362,13 +497,18 @@ def profile_leg(name: str, reps: int) -> int:
         print(json.dumps({"leg": name, "workload": batch.name, "rep": r, "kernel_ms": ms,
                           "algorithmic_tflops": flops / (ms / 1e3) / 1e12}), flush=True)
     plan.close()
+    if calib:
+        calib_copy_run()
     return 0
 
 
 def parse_pmc(dirs):
-    """Sum FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the solve kernel and of
-    the calibration copy from rocprofv3 --pmc CSV output directories."""
-    out = {}
+    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of each solve kernel and of the
+    calibration copy from rocprofv3 --pmc CSV output directories.  Per kernel
+    only the dispatches with its largest grid count (the full-batch launches,
+    not the autotuner's sample launches); the calibration copy is the large
+    __amd_rocclr_copyBuffer of --calib-copy."""
+    per = {}
     for d in dirs:
         for f in glob.glob(os.path.join(d, "**", "*counter_collection*.csv"), recursive=True):
             with open(f) as fh:
@@ -377,32 +517,67 @@ def parse_pmc(dirs):
                     cname = row.get("Counter_Name", "")
                     val = float(row.get("Counter_Value", 0) or 0)
                     grid = int(row.get("Grid_Size", 0) or 0)
-                    kind = ("solve" if ("ammse_" in name and "_kernel" in name) else
-                            "copy" if ("copyBuffer" in name and grid >= 131072 and val > 100000)
-                            else None)
-                    if kind is None:
+                    if "ammse_" in name and "_kernel" in name:
+                        kname = name
+                    elif "copyBuffer" in name and grid >= 131072 and val > 100000:
+                        kname = "copy"
+                    else:
                         continue
-                    key = (kind, cname, row.get("Dispatch_Id", row.get("Correlation_Id", "")))
-                    out[key] = out.get(key, 0.0) + val
+                    disp = row.get("Dispatch_Id", row.get("Correlation_Id", ""))
+                    key = (kname, cname, disp)
+                    per[key] = (per.get(key, (0.0, grid))[0] + val, grid)
+    gmax = {}
+    for (k, c, _), (v, g) in per.items():
+        gmax[k] = max(gmax.get(k, 0), g)
     agg = {}
-    for (kind, cname, _), v in out.items():
-        agg.setdefault((kind, cname), []).append(v)
+    for (k, c, _), (v, g) in per.items():
+        if g == gmax[k]:
+            agg.setdefault((k, c), []).append(v)
     res = {f"{k[0]}:{k[1]}": (float(np.mean(v)), len(v)) for k, v in agg.items()}
-    # calibration: the --calib-copy run copies CALIB_COPY_MIB MiB device-to-device
     known_kib = CALIB_COPY_MIB * 1024.0
-    out2 = {"raw_kib_per_dispatch": res}
-    if "copy:FETCH_SIZE" in res and "solve:FETCH_SIZE" in res:
-        sf = known_kib / res["copy:FETCH_SIZE"][0]
-        out2["fetch_scale"] = sf
-        out2["solve_fetch_bytes"] = res["solve:FETCH_SIZE"][0] * 1024 * sf
-    if "copy:WRITE_SIZE" in res and "solve:WRITE_SIZE" in res:
-        sw = known_kib / res["copy:WRITE_SIZE"][0]
-        out2["write_scale"] = sw
-        out2["solve_write_bytes"] = res["solve:WRITE_SIZE"][0] * 1024 * sw
-    if "solve_fetch_bytes" in out2 and "solve_write_bytes" in out2:
-        out2["traffic_bytes_per_launch"] = out2["solve_fetch_bytes"] + out2["solve_write_bytes"]
+    out2 = {"raw_kib_per_dispatch": res, "grid": gmax}
+    sf = known_kib / res["copy:FETCH_SIZE"][0] if "copy:FETCH_SIZE" in res else None
+    sw = known_kib / res["copy:WRITE_SIZE"][0] if "copy:WRITE_SIZE" in res else None
+    out2["fetch_scale"], out2["write_scale"] = sf, sw
+    kernels = {}
+    for k in gmax:
+        if k == "copy":
+            continue
+        e = {}
+        if sf and f"{k}:FETCH_SIZE" in res:
+            e["fetch_bytes"] = res[f"{k}:FETCH_SIZE"][0] * 1024 * sf
+        if sw and f"{k}:WRITE_SIZE" in res:
+            e["write_bytes"] = res[f"{k}:WRITE_SIZE"][0] * 1024 * sw
+        if "fetch_bytes" in e and "write_bytes" in e:
+            e["traffic_bytes_per_launch"] = e["fetch_bytes"] + e["write_bytes"]
+        kernels[k] = e
+    out2["kernels"] = kernels
     out2["kernel_sha"] = kernel_sha()
     return out2
+
+
+def parse_trace(dirs, skip: int):
+    """Per-kernel durations from rocprofv3 --kernel-trace CSV output, without
+    the first `skip` dispatches of each kernel (the untimed warm-up launches of
+    the run), so that the average is over the same launches the bench times."""
+    rows = {}
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True):
+            with open(f) as fh:
+                for row in csv.DictReader(fh):
+                    name = row.get("Kernel_Name", "")
+                    t = int(row["End_Timestamp"]) - int(row["Start_Timestamp"])
+                    rows.setdefault(name, []).append((int(row["Start_Timestamp"]), t))
+    out = {}
+    for name, v in rows.items():
+        v.sort()
+        warm = [t for _, t in v[skip:]]
+        if not warm:
+            continue
+        out[name] = {"calls": len(v), "warm_calls": len(warm),
+                     "warm_avg_ns": float(np.mean(warm)), "warm_min_ns": int(min(warm)),
+                     "warm_max_ns": int(max(warm))}
+    return out
 
 
 def main():
@@ -417,9 +592,16 @@ def main():
     ap.add_argument("--no-unrolled", action="store_true")
     ap.add_argument("--no-early-exit", action="store_true")
     ap.add_argument("--no-single", action="store_true")
+    ap.add_argument("--no-hexcell", action="store_true")
+    ap.add_argument("--hexcell-wmmse", action="store_true",
+                    help="also run GPU WMMSE on the 512 sampled seven-cell instances (about a minute)")
     ap.add_argument("--calib-copy", action="store_true",
                     help=f"also run a {CALIB_COPY_MIB} MiB device copy (counter calibration)")
     ap.add_argument("--parse-pmc", nargs="+", metavar="DIR")
+    ap.add_argument("--parse-trace", nargs="+", metavar="DIR",
+                    help="per-kernel warm-launch durations from rocprofv3 --kernel-trace output")
+    ap.add_argument("--skip", type=int, default=0,
+                    help="with --parse-trace: leading dispatches of each kernel to leave out")
     ap.add_argument("--profile-leg", choices=["hexcell", "large_fp32", "large_bf16", "wmmse",
                                               "unrolled"],
                     help="run only one other workload's launches (for rocprofv3) and exit")
@@ -428,8 +610,11 @@ def main():
     if a.parse_pmc:
         print(json.dumps(parse_pmc(a.parse_pmc), indent=1))
         return 0
+    if a.parse_trace:
+        print(json.dumps(parse_trace(a.parse_trace, a.skip), indent=1))
+        return 0
     if a.profile_leg:
-        return profile_leg(a.profile_leg, a.steps)
+        return profile_leg(a.profile_leg, a.steps, a.calib_copy)
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); instances "
               "are independent, so a multi-GPU run would shard the batch with no communication.",
@@ -518,7 +703,8 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
                      "traffic": traffic,
-                     "kernel": ("ammse_fast_kernel (LDS-resident, MFMA FP32)"
+                     "kernel": ("ammse_fast_bound_kernel + ammse_fast_kernel (one solve: "
+                                "stage-II step bound, then the LDS-resident MFMA FP32 solve)"
                                 if plan.kernel == ammse.KERNEL_LDS_MFMA
                                 else "ammse_solve_kernel<float> (general)"),
                      "kernel_ms": kern_ms, "flops_per_launch": flops,
@@ -537,14 +723,10 @@ def main():
         line["single_instance"] = single_instance()
     if not a.no_early_exit:
         line["early_exit"] = early_exit(batch, ref)
+    if not a.no_hexcell:
+        line["hexcell"] = hexcell_leg(cpu=not a.no_cpu_baseline, wmmse=a.hexcell_wmmse)
     if a.calib_copy:
-        n = CALIB_COPY_MIB * (1 << 20) // 4
-        x = torch.ones(n, dtype=torch.float32, device="cuda")
-        y = torch.empty_like(x)
-        for _ in range(3):
-            y.copy_(x)
-        torch.cuda.synchronize()
-        line["calib_copy_bytes"] = n * 4
+        line["calib_copy_bytes"] = calib_copy_run()
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(batch, ref)
     print(json.dumps(line), flush=True)
