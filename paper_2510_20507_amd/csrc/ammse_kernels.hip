@@ -1259,54 +1259,89 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     const double om = p.extrapolate ? fmax((t - 2.0) / (t + 1.0), 0.0) : 0.0;
     const T ga1 = (T)((1.0 + om) * gsp), ga2 = (T)(om * gsq);
     const T xa1 = (T)((1.0 + om) * xs1), xa2 = (T)(om * xs2), gz = (T)(2.0 * sm.gamma[0]);
-    for (int c = 0; c < C; ++c) {
-      const int nc = sm.cu[c] * d;
-      const long base = (long)un * sm.colOff[c];
-      const int ne = U * nc;
-#pragma unroll 2
-      for (int e = tid; e < ne; e += AMMSE_BLOCK) {
-        const int u = e / nc, j = e - u * nc;
-        const long g0 = base + (long)(u * N) * nc + j;
-        cx<T> gh[AMMSE_MAX_RX];
+    // Compiled per N (the loop bounds fold); with float storage each thread
+    // takes two (user, column) elements per trip and issues every load of both
+    // before the arithmetic, so that their latencies overlap (one element with
+    // double storage, whose registers are the tighter budget).
+    auto zbuild = [&](auto nn) __attribute__((always_inline)) {
+      constexpr int NN = decltype(nn)::value;
+      for (int c = 0; c < C; ++c) {
+        const int nc = sm.cu[c] * d;
+        const long base = (long)un * sm.colOff[c];
+        const int ne = U * nc;
+        constexpr int QB = sizeof(R) == 4 ? 2 : 1;
+        for (int e0 = tid; e0 < ne; e0 += QB * AMMSE_BLOCK) {
+          int uq[QB], jq[QB];
+          long gq0[QB];
+          bool live[QB];
+          cx<R> ga[QB][NN], gb[QB][NN], x1[QB][NN], x2[QB][NN];
+          cx<T> dm[QB][NN][NN];
 #pragma unroll
-        for (int k = 0; k < AMMSE_MAX_RX; ++k) {
-          gh[k] = {T(0), T(0)};
-          if (k < N) {
-            const cx<R> a = Gp[g0 + (long)k * nc], q = Gq[g0 + (long)k * nc];
-            gh[k] = {ga1 * (T)a.x - ga2 * (T)q.x, ga1 * (T)a.y - ga2 * (T)q.y};
-          }
-        }
-        const int j0 = sm.local[u] * d;
-        const bool own = sm.cellOf[u] == c && j >= j0 && j < j0 + d;
-        const T is = (T)sm.invsig[u];
+          for (int q = 0; q < QB; ++q) {
+            const int e = min(e0 + q * AMMSE_BLOCK, ne - 1);
+            live[q] = e0 + q * AMMSE_BLOCK < ne;
+            const int u = e / nc, j = e - u * nc;
+            uq[q] = u;
+            jq[q] = j;
+            gq0[q] = base + (long)(u * NN) * nc + j;
 #pragma unroll
-        for (int n = 0; n < AMMSE_MAX_RX; ++n) {
-          if (n < N) {
-            cx<T> acc = {T(0), T(0)};
-#pragma unroll
-            for (int k = 0; k < AMMSE_MAX_RX; ++k)
-              if (k < N) acc = acc + DmT[u * 16 + n * 4 + k] * gh[k];
-            if (own) acc = acc - YmT[u * 16 + n * 4 + (j - j0)];
-            if (rpath) {
-              // implicit precoder: Z' = D G^ - Y (the gradient is 2 H^H S Z'),
-              // X~ = X^ - 2 gamma Z' over X^{t-2}
-              const long e = g0 + (long)n * nc;
-              const cx<R> x1 = X1[e], x2 = X2[e];
-              X2[e] = cx<R>{(R)(xa1 * (T)x1.x - xa2 * (T)x2.x - gz * acc.x),
-                            (R)(xa1 * (T)x1.y - xa2 * (T)x2.y - gz * acc.y)};
-              continue;
-            }
-            const cx<R> zv = {(R)(is * acc.x), (R)(is * acc.y)};
-            if constexpr (sizeof(R) == 4) {
-              if (lowp && copies) {
-                Zb[g0 + (long)n * nc] = to_bfc(zv);
-                continue;
+            for (int k = 0; k < NN; ++k) {
+              ga[q][k] = Gp[gq0[q] + (long)k * nc];
+              gb[q][k] = Gq[gq0[q] + (long)k * nc];
+              if (rpath) {
+                x1[q][k] = X1[gq0[q] + (long)k * nc];
+                x2[q][k] = X2[gq0[q] + (long)k * nc];
               }
             }
-            Z[g0 + (long)n * nc] = zv;
+#pragma unroll
+            for (int n = 0; n < NN; ++n)
+#pragma unroll
+              for (int k = 0; k < NN; ++k) dm[q][n][k] = DmT[u * 16 + n * 4 + k];
+          }
+#pragma unroll
+          for (int q = 0; q < QB; ++q) {
+            const int u = uq[q], j = jq[q];
+            cx<T> gh[NN];
+#pragma unroll
+            for (int k = 0; k < NN; ++k)
+              gh[k] = {ga1 * (T)ga[q][k].x - ga2 * (T)gb[q][k].x,
+                       ga1 * (T)ga[q][k].y - ga2 * (T)gb[q][k].y};
+            const int j0 = sm.local[u] * d;
+            const bool own = sm.cellOf[u] == c && j >= j0 && j < j0 + d;
+            const T is = (T)sm.invsig[u];
+#pragma unroll
+            for (int n = 0; n < NN; ++n) {
+              cx<T> acc = {T(0), T(0)};
+#pragma unroll
+              for (int k = 0; k < NN; ++k) acc = acc + dm[q][n][k] * gh[k];
+              if (own) acc = acc - YmT[u * 16 + n * 4 + (j - j0)];
+              const long e = gq0[q] + (long)n * nc;
+              if (!live[q]) continue;
+              if (rpath) {
+                // implicit precoder: Z' = D G^ - Y (the gradient is 2 H^H S Z'),
+                // X~ = X^ - 2 gamma Z' over X^{t-2}
+                X2[e] = cx<R>{(R)(xa1 * (T)x1[q][n].x - xa2 * (T)x2[q][n].x - gz * acc.x),
+                              (R)(xa1 * (T)x1[q][n].y - xa2 * (T)x2[q][n].y - gz * acc.y)};
+                continue;
+              }
+              const cx<R> zv = {(R)(is * acc.x), (R)(is * acc.y)};
+              if constexpr (sizeof(R) == 4) {
+                if (lowp && copies) {
+                  Zb[e] = to_bfc(zv);
+                  continue;
+                }
+              }
+              Z[e] = zv;
+            }
           }
         }
       }
+    };
+    switch (N) {
+      case 1: zbuild(std::integral_constant<int, 1>{}); break;
+      case 2: zbuild(std::integral_constant<int, 2>{}); break;
+      case 3: zbuild(std::integral_constant<int, 3>{}); break;
+      default: zbuild(std::integral_constant<int, 4>{}); break;
     }
     __syncthreads();
 
