@@ -1173,15 +1173,19 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     const bool use_bound = !wm && stage2 && !adaptive && !(p.gamma_c > 0.0) &&
                            p.step_rule == AMMSE_STEP_BOUND;
     if (use_bound && !have_bound) {
-      // Lhat_c / 2 = lambda_max(H_c^H S diag(alpha) S H_c) by the same Lanczos
-      // on the operator with D = alpha_u I (D is rewritten by weights() below)
+      // Lhat_c / 2 = lambda_max(H_c^H S diag(alpha) S H_c) by the step-size
+      // Lanczos: on the Q path on K = C^H Q C with C = diag(sqrt(alpha)) (one
+      // read of Q per step instead of two passes over H), otherwise on the
+      // operator with D = alpha_u I (C and D are rewritten by the weights below)
       for (int e = tid; e < U * 16; e += AMMSE_BLOCK) {
         const int u = e >> 4, a = (e >> 2) & 3, bb = e & 3;
-        Dm[e] = (a == bb && a < N) ? zd{sm.alpha[u], 0.0} : zd{0.0, 0.0};
+        const bool dg = a == bb && a < N;
+        if (qpath) Cm[e] = dg ? zd{sqrt(sm.alpha[u]), 0.0} : zd{0.0, 0.0};
+        else Dm[e] = dg ? zd{sm.alpha[u], 0.0} : zd{0.0, 0.0};
       }
       __syncthreads();
       for (int c = 0; c < C; ++c) {
-        const double lm = (sm.cu[c] == 0) ? 0.0 : lanczos_lmax(c);
+        const double lm = (sm.cu[c] == 0) ? 0.0 : qpath ? lanczos_q() : lanczos_lmax(c);
         if (tid == 0) sm.gbound[c] = (lm > 0.0) ? 1.0 / (2.0 * lm) : 0.0;
         __syncthreads();
       }
