@@ -263,6 +263,7 @@ __device__ __forceinline__ void fast_body(const ammse_kparams_t& p) {
   const float2* Hg = (const float2*)p.H + Dd.h_off;
   float2* Vg = (float2*)p.V + Dd.v_off;
   const double Pc = p.wsr_only ? 0.0 : p.P[Dd.bs_off];
+  const double iPc = (Pc > 0.0) ? 1.0 / Pc : 0.0;
 
   for (int r = tid; r < UN; r += 256) {
     invsig[r] = 1.0 / sqrt(p.sigma2[Dd.user_off + r / N]);
@@ -563,7 +564,9 @@ __device__ __forceinline__ void fast_body(const ammse_kparams_t& p) {
       const zd y = (part[lane] + part[UN + lane]) + (part[2 * UN + lane] + part[3 * UN + lane]);
       double al = x.x * y.x + x.y * y.y, yy = nrm2(y), py = pp.x * y.x + pp.y * y.y;
       wave_sum3_dpp(al, yy, py);
-      const double bb = sqrt(fmax(yy - al * al - 2.0 * beta_prev * py + beta_prev * beta_prev, 0.0));
+      const double b2 = fmax(yy - al * al - 2.0 * beta_prev * py + beta_prev * beta_prev, 0.0);
+      const double ib = rsqrt_nr(fmin(fmax(b2, 1e-300), __DBL_MAX__));   // 1 / beta
+      const double bb = b2 * ib;
       if (lane == j) {
         ta = al;
         tb = bb;
@@ -578,7 +581,7 @@ __device__ __forceinline__ void fast_body(const ammse_kparams_t& p) {
         stop = breakdown || conv || msz == m;
       }
       if (!stop) {
-        const zd xn = scal(1.0 / bb, y - scal(al, x) - scal(beta_prev, pp));
+        const zd xn = scal(ib, y - scal(al, x) - scal(beta_prev, pp));
         pp = x;
         x = xn;
         beta_prev = bb;
@@ -759,7 +762,9 @@ __device__ __forceinline__ void fast_body(const ammse_kparams_t& p) {
             Gp[i][j][r] = gt;        // G~
           }
       const double pw = ch * ch * nu + block_sum4((double)acc, red + 8);
-      const double scd = (pw > Pc) ? sqrt(Pc / pw) : 1.0;
+      // sqrt(Pc / pw) = 1 / sqrt(pw / Pc) by the refined reciprocal square root
+      const double scd = (pw > Pc) ? ((Pc > 0.0) ? rsqrt_nr(fmin(pw * iPc, __DBL_MAX__)) : 0.0)
+                                   : 1.0;
       const float sc = (float)scd;
       c2s = c1;
       c1 = scd * ch;
