@@ -248,7 +248,8 @@ def hexcell_leg(reps: int = 3, cpu: bool = True, wmmse: bool = False):
                         "frac": alg_bytes / (t / 1e3) / 1e9 / PEAK_HBM_GBS,
                         "traffic": read_traffic(HEX_TRAFFIC_FILE), "algorithmic_bytes": alg_bytes,
                         "algorithmic_tflops": flops / (t / 1e3) / 1e12,
-                        "kernel": "ammse_solve_kernel<float> (general)"}}
+                        "kernel": "ammse_bound_gram_kernel + ammse_solve_kernel<float> (one solve: "
+                                  "stage-II step bound, then the general solve)"}}
     if wmmse:   # GPU WMMSE on the sampled instances (the reference's algorithm)
         out["gpu_wmmse_sample"] = hexcell_wmmse(batch.subset(idx), wref)
     if cpu:

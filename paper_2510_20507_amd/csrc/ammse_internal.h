@@ -41,6 +41,10 @@ struct ammse_ws_layout_t {
   size_t Ubm, Wbm, Jbm, Fbm;  // BCGD-WMMSE: per-user U and W iterates, receive covariance J
                               // and own-stream image G_own of the current V (double complex
                               // 4 x 4 blocks)
+  size_t Rb, Ab, Gb;          // stage-II step bound on the antenna side (ammse_bound_gram):
+                              // S_a H_{:,c} ((U N) x M, one BS at a time),
+                              // A_c = H_{:,c}^H S_a^2 H_{:,c} (M x M per BS), storage
+                              // precision, and the resulting steps 1 / Lhat_c (C doubles)
   size_t total;
 };
 
@@ -78,6 +82,9 @@ struct ammse_kparams_t {
                          // (and G^0 when lowp_iters >= 1); -1: float products only
   int32_t tile_force;    // 0: per-instance tile shape from the descriptor; v + 1: shape v
   int32_t step_rule;     // AMMSE_STEP_BOUND / AMMSE_STEP_FROZEN
+  int32_t bound_pre;     // general kernel: the stage-II bound of the instances that
+                         // ammse_bound_gram selects was written to their workspace by
+                         // ammse_bound_gram_kernel before this launch
   double eps1, eps2, gamma_c;
   double* gbound;        // LDS-resident kernel: 1 / Lhat per launch position (bound rule)
 };
@@ -102,6 +109,18 @@ __host__ __device__ inline bool ammse_gram_path(int real_bytes, int C, int U, in
   const long un = (long)U * N, ud = (long)U * d;
   const bool qp = !wmmse && C == 1 && un <= M;
   return real_bytes == 4 && !wmmse && !qp && ud * ud < 2 * un * (long)M;
+}
+
+// Stage-II step bound of Algorithm 3 (and of BCGD-WMMSE), lambda_max(A_c) with
+// A_c = H_{:,c}^H S_a^2 H_{:,c}, S_a = diag(sqrt(alpha_u) / sigma_u): with
+// float storage off the single-cell Q path and M <= AMMSE_GRAM_WAVE_N, A_c is
+// formed by an MFMA product and its largest eigenvalue found by one wave per
+// BS (each Lanczos step then reads A_c once instead of passing over H_{:,c}
+// twice), in a kernel of its own launched before the solve kernel.
+__host__ __device__ inline bool ammse_bound_gram(int real_bytes, int C, int U, int M, int N,
+                                                 bool wmmse, bool bcgd) {
+  const bool qp = !wmmse && !bcgd && C == 1 && (long)U * N <= M;
+  return real_bytes == 4 && !wmmse && !qp && M <= AMMSE_GRAM_WAVE_N;
 }
 
 __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int C, int U, int M,
@@ -164,6 +183,10 @@ __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int
   L.Wbm = o; o += ammse_align256(bc * (size_t)U * 16 * zs);
   L.Jbm = o; o += ammse_align256(bc * (size_t)U * 16 * zs);
   L.Fbm = o; o += ammse_align256(bc * (size_t)U * 16 * zs);
+  const size_t ba = ammse_bound_gram(real_bytes, C, U, M, N, wmmse, bcgd) ? 1 : 0;
+  L.Rb = o;  o += ammse_align256(ba * un * (size_t)M * cs);
+  L.Ab = o;  o += ammse_align256(ba * (size_t)C * M * M * cs);
+  L.Gb = o;  o += ammse_align256(ba * (size_t)C * sizeof(double));
   L.total = o;
   return L;
 }

@@ -178,6 +178,75 @@ static_assert((AMMSE_BLOCK / 64) * ((AMMSE_GRAM_WAVE_N + 16) * sizeof(float2) + 
                   3 * AMMSE_LANCZOS_LDS_N * sizeof(zd),
               "the per-wave Gram Lanczos buffers fit the A-MMMSE dynamic LDS");
 
+// Stage-II step of the bound rule for the general kernel's instances that
+// ammse_bound_gram selects (float storage, not the single-cell Q path,
+// M <= AMMSE_GRAM_WAVE_N): for every BS c with users, 1 / (2 lambda_max(A_c)),
+// A_c = R_c^H R_c, R_c = S_a H_{:,c}, S_a = diag(sqrt(alpha_u) / sigma_u).
+// R_c is formed in one pass over H_{:,c}, A_c by one MFMA product (made
+// exactly Hermitian), then one wave per BS runs the Lanczos iteration of the
+// step size (wave_lanczos_lmax) on its A_c.  The bound depends only on the
+// channel, the noise powers and the weights, so this kernel runs before the
+// solve kernel (one workgroup per instance, same stream) and writes the
+// values into the instance workspace, where the solve kernel reads them when
+// its second stage first needs them.  Other instances return at once.
+__global__ __launch_bounds__(AMMSE_BLOCK, 2) void ammse_bound_gram_kernel(ammse_kparams_t p) {
+  __shared__ __align__(16) char tiles[tile_bytes<float>()];
+  __shared__ float2 qsa[4 * (AMMSE_GRAM_WAVE_N + 16)];
+  __shared__ double2 tpa[4 * 64];
+  __shared__ double sa[AMMSE_MAX_USERS];
+  const ammse_desc_t D = p.desc[blockIdx.x];
+  const int C = D.C, U = D.U, M = D.M, N = D.N, d = D.d, un = D.un;
+  const bool wm = p.algorithm == AMMSE_ALGO_WMMSE || p.algorithm == AMMSE_ALGO_MMMSE;
+  const bool bc = p.algorithm == AMMSE_ALGO_BCGD;
+  if (!ammse_bound_gram(4, C, U, M, N, wm, bc)) return;   // uniform over the workgroup
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tile = (p.tile_force > 0) ? p.tile_force - 1 : D.tile;
+  const ammse_ws_layout_t L =
+      ammse_ws_layout(4, C, U, M, N, d, p.lanczos_steps, wm, p.bf16_copies != 0, bc);
+  char* ws = p.ws + D.ws_off;
+  cx<float>* Rb = (cx<float>*)(ws + L.Rb);
+  cx<float>* Ab = (cx<float>*)(ws + L.Ab);
+  double* gb = (double*)(ws + L.Gb);
+  const cx<float>* H = (const cx<float>*)p.H + D.h_off;
+  for (int u = tid; u < U; u += AMMSE_BLOCK)
+    sa[u] = sqrt(p.alpha[D.user_off + u] / p.sigma2[D.user_off + u]);
+  __syncthreads();
+  for (int c = 0; c < C; ++c) {
+    if (p.cell_users[D.cell_off + c] == 0) continue;   // no precoder, no step
+    const cx<float>* __restrict__ Hc = H + (long)c * un * M;
+    cx<float>* __restrict__ Ac = Ab + (long)c * M * M;
+    for (int e = tid; e < un * M; e += AMMSE_BLOCK) {
+      const double f = sa[(e / M) / N];
+      const cx<float> h = Hc[e];
+      Rb[e] = {(float)(f * (double)h.x), (float)(f * (double)h.y)};
+    }
+    __syncthreads();
+    channel_gemm<float, true, false>(M, M, un, Rb, M, Rb, M, tiles, false, tile,
+                                     [&](int i, int j, cx<float> v) { Ac[(long)i * M + j] = v; });
+    __syncthreads();
+    for (int e = tid; e < M * M; e += AMMSE_BLOCK) {   // exactly Hermitian
+      const int i = e / M, j = e - i * M;
+      if (i < j) {
+        const cx<float> x = Ac[e], y = Ac[(long)j * M + i];
+        const cx<float> mm = {0.5f * (x.x + y.x), 0.5f * (x.y - y.y)};
+        Ac[e] = mm;
+        Ac[(long)j * M + i] = {mm.x, -mm.y};
+      } else if (i == j) {
+        Ac[e].y = 0.f;
+      }
+    }
+    __syncthreads();
+  }
+  float2* qs = qsa + wave * (AMMSE_GRAM_WAVE_N + 16);
+  double2* tp = tpa + wave * 64;
+  for (int c = wave; c < C; c += AMMSE_BLOCK / 64) {
+    const double lm = (p.cell_users[D.cell_off + c] == 0)
+                          ? 0.0
+                          : wave_lanczos_lmax(Ab + (long)c * M * M, M, p.lanczos_steps, qs, tp);
+    if (lane == 0) gb[c] = (lm > 0.0) ? 1.0 / (2.0 * lm) : 0.0;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // The fused kernel
 // ---------------------------------------------------------------------------
@@ -228,6 +297,8 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   // in bfloat16 iterations that product takes bfloat16 operands, and the
   // refinement pass starts from G^{t-1}, G^{t-2} recomputed with float products.
   const bool rpath = qpath && sizeof(R) == 4;
+  // stage-II bound from the antenna-side Gram matrices (see ammse_bound_gram)
+  const bool bgram = ammse_bound_gram((int)sizeof(R), C, U, M, N, wm, bc);
   const ammse_ws_layout_t L =
       ammse_ws_layout((int)sizeof(R), C, U, M, N, d, p.lanczos_steps, wm, p.bf16_copies != 0, bc);
   char* ws = p.ws + D.ws_off;
@@ -263,6 +334,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   zd* Cm = (zd*)(ws + L.Cm);
   cx<R>* Rg = (cx<R>*)(ws + L.Rg);
   cx<R>* Kg = (cx<R>*)(ws + L.Kg);
+  const double* Gbw = (const double*)(ws + L.Gb);   // stage-II bound (bgram below)
   zd* Ubm = (zd*)(ws + L.Ubm);       // BCGD-WMMSE: U, W iterates, J and G_own of V^{t-1}
   zd* Wbm = (zd*)(ws + L.Wbm);
   zd* Jbm = (zd*)(ws + L.Jbm);
@@ -1172,6 +1244,12 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
                                          t < switch_iter + p.T_c);
     const bool use_bound = !wm && stage2 && !adaptive && !(p.gamma_c > 0.0) &&
                            p.step_rule == AMMSE_STEP_BOUND;
+    if (use_bound && !have_bound && bgram && p.bound_pre) {
+      // written by ammse_bound_gram_kernel (launched before this kernel)
+      if (tid < C) sm.gbound[tid] = Gbw[tid];
+      __syncthreads();
+      have_bound = true;
+    }
     if (use_bound && !have_bound) {
       // Lhat_c / 2 = lambda_max(H_c^H S diag(alpha) S H_c) by the step-size
       // Lanczos: on the Q path on K = C^H Q C with C = diag(sqrt(alpha)) (one
@@ -1558,6 +1636,16 @@ hipError_t launch_general(const ammse_kparams_t& p0, hipStream_t s) {
     p.lds_factor = sizeof(R) == 4 ? 2 : 1;
   } else {
     p.lds_factor = 0;
+  }
+  p.bound_pre = 0;
+  if constexpr (sizeof(R) == 4) {
+    // the stage-II bound of the instances that ammse_bound_gram selects
+    // (the kernel returns at once for the others)
+    if ((p.algorithm == AMMSE_ALGO_AMMMSE || p.algorithm == AMMSE_ALGO_BCGD) && !p.wsr_only &&
+        p.step_rule == AMMSE_STEP_BOUND && !(p.gamma_c > 0.0) && p.max_iters > p.T_c) {
+      hipLaunchKernelGGL(ammse_bound_gram_kernel, dim3(p.batch), dim3(AMMSE_BLOCK), 0, s, p);
+      p.bound_pre = 1;
+    }
   }
   hipLaunchKernelGGL(ammse_solve_kernel<R>, dim3(p.batch), dim3(AMMSE_BLOCK), dyn, s, p);
   return hipGetLastError();
