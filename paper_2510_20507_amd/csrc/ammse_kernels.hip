@@ -755,20 +755,18 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       Rg[e] = {(R)(f * acc.x), (R)(f * acc.y)};
     }
     __syncthreads();
-    channel_gemm<R, false, true>(ud, ud, M, Rg, M, Rg, M, sm.tiles, false, tile,
-                                 [&](int i, int j, cx<R> v) { Kc[(long)i * ud + j] = v; });
-    __syncthreads();
-    for (int e = tid; e < ud * ud; e += AMMSE_BLOCK) {   // exactly Hermitian
-      const int i = e / ud, j = e - i * ud;
-      if (i < j) {
-        const cx<R> x = Kc[e], y = Kc[(long)j * ud + i];
-        const cx<R> mm = {(R)0.5 * (x.x + y.x), (R)0.5 * (x.y - y.y)};
-        Kc[e] = mm;
-        Kc[(long)j * ud + i] = {mm.x, -mm.y};
-      } else if (i == j) {
-        Kc[e].y = (R)0;
-      }
-    }
+    // square output: the 64 x 64 tile shape whatever the channel products
+    // use; K made exactly Hermitian by taking the computed upper triangle
+    // (its conjugate transpose below the diagonal, a real diagonal)
+    channel_gemm<R, false, true>(ud, ud, M, Rg, M, Rg, M, sm.tiles, false, 0,
+                                 [&](int i, int j, cx<R> v) {
+                                   if (i < j) {
+                                     Kc[(long)i * ud + j] = v;
+                                     Kc[(long)j * ud + i] = {v.x, -v.y};
+                                   } else if (i == j) {
+                                     Kc[(long)i * ud + j] = {v.x, (R)0};
+                                   }
+                                 });
     __syncthreads();
   };
   auto lanczos_gram = [&]() {   // on the K formed last (at Kg)
