@@ -34,7 +34,7 @@ struct ammse_ws_layout_t {
   size_t Lwm, Lim, Cm;        // per-user Lw, Lw^{-1}, C (double complex 4 x 4): WMMSE,
                               // and Lw^{-1}, C for the Q- and Gram-based Lanczos
   size_t Rg, Kg;              // Gram-based Lanczos: R = C^H S H_{:,c} ((U d) x M) and
-                              // K = R R^H ((U d) x (U d)), storage precision
+                              // R R^H or R^H R (ammse_gram_order), storage precision
   size_t X1, X2, G0;          // Q recursion (single cell, U N <= M, float products): the
                               // implicit precoder's X^{t-1}, X^{t-2} and G^0 ((U N) x (U d),
                               // storage precision)
@@ -100,15 +100,23 @@ struct ammse_kparams_t {
 // starts on a 256-byte boundary.
 __host__ __device__ inline size_t ammse_align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Step-size Lanczos of Algorithm 3 on the stream-space Gram matrix
-// K_c = R_c R_c^H, R_c = C^H S H_{:,c} (D = C C^H), instead of the operator
+// Order of the Gram matrix of the step-size Lanczos: with D = C C^H and
+// R_c = C^H S H_{:,c} ((U d) x M), lambda_max(H_{:,c}^H S D S H_{:,c}) is the
+// largest eigenvalue of both R_c R_c^H ((U d) x (U d), stream side) and
+// R_c^H R_c (M x M, antenna side); the smaller one is used.
+__host__ __device__ inline long ammse_gram_order(int U, int M, int d) {
+  const long ud = (long)U * d;
+  return ud < M ? ud : (long)M;
+}
+
+// Step-size Lanczos of Algorithm 3 on that Gram matrix instead of the operator
 // x -> H_{:,c}^H S D S H_{:,c} x: float storage, not the single-cell Q path,
-// and fewer matrix entries per step ((U d)^2 < 2 U N M).
+// and fewer matrix entries per step (order^2 < 2 U N M).
 __host__ __device__ inline bool ammse_gram_path(int real_bytes, int C, int U, int M, int N, int d,
                                                 bool wmmse) {
-  const long un = (long)U * N, ud = (long)U * d;
+  const long un = (long)U * N, ng = ammse_gram_order(U, M, d);
   const bool qp = !wmmse && C == 1 && un <= M;
-  return real_bytes == 4 && !wmmse && !qp && ud * ud < 2 * un * (long)M;
+  return real_bytes == 4 && !wmmse && !qp && ng * ng < 2 * un * (long)M;
 }
 
 // Stage-II step bound of Algorithm 3 (and of BCGD-WMMSE), lambda_max(A_c) with
@@ -141,7 +149,8 @@ __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int
   L.Dm = o;  o += ammse_align256((size_t)U * 16 * zs);
   L.Ym = o;  o += ammse_align256((size_t)U * 16 * zs);
   const size_t gp = ammse_gram_path(real_bytes, C, U, M, N, d, wmmse || bcgd) ? 1 : 0;
-  const size_t nl = (gp && ud > (size_t)M) ? ud : (size_t)M;   // Lanczos order (at most)
+  const size_t ng = (size_t)ammse_gram_order(U, M, d);   // <= M
+  const size_t nl = (size_t)M;                           // Lanczos order (at most)
   L.Lq = o;  o += ammse_align256((size_t)3 * nl * zs);   // three Lanczos vectors
   L.Lw = o;  o += ammse_align256((size_t)M * zs);
   L.Ly1 = o; o += ammse_align256(un * zs);
@@ -161,10 +170,10 @@ __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int
   L.Lim = o; o += ammse_align256((w | qp | gp) * (size_t)U * 16 * zs);
   L.Cm = o;  o += ammse_align256((w | qp | gp) * (size_t)U * 16 * zs);
   L.Rg = o;  o += ammse_align256(gp * ud * (size_t)M * cs);
-  // one K_c per BS when the per-BS iterations run one wave each (order <=
-  // AMMSE_GRAM_WAVE_N), else one K at a time
-  const size_t gk = (ud <= (size_t)AMMSE_GRAM_WAVE_N) ? (size_t)C : 1;
-  L.Kg = o;  o += ammse_align256(gp * gk * ud * ud * cs);
+  // one Gram matrix per BS when the per-BS iterations run one wave each
+  // (order <= AMMSE_GRAM_WAVE_N), else one at a time
+  const size_t gk = (ng <= (size_t)AMMSE_GRAM_WAVE_N) ? (size_t)C : 1;
+  L.Kg = o;  o += ammse_align256(gp * gk * ng * ng * cs);
   const size_t rp = (qp && real_bytes == 4) ? 1 : 0;
   L.X1 = o;  o += ammse_align256(rp * un * ud * cs);
   L.X2 = o;  o += ammse_align256(rp * un * ud * cs);

@@ -736,10 +736,11 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     });
   };
 
-  // lambda_max(A_c) on the stream side: with D = C C^H (C block diagonal,
+  // lambda_max(A_c) from a Gram matrix: with D = C C^H (C block diagonal,
   // N x d per user), A_c = R_c^H R_c for R_c = C^H S H_{:,c} ((U d) x M), so
-  // lambda_max(A_c) = lambda_max(K_c), K_c = R_c R_c^H ((U d) x (U d)).  R_c is
-  // formed in one pass over H_{:,c}, K_c by one MFMA product (made exactly
+  // lambda_max(A_c) = lambda_max(K_c) for K_c = R_c R_c^H ((U d) x (U d)) or
+  // K_c = A_c itself, whichever is smaller (ammse_gram_order).  R_c is formed
+  // in one pass over H_{:,c}, K_c by one MFMA product (made exactly
   // Hermitian), and each Lanczos step reads K_c once instead of H_{:,c} twice.
   auto gram_form = [&](int c, cx<R>* __restrict__ Kc) {
     const int tid = phase_tid();
@@ -758,20 +759,24 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     // square output: the 64 x 64 tile shape whatever the channel products
     // use; K made exactly Hermitian by taking the computed upper triangle
     // (its conjugate transpose below the diagonal, a real diagonal)
-    channel_gemm<R, false, true>(ud, ud, M, Rg, M, Rg, M, sm.tiles, false, 0,
-                                 [&](int i, int j, cx<R> v) {
-                                   if (i < j) {
-                                     Kc[(long)i * ud + j] = v;
-                                     Kc[(long)j * ud + i] = {v.x, -v.y};
-                                   } else if (i == j) {
-                                     Kc[(long)i * ud + j] = {v.x, (R)0};
-                                   }
-                                 });
+    const int ng = (int)ammse_gram_order(U, M, d);
+    auto epi = [&](int i, int j, cx<R> v) {
+      if (i < j) {
+        Kc[(long)i * ng + j] = v;
+        Kc[(long)j * ng + i] = {v.x, -v.y};
+      } else if (i == j) {
+        Kc[(long)i * ng + j] = {v.x, (R)0};
+      }
+    };
+    if (ng < ud)   // antenna side: R^H R
+      channel_gemm<R, true, false>(M, M, ud, Rg, M, Rg, M, sm.tiles, false, 0, epi);
+    else           // stream side: R R^H
+      channel_gemm<R, false, true>(ud, ud, M, Rg, M, Rg, M, sm.tiles, false, 0, epi);
     __syncthreads();
   };
   auto lanczos_gram = [&]() {   // on the K formed last (at Kg)
     const int tid = phase_tid();
-    const int ud = U * d;
+    const int ud = (int)ammse_gram_order(U, M, d);   // its order
     // w = K q with K Hermitian (column r read for row r, coalesced over r):
     // nparts threads per row, each over every nparts-th column, partial sums
     // combined through LDS (the product tiles, free here)
@@ -1288,9 +1293,10 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     if (adaptive) {
       // Gram path with order <= AMMSE_GRAM_WAVE_N: every K_c first (the whole
       // block on each), then one wave per BS runs its Lanczos iteration
-      const bool gw = gpath && U * d <= AMMSE_GRAM_WAVE_N;
+      const int ng = (int)ammse_gram_order(U, M, d);
+      const bool gw = gpath && ng <= AMMSE_GRAM_WAVE_N;
       for (int c = 0; c < C; ++c) {
-        if (sm.cu[c] != 0 && gpath) gram_form(c, gw ? Kg + (long)c * U * d * U * d : Kg);
+        if (sm.cu[c] != 0 && gpath) gram_form(c, gw ? Kg + (long)c * ng * ng : Kg);
         if (gw) continue;
         const double lm = (sm.cu[c] == 0) ? 0.0
                           : qpath ? lanczos_q()
@@ -1305,9 +1311,8 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
           float2* qs = (float2*)dyn_lds + wave * (AMMSE_GRAM_WAVE_N + 16);
           double2* tp = (double2*)((float2*)dyn_lds + 4 * (AMMSE_GRAM_WAVE_N + 16)) + wave * 64;
           for (int c = wave; c < C; c += AMMSE_BLOCK / 64) {
-            const int n = U * d;
             const double lm = (sm.cu[c] == 0) ? 0.0
-                              : wave_lanczos_lmax(Kg + (long)c * n * n, n, p.lanczos_steps, qs, tp);
+                              : wave_lanczos_lmax(Kg + (long)c * ng * ng, ng, p.lanczos_steps, qs, tp);
             if (lane == 0) sm.gamma[c] = (lm > 0.0) ? 1.0 / (2.0 * lm) : 0.0;
           }
           __syncthreads();
