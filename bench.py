@@ -41,10 +41,14 @@ HEX_REF_FILE = os.path.join(ROOT, "tests", "golden", "oracle_ref_hexcell7_b4096.
 LARGE_REF_FILE = os.path.join(ROOT, "tests", "golden", "oracle_ref_rayleigh_m256u64n2d2_b512.json")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ammse_solve_fp32_rayleigh_sweep1024_traffic.txt")
 HEX_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ammse_general_fp32_hexcell4096_traffic.txt")
+LARGE_PROFILES = {"fp32": os.path.join(ROOT, "profiles", "ammse_general_fp32_rayleigh_m256_b512_stats.txt"),
+                  "bf16_refined": os.path.join(ROOT, "profiles",
+                                               "ammse_general_bf16_rayleigh_m256_b512_stats.txt")}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2510_20507_amd", "csrc", f)
                   for f in ("ammse_fast.hip", "ammse_kernels.hip", "ammse_device.h",
                             "ammse_internal.h", "ammse_gemm.h")]
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 ITERS = 100
 CALIB_COPY_MIB = 1024
@@ -58,11 +62,10 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(path=None):
-    """HBM bytes per launch from a committed counter summary, if it was taken
-    on the current kernel source."""
-    path = path or TRAFFIC_FILE
-    if not os.path.exists(path):
+def read_profile_value(path, key):
+    """A `key = value` figure of a committed counter summary, if the summary
+    was taken on the current kernel source (else None)."""
+    if not path or not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):
@@ -72,9 +75,15 @@ def read_traffic(path=None):
     if vals.get("kernel_sha") != kernel_sha():
         return None
     try:
-        return float(vals["traffic_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
+
+
+def read_traffic(path=None):
+    """HBM bytes per launch from a committed counter summary, if it was taken
+    on the current kernel source."""
+    return read_profile_value(path or TRAFFIC_FILE, "traffic_bytes_per_launch")
 
 
 def cpu_baseline(batch, ref, per_p: int = 256):
@@ -175,10 +184,25 @@ def mixed_precision(reps: int = 2):
         ok = int(((w >= 0.99 * wm) & (st.cpu().numpy() == 0)).sum())
         t = float(np.mean(ms))
         err = np.abs(w[am_idx] - am) / am
+        bf = opts.precision == ammse.PREC_BF16
+        peak = PEAK_BF16_MFMA_TFLOPS if bf else PEAK_FP32_MFMA_TFLOPS
+        # HBM side: the channel streamed twice per iteration in the product type
+        alg_bytes = 2.0 * ITERS * float(batch.H.size) * (4.0 if bf else 8.0)
+        prof = LARGE_PROFILES.get(name)
         out[name] = {"kernel_ms": t, "instances_per_s_reached_99": ok / (t / 1e3),
                      "reached_99": ok, "achieved_tflops": flops / (t / 1e3) / 1e12,
                      "wsr_rel_err_vs_fp64_oracle_max": float(err.max()),
-                     "wsr_rel_err_vs_fp64_oracle_mean": float(err.mean())}
+                     "wsr_rel_err_vs_fp64_oracle_mean": float(err.mean()),
+                     "roofline": {"bound": "mfma", "achieved": flops / (t / 1e3) / 1e12,
+                                  "peak": peak, "unit": "TFLOP/s",
+                                  "frac": flops / (t / 1e3) / 1e12 / peak,
+                                  "hbm_algorithmic_bytes": alg_bytes,
+                                  "hbm_achieved_GBs": alg_bytes / (t / 1e3) / 1e9,
+                                  "hbm_frac": alg_bytes / (t / 1e3) / 1e9 / PEAK_HBM_GBS,
+                                  "traffic": read_profile_value(prof, "traffic_bytes_per_launch"),
+                                  "mfma_busy": read_profile_value(prof, "mfma_busy_fraction"),
+                                  "kernel": "ammse_solve_kernel<float> (general, single-cell Q path"
+                                            + (", bfloat16 products)" if bf else ", float products)")}}
         plan.close()
     out["speedup_bf16_refined_vs_fp32"] = out["fp32"]["kernel_ms"] / out["bf16_refined"]["kernel_ms"]
     return out
