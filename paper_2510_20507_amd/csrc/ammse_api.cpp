@@ -14,6 +14,7 @@ struct ammse_plan_s {
   int32_t device = 0;
   int32_t batch = 0;
   int32_t use_fast = 0;
+  int32_t n_qp = 0;            // launch positions [0, n_qp): the general kernel's Q path
   ammse_options_t opt{};
   size_t ws_bytes = 0;
   ammse_desc_t* d_desc = nullptr;
@@ -179,8 +180,19 @@ ammse_status_t ammse_plan_create(ammse_plan_t* plan, int32_t device,
     const ammse_instance_t& t = table[i];
     cost[i] = (double)t.C * t.U * t.N * (double)t.M * t.U * t.d;
   }
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+  // general kernel: the instances of its single-cell Q path first (they run in
+  // their own kernel variant), each group by decreasing work
+  std::vector<char> qpi(batch);
+  for (int32_t i = 0; i < batch; ++i) {
+    const ammse_instance_t& t = table[i];
+    qpi[i] = ammse_qpath_instance(t.C, t.U, t.M, t.N, o.algorithm) ? 1 : 0;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    if (qpi[a] != qpi[b]) return qpi[a] > qpi[b];
+    return cost[a] > cost[b];
+  });
+  int32_t n_qp = 0;
+  for (int32_t i = 0; i < batch; ++i) n_qp += qpi[i];
 
   bool fast = (o.precision == AMMSE_PREC_FP32) && (o.path == AMMSE_PATH_AUTO) &&
               (o.algorithm == AMMSE_ALGO_AMMMSE);
@@ -239,6 +251,7 @@ ammse_status_t ammse_plan_create(ammse_plan_t* plan, int32_t device,
   P->device = device;
   P->batch = batch;
   P->use_fast = fast ? 1 : 0;
+  P->n_qp = n_qp;
   P->opt = o;
   P->opt.lanczos_steps = ls;
   // the LDS-resident kernel keeps its state on chip; its workspace holds the
@@ -314,6 +327,7 @@ static void fill_common(ammse_plan_t plan, ammse_kparams_t& k) {
   k.desc = plan->d_desc;
   k.cell_users = plan->d_cell_users;
   k.batch = plan->batch;
+  k.n_qp = plan->n_qp;
   k.max_iters = o.max_iters;
   k.T_c = o.T_c;
   k.warm_start = o.warm_start;
@@ -438,6 +452,13 @@ ammse_status_t ammse_autotune(ammse_plan_t plan, const void* H, const double* si
     std::vector<ammse_desc_t> sample;
     const size_t ns = std::min<size_t>(pos.size(), nsample_max);
     for (size_t q = 0; q < ns; ++q) sample.push_back(plan->h_desc[pos[q * pos.size() / ns]]);
+    // Q-path instances first, as in the plan's launch order
+    std::stable_partition(sample.begin(), sample.end(), [&](const ammse_desc_t& d) {
+      return ammse_qpath_instance(d.C, d.U, d.M, d.N, plan->opt.algorithm);
+    });
+    int32_t sample_qp = 0;
+    for (const auto& d : sample)
+      sample_qp += ammse_qpath_instance(d.C, d.U, d.M, d.N, plan->opt.algorithm) ? 1 : 0;
     float best_ms = 0.f;
     for (int v = 0; v < AMMSE_TILE_SHAPES && st == AMMSE_OK; ++v) {
       for (auto& d : sample) d.tile = v;
@@ -450,6 +471,7 @@ ammse_status_t ammse_autotune(ammse_plan_t plan, const void* H, const double* si
       fill_common(plan, k);
       k.desc = dd;
       k.batch = (int32_t)ns;
+      k.n_qp = sample_qp;
       k.max_iters = std::min(plan->opt.max_iters, 8);
       k.trace_len = k.max_iters + 1;
       if (k.lowp_iters >= 0) k.lowp_iters = std::max(0, k.max_iters - std::min(plan->opt.refine_iters, 2));

@@ -29,6 +29,7 @@ struct ammse_ws_layout_t {
   size_t Tm;                  // WMMSE: S D S H_{:,c} or R = C^H S H_{:,c} ((U N) x M,
                               // double complex)
   size_t Qm;                  // S H H^H S ((U N) x (U N), storage precision), see below
+  size_t Kq;                  // Q path: K = C^H Q C of the step-size Lanczos ((U N) x (U N))
   size_t Hb, Xb, Zb;          // bfloat16 copies of H, X and Z (mixed precision only)
   size_t Dmf, Ymf;            // float copies of Dm, Ym (float storage only)
   size_t Lwm, Lim, Cm;        // per-user Lw, Lw^{-1}, C (double complex 4 x 4): WMMSE,
@@ -82,6 +83,9 @@ struct ammse_kparams_t {
                          // (and G^0 when lowp_iters >= 1); -1: float products only
   int32_t tile_force;    // 0: per-instance tile shape from the descriptor; v + 1: shape v
   int32_t step_rule;     // AMMSE_STEP_BOUND / AMMSE_STEP_FROZEN
+  int32_t n_qp;          // general kernel: launch positions [0, n_qp) hold the instances
+                         // of the single-cell Q path (ammse_qpath_instance)
+  int32_t block_base;    // launch position of workgroup 0 of a general-kernel launch
   int32_t bound_pre;     // general kernel: the stage-II bound of the instances that
                          // ammse_bound_gram selects was written to their workspace by
                          // ammse_bound_gram_kernel before this launch
@@ -99,6 +103,12 @@ struct ammse_kparams_t {
 // `real_bytes` per component (8 for FP64, 4 for FP32).  Every sub-buffer
 // starts on a 256-byte boundary.
 __host__ __device__ inline size_t ammse_align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Algorithm 3 on a single cell with U N <= M: the one-product Q path of the
+// general kernel (its own kernel variant, its instances first in launch order).
+__host__ __device__ inline bool ammse_qpath_instance(int C, int U, int M, int N, int algorithm) {
+  return algorithm == AMMSE_ALGO_AMMMSE && C == 1 && (long)U * N <= M;
+}
 
 // Order of the Gram matrix of the step-size Lanczos: with D = C C^H and
 // R_c = C^H S H_{:,c} ((U d) x M), lambda_max(H_{:,c}^H S D S H_{:,c}) is the
@@ -164,6 +174,7 @@ __host__ __device__ inline ammse_ws_layout_t ammse_ws_layout(int real_bytes, int
   // Algorithm 3, single cell with U N <= M: Lanczos on Q = S H H^H S
   const size_t qp = (!wmmse && !bcgd && C == 1 && un <= (size_t)M) ? 1 : 0;
   L.Qm = o;  o += ammse_align256(qp * un * un * cs);
+  L.Kq = o;  o += ammse_align256(qp * un * un * cs);
   // Algorithm 3 otherwise, float storage, when the (U d) x (U d) Gram matrix
   // is smaller than two passes over H_{:,c}: Lanczos on K = R R^H (gp above)
   L.Lwm = o; o += ammse_align256(w * (size_t)U * 16 * zs);

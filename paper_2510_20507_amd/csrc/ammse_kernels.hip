@@ -178,6 +178,33 @@ static_assert((AMMSE_BLOCK / 64) * ((AMMSE_GRAM_WAVE_N + 16) * sizeof(float2) + 
                   3 * AMMSE_LANCZOS_LDS_N * sizeof(zd),
               "the per-wave Gram Lanczos buffers fit the A-MMMSE dynamic LDS");
 
+// K = C^H Q C ((U N) x (U N)) for the Q-path Lanczos, C block diagonal with an
+// N x N block per user (Cm: 4 x 4 padded, double), Q exactly Hermitian: one
+// thread per entry of the blocks on and above the diagonal, the conjugate
+// written to the mirrored entry, so K is exactly Hermitian.  A function of
+// its own so that its restrict-qualified pointers let the loads of an entry
+// be issued ahead of the previous entry's stores.
+template <class R>
+__device__ __forceinline__ void kq_form(const cx<R>* __restrict__ Q, const zd* __restrict__ Cm,
+                                        cx<R>* __restrict__ K, int U, int N, int tid) {
+  const int un = U * N;
+  for (int e = tid; e < un * un; e += AMMSE_BLOCK) {
+    const int i = e / un, j = e - i * un;
+    const int u = i / N, a = i - u * N, v = j / N, b = j - v * N;
+    if (u > v || (u == v && a > b)) continue;
+    zd acc = {0.0, 0.0};
+    for (int k = 0; k < N; ++k) {
+      zd t = {0.0, 0.0};
+      for (int l = 0; l < N; ++l)
+        t = t + to_d(Q[(long)(u * N + k) * un + v * N + l]) * Cm[v * 16 + l * 4 + b];
+      acc = acc + cj(Cm[u * 16 + k * 4 + a]) * t;
+    }
+    if (i == j) acc.y = 0.0;
+    K[(long)i * un + j] = from_d<R>(acc);
+    if (i != j) K[(long)j * un + i] = from_d<R>(cj(acc));
+  }
+}
+
 // Stage-II step of the bound rule for the general kernel's instances that
 // ammse_bound_gram selects (float storage, not the single-cell Q path,
 // M <= AMMSE_GRAM_WAVE_N): for every BS c with users, 1 / (2 lambda_max(A_c)),
@@ -250,12 +277,26 @@ __global__ __launch_bounds__(AMMSE_BLOCK, 2) void ammse_bound_gram_kernel(ammse_
 // ---------------------------------------------------------------------------
 // The fused kernel
 // ---------------------------------------------------------------------------
-template <class R>
+// QP = 1: the instances of the single-cell Q path (ammse_qpath_instance), QP =
+// 0: all others; the plan puts the former first in launch order and each
+// variant runs over its own range (block_base), so that neither carries the
+// other's code.
+template <class R, int QP>
 __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_solve_kernel(
     ammse_kparams_t p) {
   __shared__ Smem<R> sm;
   extern __shared__ __align__(16) char dyn_lds[];   // WMMSE / MMMSE: Cholesky factor
-  const ammse_desc_t D = p.desc[blockIdx.x];
+  const ammse_desc_t D = p.desc[p.block_base + blockIdx.x];
+  if constexpr (QP != 0) {
+    if (!ammse_qpath_instance(D.C, D.U, D.M, D.N, p.algorithm)) {
+      // not an instance of this variant (the plan never launches one here)
+      if (threadIdx.x == 0) {
+        p.wsr[D.b] = NAN;
+        if (p.status) p.status[D.b] = AMMSE_INST_NONFINITE;
+      }
+      return;
+    }
+  }
   // output tile shape of the channel products: forced by the options, else
   // the plan's (autotuned) choice for this instance's shape class
   const int tile = (p.tile_force > 0) ? p.tile_force - 1 : D.tile;
@@ -290,7 +331,8 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   // exact V step (Algorithm 2 / MMMSE); BCGD-WMMSE (explicit steps for U, W, V)
   const bool wm = p.algorithm == AMMSE_ALGO_WMMSE || p.algorithm == AMMSE_ALGO_MMMSE;
   const bool bc = p.algorithm == AMMSE_ALGO_BCGD;
-  const bool qpath = C == 1 && un <= M && !wm && !bc;   // stream-space Lanczos with Q = S H H^H S
+  // stream-space Lanczos with Q = S H H^H S, one product with Q per iteration
+  const bool qpath = QP != 0;
   const bool gpath = ammse_gram_path((int)sizeof(R), C, U, M, N, d, wm || bc);   // ... K = R R^H
   // float storage on the Q path: one product with Q per iteration, the
   // precoder carried implicitly as V = c V^0 + H^H S X (see the update below);
@@ -322,6 +364,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   zd* Xm = (zd*)(ws + L.Xm);
   zd* Tm = (zd*)(ws + L.Tm);
   cx<R>* Qm = (cx<R>*)(ws + L.Qm);
+  cx<R>* Kq = (cx<R>*)(ws + L.Kq);
   bfc* Hb = (bfc*)(ws + L.Hb);     // bfloat16 operand copies (mixed precision)
   bfc* Xb = (bfc*)(ws + L.Xb);
   bfc* Zb = (bfc*)(ws + L.Zb);
@@ -707,35 +750,6 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     });
   };
 
-  // Single cell with U N <= M: the same lambda_max on the (U N)-dimensional
-  // operator K = C^H Q C, D = C C^H per user and Q = S H H^H S (formed once
-  // per solve), which reads Q once per step instead of H twice.
-  auto lanczos_q = [&]() {
-    const int tid = phase_tid();
-    return lanczos_core(un, [&](const zd* qv, zd* wv) {
-      for (int r = tid; r < un; r += AMMSE_BLOCK) {   // u = C x
-        const int u = r / N, n = r - u * N;
-        zd acc = {0.0, 0.0};
-        for (int k = 0; k < N; ++k) acc = acc + Cm[u * 16 + n * 4 + k] * qv[u * N + k];
-        Ly1[r] = acc;
-      }
-      __syncthreads();
-      for (int r = tid; r < un; r += AMMSE_BLOCK) {   // z = Q u (Q Hermitian: column r)
-        zd acc = {0.0, 0.0};
-#pragma unroll 8
-        for (int c2 = 0; c2 < un; ++c2) acc = acc + cj(to_d(Qm[(long)c2 * un + r])) * Ly1[c2];
-        Ly2[r] = acc;
-      }
-      __syncthreads();
-      for (int r = tid; r < un; r += AMMSE_BLOCK) {   // w = C^H z
-        const int u = r / N, n = r - u * N;
-        zd acc = {0.0, 0.0};
-        for (int k = 0; k < N; ++k) acc = acc + cj(Cm[u * 16 + k * 4 + n]) * Ly2[u * N + k];
-        wv[r] = acc;
-      }
-    });
-  };
-
   // lambda_max(A_c) from a Gram matrix: with D = C C^H (C block diagonal,
   // N x d per user), A_c = R_c^H R_c for R_c = C^H S H_{:,c} ((U d) x M), so
   // lambda_max(A_c) = lambda_max(K_c) for K_c = R_c R_c^H ((U d) x (U d)) or
@@ -774,9 +788,13 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       channel_gemm<R, false, true>(ud, ud, M, Rg, M, Rg, M, sm.tiles, false, 0, epi);
     __syncthreads();
   };
-  auto lanczos_gram = [&]() {   // on the K formed last (at Kg)
+  // Lanczos on a formed Hermitian matrix of order ud (storage precision,
+  // row-major; column r read for row r, coalesced over r).
+  // (loads in flight per thread: 16 float or 8 double entries, which keeps
+  // the FP64 kernel within 256 registers)
+  constexpr int kDenseUnroll = sizeof(R) == 4 ? 16 : 8;
+  auto lanczos_dense = [&](const cx<R>* Kd, int ud) __attribute__((always_inline)) {
     const int tid = phase_tid();
-    const int ud = (int)ammse_gram_order(U, M, d);   // its order
     // w = K q with K Hermitian (column r read for row r, coalesced over r):
     // nparts threads per row, each over every nparts-th column, partial sums
     // combined through LDS (the product tiles, free here)
@@ -786,8 +804,8 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       if (nparts == 1) {
         for (int r = tid; r < ud; r += AMMSE_BLOCK) {
           zd acc = {0.0, 0.0};
-#pragma unroll 16
-          for (int c2 = 0; c2 < ud; ++c2) acc = acc + cj(to_d(Kg[(long)c2 * ud + r])) * qv[c2];
+#pragma unroll kDenseUnroll
+          for (int c2 = 0; c2 < ud; ++c2) acc = acc + cj(to_d(Kd[(long)c2 * ud + r])) * qv[c2];
           wv[r] = acc;
         }
         return;
@@ -795,9 +813,9 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       const int r = tid % ud, part = tid / ud;
       if (part < nparts) {
         zd acc = {0.0, 0.0};
-#pragma unroll 16
+#pragma unroll kDenseUnroll
         for (int c2 = part; c2 < ud; c2 += nparts)
-          acc = acc + cj(to_d(Kg[(long)c2 * ud + r])) * qv[c2];
+          acc = acc + cj(to_d(Kd[(long)c2 * ud + r])) * qv[c2];
         partial[part * ud + r] = acc;
       }
       __syncthreads();
@@ -807,6 +825,15 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
         wv[rr] = acc;
       }
     });
+  };
+
+  // Single cell with U N <= M: the same lambda_max on the (U N)-dimensional
+  // matrix K = C^H Q C (D = C C^H per user, Q = S H H^H S formed once per
+  // solve), formed per call; each Lanczos step reads it once.
+  auto lanczos_q = [&]() __attribute__((always_inline)) {
+    kq_form<R>(Qm, Cm, Kq, U, N, phase_tid());
+    __syncthreads();
+    return lanczos_dense(Kq, un);
   };
 
   // The iterate V^t is kept as scur_c * Xc (per BS c) and V^{t-1} as
@@ -1300,7 +1327,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
         if (gw) continue;
         const double lm = (sm.cu[c] == 0) ? 0.0
                           : qpath ? lanczos_q()
-                          : gpath ? lanczos_gram()
+                          : gpath ? lanczos_dense(Kg, (int)ammse_gram_order(U, M, d))
                                   : lanczos_lmax(c);
         if (tid == 0) sm.gamma[c] = (lm > 0.0) ? 1.0 / (2.0 * lm) : 0.0;
         __syncthreads();
@@ -1631,8 +1658,11 @@ hipError_t launch_general(const ammse_kparams_t& p0, hipStream_t s) {
     // FP32: factor and solution block (128 KiB); FP64 (larger static tiles): factor only
     dyn = sizeof(zd) * 64 * 64 * (sizeof(R) == 4 ? 2 : 1);
     if (!attr_set) {
-      hipError_t e = hipFuncSetAttribute((const void*)ammse_solve_kernel<R>,
+      hipError_t e = hipFuncSetAttribute((const void*)ammse_solve_kernel<R, 0>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)ammse_solve_kernel<R, 1>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
       if (e != hipSuccess) return e;
       attr_set = true;
     }
@@ -1641,6 +1671,7 @@ hipError_t launch_general(const ammse_kparams_t& p0, hipStream_t s) {
     p.lds_factor = 0;
   }
   p.bound_pre = 0;
+  p.block_base = 0;
   if constexpr (sizeof(R) == 4) {
     // the stage-II bound of the instances that ammse_bound_gram selects
     // (the kernel returns at once for the others)
@@ -1650,7 +1681,14 @@ hipError_t launch_general(const ammse_kparams_t& p0, hipStream_t s) {
       p.bound_pre = 1;
     }
   }
-  hipLaunchKernelGGL(ammse_solve_kernel<R>, dim3(p.batch), dim3(AMMSE_BLOCK), dyn, s, p);
+  // the Q-path instances (launch positions [0, n_qp)), then the others
+  if (p.n_qp > 0)
+    hipLaunchKernelGGL((ammse_solve_kernel<R, 1>), dim3(p.n_qp), dim3(AMMSE_BLOCK), dyn, s, p);
+  if (p.batch > p.n_qp) {
+    p.block_base = p.n_qp;
+    hipLaunchKernelGGL((ammse_solve_kernel<R, 0>), dim3(p.batch - p.n_qp), dim3(AMMSE_BLOCK), dyn,
+                       s, p);
+  }
   return hipGetLastError();
 }
 
