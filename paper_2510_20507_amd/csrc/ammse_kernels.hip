@@ -760,14 +760,36 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     const int tid = phase_tid();
     const cx<R>* __restrict__ Hc = H + (long)c * un * M;
     const int ud = U * d;
-    for (int e = tid; e < ud * M; e += AMMSE_BLOCK) {
-      const int i = e / M, m = e - i * M;
-      const int u = i / d, s = i - u * d;
-      zd acc = {0.0, 0.0};
-      for (int n = 0; n < N; ++n)
-        acc = acc + cj(Cm[u * 16 + n * 4 + s]) * to_d(Hc[(long)(u * N + n) * M + m]);
-      const double f = sm.invsig[u];
-      Rg[e] = {(R)(f * acc.x), (R)(f * acc.y)};
+    // two elements per trip, all loads of both issued before their arithmetic
+    // (the stores to R would otherwise order each trip's loads after the
+    // previous trip's store)
+    for (int e0 = tid; e0 < ud * M; e0 += 2 * AMMSE_BLOCK) {
+      cx<R> hv[2][4];
+      zd cv[2][4];
+      int uu[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int e = min(e0 + q * AMMSE_BLOCK, ud * M - 1);
+        const int i = e / M, m = e - i * M;
+        const int u = i / d, s = i - u * d;
+        uu[q] = u;
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+          const int nn = min(n, N - 1);
+          hv[q][n] = Hc[(long)(u * N + nn) * M + m];
+          cv[q][n] = Cm[u * 16 + nn * 4 + s];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int e = e0 + q * AMMSE_BLOCK;
+        zd acc = {0.0, 0.0};
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+          if (n < N) acc = acc + cj(cv[q][n]) * to_d(hv[q][n]);
+        const double f = sm.invsig[uu[q]];
+        if (e < ud * M) Rg[e] = {(R)(f * acc.x), (R)(f * acc.y)};
+      }
     }
     __syncthreads();
     // square output: the 64 x 64 tile shape whatever the channel products
