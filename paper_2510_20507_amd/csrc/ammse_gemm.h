@@ -322,11 +322,188 @@ __device__ void block_gemm_mfma(int m, int n, int k, const TA* __restrict__ A, l
   __syncthreads();
 }
 
+// Products with few output rows (m <= 32: the gradient products and the
+// antenna-side Gram matrices of small-antenna instances), where the tile
+// shapes above (64 or 128 rows) would spend most of their MFMA work on padding
+// rows: output tiles of TM = 16 TMB rows and TN = 16 TNB columns, one 16 x 16
+// block per group of waves, and the k-chunks of a step split over the
+// KS = 4 / (TMB TNB) groups (each group's chunk in its own LDS slot); at the
+// end of a tile the groups' partial accumulators are summed through LDS
+// before the epilogue.  Same staging, conversion and prefetch as above.
+template <class T, int TMB, int TNB, bool CONJA, bool CONJB, class Epi, class TA, class TB>
+__device__ void block_gemm_mfma_ks(int m, int n, int k, const TA* __restrict__ A, long lda,
+                                   const TB* __restrict__ B, long ldb, char* lds, Epi&& epi) {
+  constexpr bool LOW = sizeof(T) == 2;
+  constexpr int KC = LOW ? 32 : 16, LD = LOW ? KC + 8 : KC + 1;
+  constexpr int TM = 16 * TMB, TN = 16 * TNB, NBLK = TMB * TNB, KS = 4 / NBLK;
+  constexpr int CH_A = TM * KC, CH_B = KC * TN;               // elements per chunk
+  constexpr int NA = KS * CH_A / AMMSE_BLOCK, NB = KS * CH_B / AMMSE_BLOCK;
+  constexpr int SLOT = 2 * (TM + TN) * LD;                     // T elements per slot
+  static_assert(KS * NBLK == 4 && NA >= 1 && NB >= 1, "four waves, every thread stages");
+  static_assert(KS * SLOT * sizeof(T) <= tile_bytes<float>(), "slots fit the tile area");
+  static_assert(4 * 64 * 12 * sizeof(float) <= tile_bytes<float>(), "partials fit the tile area");
+  T* base = (T*)lds;
+  const int tid = phase_tid();
+  const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  const int blk = wave % NBLK, kg = wave / NBLK;
+  const int rbk = blk / TNB, cbk = blk % TNB;
+  const int ntn = (n + TN - 1) / TN, nk = (k + KC - 1) / KC;
+  const int nks = (nk + KS - 1) / KS;                          // steps per tile
+  const int steps = ((m + TM - 1) / TM) * ntn * nks;
+  auto a_rk = [&](int q, int& slot, int& row, int& kk) {
+    const int e = tid + AMMSE_BLOCK * q;
+    slot = e / CH_A;
+    const int f = e - slot * CH_A;
+    if (CONJA) {
+      row = f % TM;
+      kk = f / TM;
+    } else {
+      kk = f % KC;
+      row = f / KC;
+    }
+  };
+  auto b_ck = [&](int q, int& slot, int& col, int& kk) {
+    const int e = tid + AMMSE_BLOCK * q;
+    slot = e / CH_B;
+    const int f = e - slot * CH_B;
+    if (CONJB) {
+      kk = f % KC;
+      col = f / KC;
+    } else {
+      col = f % TN;
+      kk = f / TN;
+    }
+  };
+  TA ra[NA];
+  TB rb[NB];
+  auto fetch = [&](int s) {
+    const int tile = s / nks, c0 = (s - tile * nks) * KS;       // first chunk of the step
+    const int i0 = (tile / ntn) * TM, j0 = (tile % ntn) * TN;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      int slot, row, kk;
+      a_rk(q, slot, row, kk);
+      const int gi = i0 + row, gk = (c0 + slot) * KC + kk;
+      ra[q] = TA{};
+      if (gi < m && gk < k) ra[q] = CONJA ? A[(long)gk * lda + gi] : A[(long)gi * lda + gk];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      int slot, col, kk;
+      b_ck(q, slot, col, kk);
+      const int gj = j0 + col, gk = (c0 + slot) * KC + kk;
+      rb[q] = TB{};
+      if (gj < n && gk < k) rb[q] = CONJB ? B[(long)gj * ldb + gk] : B[(long)gk * ldb + gj];
+    }
+  };
+  floatx4_t P[3];
+  fetch(0);
+  for (int s = 0; s < steps; ++s) {
+    const int tile = s / nks, kc = s - tile * nks;
+    if (kc == 0) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) P[q] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    }
+    __syncthreads();   // the previous step's products (and partial sums) are done with LDS
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      int slot, row, kk;
+      a_rk(q, slot, row, kk);
+      const cx<float> va = to_f(ra[q]);
+      T* As = base + slot * SLOT;
+      As[row * LD + kk] = (T)va.x;
+      As[TM * LD + row * LD + kk] = (T)(CONJA ? -va.y : va.y);
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      int slot, col, kk;
+      b_ck(q, slot, col, kk);
+      const cx<float> vb = to_f(rb[q]);
+      T* Bs = base + slot * SLOT + 2 * TM * LD;
+      Bs[col * LD + kk] = (T)vb.x;
+      Bs[TN * LD + col * LD + kk] = (T)(CONJB ? -vb.y : vb.y);
+    }
+    __syncthreads();
+    if (s + 1 < steps) fetch(s + 1);
+    const T* AsR = base + kg * SLOT;
+    const T* AsI = AsR + TM * LD;
+    const T* BsR = AsI + TM * LD;
+    const T* BsI = BsR + TN * LD;
+    if constexpr (LOW) {
+      const int ar = (16 * rbk + li) * LD + 8 * lk, br = (16 * cbk + li) * LD + 8 * lk;
+      const bf16x8_t axr = *(const bf16x8_t*)(AsR + ar), axi = *(const bf16x8_t*)(AsI + ar);
+      const bf16x8_t bxr = *(const bf16x8_t*)(BsR + br), bxi = *(const bf16x8_t*)(BsI + br);
+      P[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(axr, bxr, P[0], 0, 0, 0);
+      P[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(axi, bxi, P[1], 0, 0, 0);
+      P[2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(axr, bxi, P[2], 0, 0, 0);
+      P[2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(axi, bxr, P[2], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < KC; kk += 4) {
+        const int ar = (16 * rbk + li) * LD + kk + lk, br = (16 * cbk + li) * LD + kk + lk;
+        const float axr = AsR[ar], axi = AsI[ar], bxr = BsR[br], bxi = BsI[br];
+        P[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(axr, bxr, P[0], 0, 0, 0);
+        P[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(axi, bxi, P[1], 0, 0, 0);
+        P[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(axr, bxi, P[2], 0, 0, 0);
+        P[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(axi, bxr, P[2], 0, 0, 0);
+      }
+    }
+    if (kc == nks - 1) {
+      if constexpr (KS > 1) {   // sum the k-groups' partials into group 0
+        float* red = (float*)lds;
+        __syncthreads();        // every wave is done reading the tiles
+        if (kg > 0) {
+#pragma unroll
+          for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[(wave * 12 + q * 4 + r) * 64 + lane] = P[q][r];
+        }
+        __syncthreads();
+        if (kg == 0) {
+#pragma unroll
+          for (int g = 1; g < KS; ++g)
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) P[q][r] += red[((blk + g * NBLK) * 12 + q * 4 + r) * 64 + lane];
+        }
+      }
+      if (kg == 0) {
+        const int i0 = (tile / ntn) * TM, j0 = (tile % ntn) * TN;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gi = i0 + 16 * rbk + 4 * lk + r, gj = j0 + 16 * cbk + li;
+          if (gi < m && gj < n) epi(gi, gj, cx<float>{P[0][r] - P[1][r], P[2][r]});
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // MFMA product with the tile shape chosen at run time (uniform per workgroup).
+// Products of the form op(A) = A^H with m <= 32 output rows take the k-split
+// small-row tiles instead.
 template <class T, bool CONJA, bool CONJB, class Epi, class TA, class TB>
 __device__ __forceinline__ void mfma_dispatch(int m, int n, int k, const TA* A, long lda,
                                               const TB* B, long ldb, char* tiles, int tile,
                                               Epi&& epi) {
+  if constexpr (CONJA && !CONJB) {
+    if (m <= 32) {
+      if (m <= 16) {
+        if (n <= 16)
+          block_gemm_mfma_ks<T, 1, 1, CONJA, CONJB>(m, n, k, A, lda, B, ldb, tiles, epi);
+        else
+          block_gemm_mfma_ks<T, 1, 2, CONJA, CONJB>(m, n, k, A, lda, B, ldb, tiles, epi);
+      } else {
+        if (n <= 16)
+          block_gemm_mfma_ks<T, 2, 1, CONJA, CONJB>(m, n, k, A, lda, B, ldb, tiles, epi);
+        else
+          block_gemm_mfma_ks<T, 2, 2, CONJA, CONJB>(m, n, k, A, lda, B, ldb, tiles, epi);
+      }
+      return;
+    }
+  }
   if (tile == 1)
     block_gemm_mfma<T, 1, CONJA, CONJB>(m, n, k, A, lda, B, ldb, tiles, epi);
   else if (tile == 2)
