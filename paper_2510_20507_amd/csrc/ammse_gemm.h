@@ -35,6 +35,9 @@ template <int V> struct TileShape;
 template <> struct TileShape<0> { static constexpr int TM = 64, TN = 64; };
 template <> struct TileShape<1> { static constexpr int TM = 128, TN = 16; };
 template <> struct TileShape<2> { static constexpr int TM = 64, TN = 32; };
+// 3: 64 x 16 (each wave one row block, one column block): not an autotuner
+//    choice; the products with 33-64 output rows and at most 16 columns take it
+template <> struct TileShape<3> { static constexpr int TM = 64, TN = 16; };
 
 template <class T, int V>
 struct MfmaTile {
@@ -483,7 +486,7 @@ __device__ void block_gemm_mfma_ks(int m, int n, int k, const TA* __restrict__ A
 
 // MFMA product with the tile shape chosen at run time (uniform per workgroup).
 // Products of the form op(A) = A^H with m <= 32 output rows take the k-split
-// small-row tiles instead.
+// small-row tiles instead, and those with m <= 64 a 64-row tile.
 template <class T, bool CONJA, bool CONJB, class Epi, class TA, class TB>
 __device__ __forceinline__ void mfma_dispatch(int m, int n, int k, const TA* A, long lda,
                                               const TB* B, long ldb, char* tiles, int tile,
@@ -501,6 +504,12 @@ __device__ __forceinline__ void mfma_dispatch(int m, int n, int k, const TA* A, 
         else
           block_gemm_mfma_ks<T, 2, 2, CONJA, CONJB>(m, n, k, A, lda, B, ldb, tiles, epi);
       }
+      return;
+    }
+    // 64-row tiles: the autotuned 128 x 16 shape would be half padding
+    if (m <= 64) tile = (n <= 16) ? 3 : 2;
+    if (tile == 3) {
+      block_gemm_mfma<T, 3, CONJA, CONJB>(m, n, k, A, lda, B, ldb, tiles, epi);
       return;
     }
   }
