@@ -485,14 +485,14 @@ __device__ void block_gemm_mfma_ks(int m, int n, int k, const TA* __restrict__ A
 }
 
 // MFMA product with the tile shape chosen at run time (uniform per workgroup).
-// Products of the form op(A) = A^H with m <= 32 output rows take the k-split
-// small-row tiles instead, and those with m <= 64 a 64-row tile.
+// Products with B not conjugated and m <= 64 output rows take a 64-row tile,
+// and those of the form op(A) = A^H with m <= 32 the k-split small-row tiles.
 template <class T, bool CONJA, bool CONJB, class Epi, class TA, class TB>
 __device__ __forceinline__ void mfma_dispatch(int m, int n, int k, const TA* A, long lda,
                                               const TB* B, long ldb, char* tiles, int tile,
                                               Epi&& epi) {
-  if constexpr (CONJA && !CONJB) {
-    if (m <= 32) {
+  if constexpr (!CONJB) {
+    if (CONJA && m <= 32) {
       if (m <= 16) {
         if (n <= 16)
           block_gemm_mfma_ks<T, 1, 1, CONJA, CONJB>(m, n, k, A, lda, B, ldb, tiles, epi);
