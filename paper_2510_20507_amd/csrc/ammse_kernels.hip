@@ -436,22 +436,40 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       const bool act = u < U;
       const int uu = act ? u : U - 1;
       const int cown = sm.cellOf[uu], j0 = sm.local[uu] * d;
-      // J-: lane li accumulates all N x N entries over the columns
-      // j = li (mod 16) of the other streams, then a reduce-scatter over the
-      // 16 lanes leaves entry (a, b) on lane 4a + b.
-      zd sj[16];
+      // J-: lane li accumulates all N x N entries over the stream columns
+      // t = li (mod 16) of the other streams (t runs over the per-BS blocks
+      // one after the other), then a reduce-scatter over the 16 lanes leaves
+      // entry (a, b) on lane 4a + b.  The sums are in the storage precision's
+      // working type (float with float storage, as in the LDS-resident
+      // kernel), scaled by gscale^2 at the end, and the loads of the lane's
+      // next column are issued before the current column's arithmetic.
+      using TJ = typename std::conditional<sizeof(R) == 4, float, double>::type;
+      cx<TJ> sj[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) sj[q] = {0.0, 0.0};
-      for (int c = 0; c < C; ++c) {
-        const int nc = sm.cu[c] * d;
-        const cx<R>* __restrict__ r0 = G + (long)un * sm.colOff[c] + (long)(uu * N) * nc;
-        const bool oc = c == cown;
-        for (int j = li; j < nc; j += 16) {
-          if (oc && j >= j0 && j < j0 + d) continue;
-          zd g[AMMSE_MAX_RX];
+      for (int q = 0; q < 16; ++q) sj[q] = {TJ(0), TJ(0)};
+      {
+        const int nstr = sm.colOff[C];
+        int t = li, c = 0;
+        while (c < C - 1 && t >= sm.colOff[c + 1]) ++c;   // BS of column t
+        cx<R> gn[AMMSE_MAX_RX];
+        auto load = [&](int tt, int cc) {
+          const int nc = sm.cu[cc] * d;
+          const cx<R>* __restrict__ r0 =
+              G + (long)un * sm.colOff[cc] + (long)(uu * N) * nc + (tt - sm.colOff[cc]);
 #pragma unroll
           for (int k = 0; k < AMMSE_MAX_RX; ++k)
-            g[k] = (k < N) ? scal(gscale, to_d(r0[(long)k * nc + j])) : zd{0.0, 0.0};
+            gn[k] = (k < N) ? r0[(long)k * nc] : cx<R>{R(0), R(0)};
+        };
+        if (t < nstr) load(t, c);
+        while (t < nstr) {
+          cx<TJ> g[AMMSE_MAX_RX];
+#pragma unroll
+          for (int k = 0; k < AMMSE_MAX_RX; ++k) g[k] = {(TJ)gn[k].x, (TJ)gn[k].y};
+          const bool own = c == cown && t - sm.colOff[c] >= j0 && t - sm.colOff[c] < j0 + d;
+          t += 16;
+          while (c < C - 1 && t >= sm.colOff[c + 1]) ++c;
+          if (t < nstr) load(t, c);
+          if (own) continue;
 #pragma unroll
           for (int x = 0; x < AMMSE_MAX_RX; ++x)
 #pragma unroll
@@ -465,13 +483,13 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
         const bool hi = (li & bit) != 0;
 #pragma unroll
         for (int q = 0; q < bit; ++q) {
-          const zd send = hi ? sj[q] : sj[q + bit];
-          const zd keep = hi ? sj[q + bit] : sj[q];
-          sj[q] = keep + zd{__shfl_xor(send.x, bit, 64), __shfl_xor(send.y, bit, 64)};
+          const cx<TJ> send = hi ? sj[q] : sj[q + bit];
+          const cx<TJ> keep = hi ? sj[q + bit] : sj[q];
+          sj[q] = keep + cx<TJ>{__shfl_xor(send.x, bit, 64), __shfl_xor(send.y, bit, 64)};
         }
       }
       zd J = {(ea == eb) ? 1.0 : 0.0, 0.0}, F = {0.0, 0.0};
-      if (ea < N && eb < N) J = J + sj[0];
+      if (ea < N && eb < N) J = J + scal(gscale * gscale, to_d(sj[0]));
       if (ea < N && eb < d) {
         const int c = cown, nc = sm.cu[c] * d;
         F = scal(gscale, to_d(G[(long)un * sm.colOff[c] + (long)(uu * N + ea) * nc + j0 + eb]));
