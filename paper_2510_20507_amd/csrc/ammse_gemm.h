@@ -156,8 +156,10 @@ __device__ void block_gemm(int m, int n, int k, const cx<R>* __restrict__ A, lon
 // global loads of the next k-chunk are issued before the current chunk's
 // products so that their latency overlaps the MFMA work.  Each of the four
 // waves owns a strip of RB 16-row blocks of the output tile and its CB
-// 16-column blocks; a complex product is three real accumulators (Re Re,
-// Im Im, Re Im + Im Re).
+// 16-column blocks; a complex product is three real accumulators: Re Re,
+// Im Im and, with float operands, (Re + Im)(Re + Im) (three real products,
+// Gauss), with bfloat16 operands Re Im + Im Re (two products, whose operand
+// sums would need a conversion each).
 // Complex bfloat16 in memory (operand copies of the mixed-precision mode).
 struct alignas(4) bfc {   // one 32-bit word per complex element
   __bf16 x, y;
@@ -295,14 +297,21 @@ __device__ void block_gemm_mfma(int m, int n, int k, const TA* __restrict__ A, l
           bxr[j] = BsR[br];
           bxi[j] = BsI[br];
         }
+        // three real products per complex product (Gauss): Ar Br, Ai Bi and
+        // (Ar + Ai)(Br + Bi), whose difference from the first two is the
+        // imaginary part
+        float axs[RB], bxs[CB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) axs[i] = axr[i] + axi[i];
+#pragma unroll
+        for (int j = 0; j < CB; ++j) bxs[j] = bxr[j] + bxi[j];
 #pragma unroll
         for (int i = 0; i < RB; ++i)
 #pragma unroll
           for (int j = 0; j < CB; ++j) {
             P[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(axr[i], bxr[j], P[i][j][0], 0, 0, 0);
             P[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(axi[i], bxi[j], P[i][j][1], 0, 0, 0);
-            P[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(axr[i], bxi[j], P[i][j][2], 0, 0, 0);
-            P[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(axi[i], bxr[j], P[i][j][2], 0, 0, 0);
+            P[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(axs[i], bxs[j], P[i][j][2], 0, 0, 0);
           }
       }
     }
@@ -317,7 +326,8 @@ __device__ void block_gemm_mfma(int m, int n, int k, const TA* __restrict__ A, l
 #pragma unroll
           for (int j = 0; j < CB; ++j) {
             const int gj = j0 + 16 * j + li;
-            if (gj < n) epi(gi, gj, cx<float>{P[i][j][0][r] - P[i][j][1][r], P[i][j][2][r]});
+            const float p0 = P[i][j][0][r], p1 = P[i][j][1][r], p2 = P[i][j][2][r];
+            if (gj < n) epi(gi, gj, cx<float>{p0 - p1, Tl::LOW ? p2 : p2 - p0 - p1});
           }
         }
     }
@@ -447,8 +457,7 @@ __device__ void block_gemm_mfma_ks(int m, int n, int k, const TA* __restrict__ A
         const float axr = AsR[ar], axi = AsI[ar], bxr = BsR[br], bxi = BsI[br];
         P[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(axr, bxr, P[0], 0, 0, 0);
         P[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(axi, bxi, P[1], 0, 0, 0);
-        P[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(axr, bxi, P[2], 0, 0, 0);
-        P[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(axi, bxr, P[2], 0, 0, 0);
+        P[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(axr + axi, bxr + bxi, P[2], 0, 0, 0);
       }
     }
     if (kc == nks - 1) {
@@ -476,7 +485,8 @@ __device__ void block_gemm_mfma_ks(int m, int n, int k, const TA* __restrict__ A
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int gi = i0 + 16 * rbk + 4 * lk + r, gj = j0 + 16 * cbk + li;
-          if (gi < m && gj < n) epi(gi, gj, cx<float>{P[0][r] - P[1][r], P[2][r]});
+          const float p0 = P[0][r], p1 = P[1][r], p2 = P[2][r];
+          if (gi < m && gj < n) epi(gi, gj, cx<float>{p0 - p1, LOW ? p2 : p2 - p0 - p1});
         }
       }
     }
