@@ -421,10 +421,21 @@ def unrolled_leg(B: int = 1024, T: int = 20, K: int = 5, reps: int = 3):
     plan.close()
     f, b_ = float(np.mean(fw)), float(np.mean(bw))
     ok = bool(torch.isfinite(dg).all()) and bool(torch.isfinite(wsr).all())
+    # algorithmic work: one complex product with H = 8 U N M U d flops; the
+    # forward step takes two per iteration, the adjoint six (the recomputed
+    # forward step of its segment and four adjoint products)
+    prod = 8.0 * float((batch.U * batch.N * batch.M * batch.U * batch.d).sum())
+    ff, fb = 2.0 * T * prod, 6.0 * T * prod
     return {"workload": batch.name, "instances": B, "T": T, "ckpt_every": K,
             "precision": "fp32", "forward_ms": f, "backward_ms": b_,
             "instances_per_s_fwd_bwd": B / ((f + b_) / 1e3), "finite": ok,
-            "workspace_bytes": ws_b, "checkpoint_bytes": ck_b}
+            "workspace_bytes": ws_b, "checkpoint_bytes": ck_b,
+            "roofline": {"bound": "mfma", "achieved": (ff + fb) / ((f + b_) / 1e3) / 1e12,
+                         "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                         "frac": (ff + fb) / ((f + b_) / 1e3) / 1e12 / PEAK_FP32_MFMA_TFLOPS,
+                         "forward_tflops": ff / (f / 1e3) / 1e12,
+                         "backward_tflops": fb / (b_ / 1e3) / 1e12,
+                         "kernel": "unroll_forward_kernel<float> + unroll_backward_kernel<float>"}}
 
 
 def early_exit(batch, ref, eps_list=(1e-3, 1e-4, 1e-5)):
