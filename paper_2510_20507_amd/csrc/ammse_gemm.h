@@ -38,6 +38,10 @@ template <> struct TileShape<2> { static constexpr int TM = 64, TN = 32; };
 // 3: 64 x 16 (each wave one row block, one column block): not an autotuner
 //    choice; the products with 33-64 output rows and at most 16 columns take it
 template <> struct TileShape<3> { static constexpr int TM = 64, TN = 16; };
+// A tile argument that fixes the 64 x 64 shape: no per-product choice by size
+// (for kernels whose products are all 64 x 64 and whose register budget does
+// not allow the other variants' code)
+constexpr int kTileFixed64 = 4;
 
 template <class T, int V>
 struct MfmaTile {
@@ -501,6 +505,10 @@ template <class T, bool CONJA, bool CONJB, class Epi, class TA, class TB>
 __device__ __forceinline__ void mfma_dispatch(int m, int n, int k, const TA* A, long lda,
                                               const TB* B, long ldb, char* tiles, int tile,
                                               Epi&& epi) {
+  if (tile == kTileFixed64) {   // the caller's fixed 64 x 64 shape, no other variant
+    block_gemm_mfma<T, 0, CONJA, CONJB>(m, n, k, A, lda, B, ldb, tiles, epi);
+    return;
+  }
   if constexpr (!CONJB) {
     if (CONJA && m <= 32) {
       if (m <= 16) {
