@@ -38,10 +38,7 @@ template <> struct TileShape<2> { static constexpr int TM = 64, TN = 32; };
 // 3: 64 x 16 (each wave one row block, one column block): not an autotuner
 //    choice; the products with 33-64 output rows and at most 16 columns take it
 template <> struct TileShape<3> { static constexpr int TM = 64, TN = 16; };
-// A tile argument that fixes the 64 x 64 shape: no per-product choice by size
-// (for kernels whose products are all 64 x 64 and whose register budget does
-// not allow the other variants' code)
-constexpr int kTileFixed64 = 4;
+
 
 template <class T, int V>
 struct MfmaTile {
@@ -505,10 +502,6 @@ template <class T, bool CONJA, bool CONJB, class Epi, class TA, class TB>
 __device__ __forceinline__ void mfma_dispatch(int m, int n, int k, const TA* A, long lda,
                                               const TB* B, long ldb, char* tiles, int tile,
                                               Epi&& epi) {
-  if (tile == kTileFixed64) {   // the caller's fixed 64 x 64 shape, no other variant
-    block_gemm_mfma<T, 0, CONJA, CONJB>(m, n, k, A, lda, B, ldb, tiles, epi);
-    return;
-  }
   if constexpr (!CONJB) {
     if (CONJA && m <= 32) {
       if (m <= 16) {
@@ -552,6 +545,21 @@ __device__ __forceinline__ void channel_gemm(int m, int n, int k, const cx<R>* A
       mfma_dispatch<float, CONJA, CONJB>(m, n, k, A, lda, B, ldb, tiles, tile, epi);
   } else {
     (void)tile;
+    cx<R>* As = (cx<R>*)tiles;
+    block_gemm<R, CONJA, CONJB>(m, n, k, A, lda, B, ldb, As, As + KC * (TM + 1), epi);
+  }
+}
+
+// The same product on the 64 x 64 tile shape only (float products for FP32
+// storage), with no per-product choice by size: for kernels whose products
+// are all of that shape and whose register budget leaves no room for the
+// other variants' code.
+template <class R, bool CONJA, bool CONJB = false, class Epi>
+__device__ __forceinline__ void channel_gemm64(int m, int n, int k, const cx<R>* A, long lda,
+                                               const cx<R>* B, long ldb, char* tiles, Epi&& epi) {
+  if constexpr (sizeof(R) == 4) {
+    block_gemm_mfma<float, 0, CONJA, CONJB>(m, n, k, A, lda, B, ldb, tiles, epi);
+  } else {
     cx<R>* As = (cx<R>*)tiles;
     block_gemm<R, CONJA, CONJB>(m, n, k, A, lda, B, ldb, As, As + KC * (TM + 1), epi);
   }

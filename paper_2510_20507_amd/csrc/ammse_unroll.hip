@@ -126,7 +126,7 @@ __device__ UView<R> make_view(const ammse_desc_t& D, const ammse_kparams_t& p,
 template <class R>
 __device__ void u_product(const UView<R>& w, USmem<R>& sm, cx<R>* G, const cx<R>* V) {
   const int N = w.N, ud = w.ud;
-  channel_gemm<R, false>(w.un, ud, w.M, w.H, w.M, V, ud, sm.tiles, false, kTileFixed64,
+  channel_gemm64<R, false>(w.un, ud, w.M, w.H, w.M, V, ud, sm.tiles,
                          [&](int i, int j, cx<R> v) {
                            const R f = (R)sm.invsig[i / N];
                            G[(long)i * ud + j] = {f * v.x, f * v.y};
@@ -277,7 +277,7 @@ __device__ void u_step(const UView<R>& w, USmem<R>& sm, int t, double gamma, boo
     }
   }
   __syncthreads();
-  channel_gemm<R, true>(M, ud, w.un, w.H, M, Z, ud, sm.tiles, false, kTileFixed64,
+  channel_gemm64<R, true>(M, ud, w.un, w.H, M, Z, ud, sm.tiles,
                         [&](int i, int j, cx<R> v) {
                           Gr[(long)i * ud + j] = {R(2) * v.x, R(2) * v.y};
                         });
@@ -602,12 +602,12 @@ __global__ __launch_bounds__(AMMSE_BLOCK, 1) void unroll_backward_kernel(ammse_k
         Gbt[e] = {(R)f * x.x, (R)f * x.y};
       }
       __syncthreads();
-      channel_gemm<R, false, true>(un, M, ud, Gbt, ud, Vt_, ud, sm.tiles, false, kTileFixed64,
+      channel_gemm64<R, false, true>(un, M, ud, Gbt, ud, Vt_, ud, sm.tiles,
                                    [&](int i, int j, cx<R> v) {
                                      cx<R>& o = dH[(long)i * M + j];
                                      o = {o.x + v.x, o.y + v.y};
                                    });
-      channel_gemm<R, true>(M, ud, un, w.H, M, Gbt, ud, sm.tiles, false, kTileFixed64,
+      channel_gemm64<R, true>(M, ud, un, w.H, M, Gbt, ud, sm.tiles,
                             [&](int i, int j, cx<R> v) {
                               cx<R>& o = Vbt[(long)i * ud + j];
                               o = {o.x + v.x, o.y + v.y};
@@ -643,11 +643,11 @@ __global__ __launch_bounds__(AMMSE_BLOCK, 1) void unroll_backward_kernel(ammse_k
       gd = block_sum(gd, sm.red);
       if (tid == 0) q.dgamma[(long)b * T + (t - 1)] = -gd;
       // (d) Grad = 2 H^H Z: Zbar = 2 H Gradbar, dH += 2 Z Gradbar^H
-      channel_gemm<R, false>(un, ud, M, w.H, M, w.Tb, ud, sm.tiles, false, kTileFixed64,
+      channel_gemm64<R, false>(un, ud, M, w.H, M, w.Tb, ud, sm.tiles,
                              [&](int i, int j, cx<R> v) {
                                w.Zb[(long)i * ud + j] = {R(2) * v.x, R(2) * v.y};
                              });
-      channel_gemm<R, false, true>(un, M, ud, w.Zs + (k - 1) * w.g, ud, w.Tb, ud, sm.tiles, false, kTileFixed64,
+      channel_gemm64<R, false, true>(un, M, ud, w.Zs + (k - 1) * w.g, ud, w.Tb, ud, sm.tiles,
                                    [&](int i, int j, cx<R> v) {
                                      cx<R>& o = dH[(long)i * M + j];
                                      o = {o.x + R(2) * v.x, o.y + R(2) * v.y};
@@ -714,7 +714,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, 1) void unroll_backward_kernel(ammse_k
       Gb0[e] = {(R)f * x.x, (R)f * x.y};
     }
     __syncthreads();
-    channel_gemm<R, false, true>(un, M, ud, Gb0, ud, ck, ud, sm.tiles, false, kTileFixed64,
+    channel_gemm64<R, false, true>(un, M, ud, Gb0, ud, ck, ud, sm.tiles,
                                  [&](int i, int j, cx<R> v) {
                                    cx<R>& o = dH[(long)i * M + j];
                                    o = {o.x + v.x, o.y + v.y};
