@@ -178,7 +178,11 @@ typedef struct ammse_options_t {
                                 general kernel (FP32 and BF16): 0 = the plan's choice
                                 (shape 0 until ammse_autotune picks one per shape
                                 class); 1, 2, 3 = force shape 0, 1, 2 (64 x 64,
-                                128 x 16, 64 x 32) for every instance */
+                                128 x 16, 64 x 32) for every instance.  Applies to
+                                products with more than 64 output rows; those with
+                                33-64 rows take a 64-row shape and conjugated ones
+                                (H^H Z, R^H R) with at most 32 rows a 16- or
+                                32-row shape whatever this option says */
   int32_t step_rule;         /* AMMSE_STEP_BOUND (default) or AMMSE_STEP_FROZEN */
   double eps1;               /* stage-switch tolerance (paper: 0.1) */
   double eps2;               /* stop tolerance (0: run exactly max_iters) */
@@ -243,7 +247,8 @@ ammse_status_t ammse_plan_info(ammse_plan_t plan, int32_t* kernel, size_t* lds_b
  * shape (0: 64 x 64, 1: 128 x 16, 2: 64 x 32), timed with HIP events on
  * `stream`, and the fastest shape is kept in the plan for every instance of
  * the class; later ammse_solve / ammse_wsr calls with options.tile = 0 use
- * it.  Arguments as for ammse_solve (V is only read); choice: host int32[3]
+ * it (for the products with more than 64 output rows; smaller products take
+ * shapes fitted to their row count, see ammse_options_t.tile).  Arguments as for ammse_solve (V is only read); choice: host int32[3]
  * (may be NULL) receives the shape picked per class, -1 for an absent class.
  * Plans without MFMA tile choices (the LDS-resident kernel, FP64) return
  * AMMSE_OK with every choice -1.  Blocks until the trials have run;
