@@ -482,20 +482,44 @@ def test_lanczos_order_beyond_the_lds_vectors():
 
 
 @pytest.mark.parametrize("cells,M,N,d", [([10, 12, 8], 64, 2, 2), ([30, 40, 20], 64, 1, 1),
-                                         ([48, 48], 128, 2, 2), ([50, 50], 128, 2, 2)])
+                                         ([30, 40, 20], 48, 1, 1), ([48, 48], 128, 2, 2),
+                                         ([50, 50], 256, 2, 2)])
 def test_fp32_gram_step_size_orders(cells, M, N, d):
     """FP32 multi-cell instances whose step size comes from the Lanczos
-    iteration on the stream-space Gram matrices K_c = R_c R_c^H: orders
-    U d = 60, 90 (a ragged second row block, not a multiple of the 8-column
-    chunks) and 192 (three full row blocks) run one wave per BS, order 200
-    (above the 192 the per-wave iteration holds) the block-wide one; the WSR
-    trajectory over 30 iterations matches the oracle's to the FP32 bound."""
+    iteration on a Gram matrix, R_c R_c^H ((U d) x (U d)) or R_c^H R_c (M x M),
+    whichever is smaller: stream side of order 60, antenna side of order 64,
+    48 (ragged: not a multiple of the 8-column chunks) and 128, all one wave
+    per BS, and stream side of order 200 (above the 192 the per-wave
+    iteration holds), the block-wide one; the WSR trajectory over 30
+    iterations matches the oracle's to the FP32 bound."""
     b = synth.pack([random_instance(700 + M + 7 * N, M=M, cell_users=cells, N=N, d=d, P=10.0)])
     ud, un = d * sum(cells), N * sum(cells)
-    assert ud * ud < 2 * un * M   # the Gram form is the cheaper step-size operator
+    ng = min(ud, M)
+    assert ng * ng < 2 * un * M   # the Gram form is the cheaper step-size operator
     opts = ammse.Options(precision=ammse.PREC_FP32, max_iters=30, path=ammse.PATH_GENERAL)
-    say("case: gram step size", cells, M, "order", ud)
+    say("case: gram step size", cells, M, "order", ng)
     res = ammse.solve(b, opts, want_trace=True)
     assert res.status[0] == 0
     refs = oracle_runs(b, [0], iters=30)
+    compare_traces(b, res, refs, [0], opts, 1e-4)
+
+
+@pytest.mark.parametrize("cells,M,N,d", [([3, 5], 16, 1, 1), ([4, 6, 2], 32, 2, 2),
+                                         ([5, 3], 48, 4, 2), ([7, 9, 4], 24, 2, 1),
+                                         ([12], 16, 2, 2)])
+def test_fp32_small_antenna_products(cells, M, N, d):
+    """FP32 instances whose channel products have few rows or columns: the
+    gradient products H^H Z and the antenna-side Gram matrices with M <= 32
+    output rows (16- and 32-row tiles, the k-chunks split over wave groups),
+    M = 48 (a 64-row tile with a ragged row block), M = 24 (a ragged k-chunk in
+    the channel products), channel products with U N <= 64 rows, a single
+    cell with U N > M (two-product form); WSR trajectories over 40 iterations
+    against the oracle at the FP32 bound."""
+    b = synth.pack([random_instance(800 + M + 11 * N + len(cells), M=M, cell_users=cells, N=N,
+                                    d=d, P=10.0, alpha_range=(0.5, 1.5))])
+    opts = ammse.Options(precision=ammse.PREC_FP32, max_iters=40, path=ammse.PATH_GENERAL)
+    say("case: small-antenna products", cells, M, N, d)
+    res = ammse.solve(b, opts, want_trace=True)
+    assert res.status[0] == 0
+    refs = oracle_runs(b, [0], iters=40)
     compare_traces(b, res, refs, [0], opts, 1e-4)
