@@ -1412,16 +1412,17 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     const T ga1 = (T)((1.0 + om) * gsp), ga2 = (T)(om * gsq);
     const T xa1 = (T)((1.0 + om) * xs1), xa2 = (T)(om * xs2), gz = (T)(2.0 * sm.gamma[0]);
     // Compiled per N (the loop bounds fold); with float storage each thread
-    // takes two (user, column) elements per trip and issues every load of both
-    // before the arithmetic, so that their latencies overlap (one element with
-    // double storage, whose registers are the tighter budget).
+    // takes four (N <= 2) or two (user, column) elements per trip and issues
+    // every load of them before the arithmetic, so that their latencies
+    // overlap (one element with double storage, whose registers are the
+    // tighter budget).
     auto zbuild = [&](auto nn) __attribute__((always_inline)) {
       constexpr int NN = decltype(nn)::value;
       for (int c = 0; c < C; ++c) {
         const int nc = sm.cu[c] * d;
         const long base = (long)un * sm.colOff[c];
         const int ne = U * nc;
-        constexpr int QB = sizeof(R) == 4 ? 2 : 1;
+        constexpr int QB = sizeof(R) == 4 ? (NN <= 2 ? 4 : 2) : 1;
         for (int e0 = tid; e0 < ne; e0 += QB * AMMSE_BLOCK) {
           int uq[QB], jq[QB];
           long gq0[QB];
