@@ -102,6 +102,26 @@ def cpu_baseline(batch, ref, per_p: int = 256):
             "seconds": dt, "reached_99": ok}
 
 
+def cpu_wmmse(batch, ref, per_p: int = 16):
+    """FP64 oracle WMMSE (Algorithm 2, the reference mode the stored WSR
+    references come from: up to 500 iterations, stop at a relative WSR change
+    of 1e-6) on a bounded sample of the workload, beside the GPU comparator."""
+    import oracle as O
+    workers = max(1, min(16, os.cpu_count() or 1))
+    idx = [k * 256 + i for k in range(4) for i in range(per_p)]
+    insts = [batch.instance(i) for i in idx]
+    t0 = time.perf_counter()
+    res = O.solve_batch(insts, "wmmse", workers=workers)
+    dt = time.perf_counter() - t0
+    ok = sum(1 for r, i in zip(res, idx) if r["wsr"] >= 0.99 * ref[i])
+    return {"value": ok / dt, "unit": "instances/s", "cores": workers, "kind": "oracle",
+            "sample": f"{len(idx)} of the {batch.batch} instances ({per_p} per SNR), WMMSE "
+                      f"reference mode (at most 500 iterations), FP64 NumPy, process pool of "
+                      f"{workers}",
+            "seconds": dt, "reached_99": ok,
+            "mean_iters": float(np.mean([r.get("iters", 0) for r in res]))}
+
+
 def plain_per_instance(batch, ref, opts, per_p: int = 8, reps: int = 2):
     """The plain form on the same GPU: one plan and one launch per instance."""
     import torch
@@ -765,6 +785,7 @@ def main():
         line["calib_copy_bytes"] = calib_copy_run()
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(batch, ref)
+        line["cpu_wmmse"] = cpu_wmmse(batch, ref)
     print(json.dumps(line), flush=True)
     plan.close()
     return 0
