@@ -3,6 +3,8 @@
 // FP32 storage on MFMA (float or bfloat16 products, float accumulation).
 #pragma once
 
+#include <type_traits>
+
 #include "ammse_device.h"
 #include "ammse_internal.h"
 
@@ -169,6 +171,20 @@ __device__ __forceinline__ cx<float> to_f(const cx<float>& v) { return v; }
 __device__ __forceinline__ cx<float> to_f(const bfc& v) { return {(float)v.x, (float)v.y}; }
 __device__ __forceinline__ bfc to_bfc(const cx<float>& v) { return {(__bf16)v.x, (__bf16)v.y}; }
 
+// An epilogue functor may also take a whole output tile at once,
+// epi.full_tile<RB, CB, LOW>(row0, col0, li, lk, P), when every element of the
+// tile is in range: element (row0 + 16 i + 4 lk + r, col0 + 16 j + li) is
+// P[i][j][0][r] - P[i][j][1][r] (real part) and P[i][j][2][r], less the first
+// two unless LOW (imaginary part).  Its loads and stores then sit in one
+// branch-free block, where the functor can declare its pointers restrict so
+// that the reads of later elements need not wait for the stores of earlier
+// ones.
+template <class E, class = void>
+struct has_full_tile : std::false_type {};
+template <class E>
+struct has_full_tile<E, std::void_t<decltype(&std::remove_reference_t<E>::is_tile_epilogue)>>
+    : std::true_type {};
+
 // Operands are float or bfloat16 complex in memory (TA, TB); either way they
 // are converted to T on the way into LDS.
 template <class T, int VAR, bool CONJA, bool CONJB, class Epi, class TA, class TB>
@@ -318,6 +334,12 @@ __device__ void block_gemm_mfma(int m, int n, int k, const TA* __restrict__ A, l
     }
     if (kc == nk - 1) {
       const int i0 = (tile / ntn) * TM, j0 = (tile % ntn) * TN;
+      if constexpr (has_full_tile<Epi>::value) {
+        if (i0 + TM <= m && j0 + TN <= n) {   // uniform: the whole tile is in range
+          epi.template full_tile<RB, CB, Tl::LOW>(i0 + 16 * RB * wave, j0, li, lk, P);
+          continue;
+        }
+      }
 #pragma unroll
       for (int i = 0; i < RB; ++i)
 #pragma unroll

@@ -53,7 +53,7 @@ struct Smem {
   double mu[AMMSE_MAX_CELLS];      // WMMSE: dual variable of each BS (warm start)
   double la[AMMSE_MAX_LANCZOS];
   double lb[AMMSE_MAX_LANCZOS];
-  zd h[AMMSE_MAX_LANCZOS];
+  double2 tp[64];   // Sturm-count operands of the FP32 Lanczos checks (wave 0)
   double red[16];
   int fail;
   int imin;
@@ -179,31 +179,121 @@ static_assert((AMMSE_BLOCK / 64) * ((AMMSE_GRAM_WAVE_N + 16) * sizeof(float2) + 
               "the per-wave Gram Lanczos buffers fit the A-MMMSE dynamic LDS");
 
 // K = C^H Q C ((U N) x (U N)) for the Q-path Lanczos, C block diagonal with an
-// N x N block per user (Cm: 4 x 4 padded, double), Q exactly Hermitian: one
-// thread per entry of the blocks on and above the diagonal, the conjugate
-// written to the mirrored entry, so K is exactly Hermitian.  A function of
-// its own so that its restrict-qualified pointers let the loads of an entry
-// be issued ahead of the previous entry's stores.
-template <class R>
-__device__ __forceinline__ void kq_form(const cx<R>* __restrict__ Q, const zd* __restrict__ Cm,
-                                        cx<R>* __restrict__ K, int U, int N, int tid) {
-  const int un = U * N;
-  for (int e = tid; e < un * un; e += AMMSE_BLOCK) {
-    const int i = e / un, j = e - i * un;
-    const int u = i / N, a = i - u * N, v = j / N, b = j - v * N;
-    if (u > v || (u == v && a > b)) continue;
-    zd acc = {0.0, 0.0};
-    for (int k = 0; k < N; ++k) {
-      zd t = {0.0, 0.0};
-      for (int l = 0; l < N; ++l)
-        t = t + to_d(Q[(long)(u * N + k) * un + v * N + l]) * Cm[v * 16 + l * 4 + b];
-      acc = acc + cj(Cm[u * 16 + k * 4 + a]) * t;
+// N x N block per user (Cm: 4 x 4 padded, double), Q exactly Hermitian.  One
+// thread per entry, in row-major order so that the reads of Q and the writes
+// of K are coalesced; an entry below the diagonal is the conjugate of its
+// mirror computed with the same operations on the same values in the same
+// order (Q's own block read and conjugated, Q being exactly Hermitian), so K
+// is exactly Hermitian.  Compiled per N; two entries per trip with the loads
+// of both issued first (the pointers are restrict-qualified, so they need not
+// wait for the previous trip's stores).
+template <class R, int NN>
+__device__ __forceinline__ void kq_form_n(const cx<R>* __restrict__ Q, const zd* __restrict__ Cm,
+                                          cx<R>* __restrict__ K, int U, int tid) {
+  const int un = U * NN, ne = un * un;
+  constexpr int QB = 2;
+  for (int e0 = tid; e0 < ne; e0 += QB * AMMSE_BLOCK) {
+    cx<R> qb[QB][NN][NN];
+    zd co[QB][NN], ci[QB][NN];
+    int ii[QB], jj[QB];
+    bool up[QB];
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int e = min(e0 + q * AMMSE_BLOCK, ne - 1);
+      const int i = e / un, j = e - i * un;
+      const int u = i / NN, a = i - u * NN, v = j / NN, b = j - v * NN;
+      ii[q] = i;
+      jj[q] = j;
+      up[q] = i <= j;
+      // outer side (conjugated C) and inner side: (u, a) and (v, b) on and
+      // above the diagonal, swapped below it
+      const int pu = up[q] ? u : v, pa = up[q] ? a : b, su = up[q] ? v : u, sb = up[q] ? b : a;
+#pragma unroll
+      for (int k = 0; k < NN; ++k) {
+        co[q][k] = Cm[pu * 16 + k * 4 + pa];
+        ci[q][k] = Cm[su * 16 + k * 4 + sb];
+#pragma unroll
+        for (int l = 0; l < NN; ++l) qb[q][k][l] = Q[(long)(u * NN + k) * un + v * NN + l];
+      }
     }
-    if (i == j) acc.y = 0.0;
-    K[(long)i * un + j] = from_d<R>(acc);
-    if (i != j) K[(long)j * un + i] = from_d<R>(cj(acc));
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      zd acc = {0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < NN; ++k) {
+        zd t = {0.0, 0.0};
+#pragma unroll
+        for (int l = 0; l < NN; ++l)
+          t = t + (up[q] ? to_d(qb[q][k][l]) : cj(to_d(qb[q][l][k]))) * ci[q][l];
+        acc = acc + cj(co[q][k]) * t;
+      }
+      if (ii[q] == jj[q]) acc.y = 0.0;
+      if (e0 + q * AMMSE_BLOCK < ne) K[(long)ii[q] * un + jj[q]] = from_d<R>(up[q] ? acc : cj(acc));
+    }
   }
 }
+template <class R>
+__device__ __forceinline__ void kq_form(const cx<R>* Q, const zd* Cm, cx<R>* K, int U, int N,
+                                        int tid) {
+  switch (N) {
+    case 1: kq_form_n<R, 1>(Q, Cm, K, U, tid); break;
+    case 2: kq_form_n<R, 2>(Q, Cm, K, U, tid); break;
+    case 3: kq_form_n<R, 3>(Q, Cm, K, U, tid); break;
+    default: kq_form_n<R, 4>(Q, Cm, K, U, tid); break;
+  }
+}
+
+// Epilogue of the single-cell Q-path product P = Q X~ (row-major, leading
+// dimension ld): G~ = c~ G^0 + P written over G^{t-2}, and the thread's partial
+// sum of 2 c~ Re<G^0, X~> + Re<X~, P> for the power of the extrapolated step.
+template <class R>
+struct QpathEpi {
+  const cx<R>* X;
+  const cx<R>* G0;
+  cx<R>* G;
+  long ld;
+  double ch;
+  double acc;
+  static constexpr bool is_tile_epilogue = true;
+  template <class V>
+  __device__ __forceinline__ void operator()(int i, int j, V pq) {
+    const long e = (long)i * ld + j;
+    const cx<R> x = X[e], g0 = G0[e];
+    acc += 2.0 * ch * ((double)g0.x * x.x + (double)g0.y * x.y) +
+           ((double)x.x * pq.x + (double)x.y * pq.y);
+    G[e] = from_d<R>(zd{ch * (double)g0.x + (double)pq.x, ch * (double)g0.y + (double)pq.y});
+  }
+  // a whole in-range tile of the float MFMA products: X, G^0 and G are
+  // distinct workspace arrays
+  template <int RB, int CB, bool LOW>
+  __device__ __forceinline__ static double tile(const cx<R>* __restrict__ Xr,
+                                                const cx<R>* __restrict__ G0r,
+                                                cx<R>* __restrict__ Gr, long ld, double ch,
+                                                int row0, int col0, int li, int lk,
+                                                const floatx4_t (&P)[RB][CB][3]) {
+    double a = 0.0;
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+          const long e = (long)(row0 + 16 * i + 4 * lk + r) * ld + col0 + 16 * j + li;
+          const float p0 = P[i][j][0][r], p1 = P[i][j][1][r], p2 = P[i][j][2][r];
+          const float px = p0 - p1, py = LOW ? p2 : p2 - p0 - p1;
+          const cx<R> x = Xr[e], g0 = G0r[e];
+          a += 2.0 * ch * ((double)g0.x * x.x + (double)g0.y * x.y) +
+               ((double)x.x * px + (double)x.y * py);
+          Gr[e] = from_d<R>(zd{ch * (double)g0.x + (double)px, ch * (double)g0.y + (double)py});
+        }
+    return a;
+  }
+  template <int RB, int CB, bool LOW>
+  __device__ __forceinline__ void full_tile(int row0, int col0, int li, int lk,
+                                            const floatx4_t (&P)[RB][CB][3]) {
+    acc += tile<RB, CB, LOW>(X, G0, G, ld, ch, row0, col0, li, lk, P);
+  }
+};
 
 // Stage-II step of the bound rule for the general kernel's instances that
 // ammse_bound_gram selects (float storage, not the single-cell Q path,
@@ -638,7 +728,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     const int m = min(p.lanczos_steps, nl);
     constexpr bool exact_beta = sizeof(R) == 8;
     const double ltol = exact_beta ? 1e-14 : 1e-8;
-    const double rtol = exact_beta ? 1e-16 : 1e-10;
+    const double rtol = 1e-16;   // FP64 checks (the FP32 multisection stops at 1e-10)
     const int first = exact_beta ? 8 : 12, every = exact_beta ? 8 : 4;
     double beta_prev = 0.0, tmax = 0.0, theta = 0.0;
     // apply() writes w[i] from thread i mod AMMSE_BLOCK (or ends with a
@@ -688,13 +778,28 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       bool stop = breakdown;
       if (breakdown || (msz >= first && (msz % every) == 0) || msz == m) {
         __syncthreads();
-        // FP32: one quick round tests the ltol criterion above the previous
-        // value before any full multisection (FP64: full value every check)
         bool conv = false;
-        const double th = (tmax > 0.0) ? tridiag_lmax(sm.la, sm.lb, msz, &sm.imin, rtol,
-                                                      exact_beta ? 0.0 : theta, ltol,
-                                                      exact_beta ? nullptr : &conv)
-                                       : 0.0;
+        double th;
+        if constexpr (exact_beta) {   // FP64: the full value at every check (block multisection)
+          th = (tmax > 0.0) ? tridiag_lmax(sm.la, sm.lb, msz, &sm.imin, rtol) : 0.0;
+        } else {
+          // FP32: wave 0 runs the multisection, whose first round tests the
+          // ltol criterion above the previous value (wave_tridiag_lmax); the
+          // other waves wait at the barrier
+          if (tid < 64) {
+            bool cv = false;
+            const double v = (tmax > 0.0) ? wave_tridiag_lmax(sm.la[tid], sm.lb[tid], msz, tmax,
+                                                              theta, ltol, sm.tp, &cv)
+                                          : 0.0;
+            if (tid == 0) {
+              sm.red[12] = v;
+              sm.imin = cv ? 1 : 0;
+            }
+          }
+          __syncthreads();
+          th = sm.red[12];
+          conv = sm.imin != 0;
+        }
         stop = stop || conv || (exact_beta && fabs(th - theta) <= ltol * fabs(th));
         theta = th;
       }
@@ -829,35 +934,55 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     __syncthreads();
   };
   // Lanczos on a formed Hermitian matrix of order ud (storage precision,
-  // row-major; column r read for row r, coalesced over r).
-  // (loads in flight per thread: 16 float or 8 double entries, which keeps
-  // the FP64 kernel within 256 registers)
-  constexpr int kDenseUnroll = sizeof(R) == 4 ? 16 : 8;
+  // row-major; column r read for row r, coalesced over r).  Per step w = K q:
+  // q staged in LDS in the storage precision (zero past ud), nparts threads
+  // per row, each over every nparts-th column, the loads of a chunk of
+  // kDenseChunk columns issued together and the chunk's products in the
+  // storage precision summed in double; partial sums combined through LDS
+  // (the product tiles, free here).
+  constexpr int kDenseChunk = 8;
   auto lanczos_dense = [&](const cx<R>* Kd, int ud) __attribute__((always_inline)) {
     const int tid = phase_tid();
-    // w = K q with K Hermitian (column r read for row r, coalesced over r):
-    // nparts threads per row, each over every nparts-th column, partial sums
-    // combined through LDS (the product tiles, free here)
     const int nparts = (ud >= AMMSE_BLOCK) ? 1 : AMMSE_BLOCK / ud;
     zd* partial = (zd*)sm.tiles;
+    cx<R>* qs = (cx<R>*)(partial + (nparts > 1 ? nparts * ud : 0));
+    const int nq = ud + kDenseChunk * nparts;
     return lanczos_core(ud, [&](const zd* qv, zd* wv) {
-      if (nparts == 1) {
-        for (int r = tid; r < ud; r += AMMSE_BLOCK) {
-          zd acc = {0.0, 0.0};
-#pragma unroll kDenseUnroll
-          for (int c2 = 0; c2 < ud; ++c2) acc = acc + cj(to_d(Kd[(long)c2 * ud + r])) * qv[c2];
-          wv[r] = acc;
+      for (int i = tid; i < nq; i += AMMSE_BLOCK)
+        qs[i] = (i < ud) ? from_d<R>(qv[i]) : cx<R>{R(0), R(0)};
+      __syncthreads();
+      auto row = [&](int r, int part) __attribute__((always_inline)) {
+        zd acc = {0.0, 0.0};
+        for (int c0 = part; c0 < ud; c0 += kDenseChunk * nparts) {
+          cx<R> kv[kDenseChunk];
+#pragma unroll
+          for (int u = 0; u < kDenseChunk; ++u)
+            kv[u] = Kd[(long)min(c0 + u * nparts, ud - 1) * ud + r];
+          if constexpr (sizeof(R) == 4) {
+            float ax = 0.f, ay = 0.f, bx = 0.f, by = 0.f;
+#pragma unroll
+            for (int u = 0; u < kDenseChunk; u += 2) {   // conj(K(c, r)) q_c
+              const cx<float> q0 = qs[c0 + u * nparts], q1 = qs[c0 + (u + 1) * nparts];
+              ax = fmaf(kv[u].x, q0.x, fmaf(kv[u].y, q0.y, ax));
+              ay = fmaf(kv[u].x, q0.y, fmaf(-kv[u].y, q0.x, ay));
+              bx = fmaf(kv[u + 1].x, q1.x, fmaf(kv[u + 1].y, q1.y, bx));
+              by = fmaf(kv[u + 1].x, q1.y, fmaf(-kv[u + 1].y, q1.x, by));
+            }
+            acc.x += (double)ax + (double)bx;
+            acc.y += (double)ay + (double)by;
+          } else {
+#pragma unroll
+            for (int u = 0; u < kDenseChunk; ++u) acc = acc + cj(kv[u]) * qs[c0 + u * nparts];
+          }
         }
+        return acc;
+      };
+      if (nparts == 1) {
+        for (int r = tid; r < ud; r += AMMSE_BLOCK) wv[r] = row(r, 0);
         return;
       }
       const int r = tid % ud, part = tid / ud;
-      if (part < nparts) {
-        zd acc = {0.0, 0.0};
-#pragma unroll kDenseUnroll
-        for (int c2 = part; c2 < ud; c2 += nparts)
-          acc = acc + cj(to_d(Kd[(long)c2 * ud + r])) * qv[c2];
-        partial[part * ud + r] = acc;
-      }
+      if (part < nparts) partial[part * ud + r] = row(r, part);
       __syncthreads();
       for (int rr = tid; rr < ud; rr += AMMSE_BLOCK) {
         zd acc = {0.0, 0.0};
@@ -1506,16 +1631,9 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       // projection factor becomes the scale of G~ and X~.
       const int ud = D.ud;
       const double ch = (1.0 + om) * c1 - om * c2;
-      double acc = 0.0;
-      auto epi = [&](int i, int j, cx<R> pq) {
-        const long e = (long)i * ud + j;
-        const cx<R> x = X2[e], g0 = G0[e];
-        acc += 2.0 * ch * ((double)g0.x * x.x + (double)g0.y * x.y) +
-               ((double)x.x * pq.x + (double)x.y * pq.y);
-        Gq[e] = from_d<R>(zd{ch * (double)g0.x + (double)pq.x, ch * (double)g0.y + (double)pq.y});
-      };
+      QpathEpi<R> epi{X2, G0, Gq, ud, ch, 0.0};
       channel_gemm<R, false>(un, ud, un, Qm, un, X2, ud, sm.tiles, lowp, tile, epi);
-      const double pw = ch * ch * nu + block_sum(acc, sm.red);
+      const double pw = ch * ch * nu + block_sum(epi.acc, sm.red);
       const double sc = (pw > sm.Pc[0]) ? sqrt(sm.Pc[0] / pw) : 1.0;
       cx<R>* tg = Gq;
       Gq = Gp;
