@@ -171,19 +171,27 @@ __device__ __forceinline__ cx<float> to_f(const cx<float>& v) { return v; }
 __device__ __forceinline__ cx<float> to_f(const bfc& v) { return {(float)v.x, (float)v.y}; }
 __device__ __forceinline__ bfc to_bfc(const cx<float>& v) { return {(__bf16)v.x, (__bf16)v.y}; }
 
-// An epilogue functor may also take a whole output tile at once,
-// epi.full_tile<RB, CB, LOW>(row0, col0, li, lk, P), when every element of the
-// tile is in range: element (row0 + 16 i + 4 lk + r, col0 + 16 j + li) is
-// P[i][j][0][r] - P[i][j][1][r] (real part) and P[i][j][2][r], less the first
-// two unless LOW (imaginary part).  Its loads and stores then sit in one
-// branch-free block, where the functor can declare its pointers restrict so
-// that the reads of later elements need not wait for the stores of earlier
-// ones.
+// An epilogue functor may split each element into a load phase, L l =
+// epi.pre(i, j) (reads only; any in-range indices), and epi(i, j, v, l) (the
+// arithmetic and stores).  The tile products then issue the reads of a group
+// of the lane's elements together and finish the group before reading the
+// next, instead of waiting for each element's reads after the previous
+// element's stores (which may alias them for all the compiler knows); the
+// next tile's first k-chunk is fetched after the epilogue, so the groups'
+// reads take the registers of that prefetch.
 template <class E, class = void>
-struct has_full_tile : std::false_type {};
+struct has_pre : std::false_type {};
 template <class E>
-struct has_full_tile<E, std::void_t<decltype(&std::remove_reference_t<E>::is_tile_epilogue)>>
+struct has_pre<E, std::void_t<decltype(std::declval<std::remove_reference_t<E>&>().pre(0, 0))>>
     : std::true_type {};
+template <class E, bool P>
+struct PreType {
+  struct type {};
+};
+template <class E>
+struct PreType<E, true> {
+  using type = decltype(std::declval<std::remove_reference_t<E>&>().pre(0, 0));
+};
 
 // Operands are float or bfloat16 complex in memory (TA, TB); either way they
 // are converted to T on the way into LDS.
@@ -274,7 +282,27 @@ __device__ void block_gemm_mfma(int m, int n, int k, const TA* __restrict__ A, l
       BsI[col * LD + kk] = (T)(CONJB ? -vb.y : vb.y);
     }
     __syncthreads();
-    if (s + 1 < steps) fetch(s + 1);
+    constexpr int EG = 2;   // lane elements per load group of the epilogue
+    // (only where the prefetch it displaces holds at least as many registers)
+    constexpr bool PRE = has_pre<Epi>::value &&
+                         EG * sizeof(typename PreType<Epi, has_pre<Epi>::value>::type) <=
+                             NA * sizeof(TA) + NB * sizeof(TB);
+    using L = typename PreType<Epi, PRE>::type;
+    L pl[EG];               // load phase of the epilogue's current group (PRE)
+    const bool last = kc == nk - 1;
+    // group g: 16 x 16 block g / (4 / EG) of the lane's blocks, rows EG (g % (4 / EG)) on
+    auto preload = [&](int g) __attribute__((always_inline)) {
+      if constexpr (PRE) {
+        const int blk = g / (4 / EG), r0 = EG * (g % (4 / EG));
+        const int i = blk / CB, j = blk - i * CB;
+        const int i0 = (tile / ntn) * TM, j0 = (tile % ntn) * TN;
+        const int gj = min(j0 + 16 * j + li, n - 1);
+#pragma unroll
+        for (int r = 0; r < EG; ++r)
+          pl[r] = epi.pre(min(i0 + 16 * (RB * wave + i) + 4 * lk + r0 + r, m - 1), gj);
+      }
+    };
+    if (!(PRE && last) && s + 1 < steps) fetch(s + 1);
     if constexpr (Tl::LOW) {
       bf16x8_t axr[RB], axi[RB], bxr[CB], bxi[CB];
 #pragma unroll
@@ -332,27 +360,39 @@ __device__ void block_gemm_mfma(int m, int n, int k, const TA* __restrict__ A, l
           }
       }
     }
-    if (kc == nk - 1) {
+    if (last) {
       const int i0 = (tile / ntn) * TM, j0 = (tile % ntn) * TN;
-      if constexpr (has_full_tile<Epi>::value) {
-        if (i0 + TM <= m && j0 + TN <= n) {   // uniform: the whole tile is in range
-          epi.template full_tile<RB, CB, Tl::LOW>(i0 + 16 * RB * wave, j0, li, lk, P);
-          continue;
-        }
-      }
+      if constexpr (PRE) {
+        preload(0);
 #pragma unroll
-      for (int i = 0; i < RB; ++i)
+        for (int g = 0; g < RB * CB * (4 / EG); ++g) {
+          const int blk = g / (4 / EG), r0 = EG * (g % (4 / EG));
+          const int i = blk / CB, j = blk - i * CB;
+          const int gj = j0 + 16 * j + li;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int gi = i0 + 16 * (RB * wave + i) + 4 * lk + r;
-          if (gi >= m) continue;
-#pragma unroll
-          for (int j = 0; j < CB; ++j) {
-            const int gj = j0 + 16 * j + li;
-            const float p0 = P[i][j][0][r], p1 = P[i][j][1][r], p2 = P[i][j][2][r];
-            if (gj < n) epi(gi, gj, cx<float>{p0 - p1, Tl::LOW ? p2 : p2 - p0 - p1});
+          for (int r = 0; r < EG; ++r) {
+            const int gi = i0 + 16 * (RB * wave + i) + 4 * lk + r0 + r;
+            const float p0 = P[i][j][0][r0 + r], p1 = P[i][j][1][r0 + r], p2 = P[i][j][2][r0 + r];
+            if (gi < m && gj < n) epi(gi, gj, cx<float>{p0 - p1, Tl::LOW ? p2 : p2 - p0 - p1}, pl[r]);
           }
+          if (g + 1 < RB * CB * (4 / EG)) preload(g + 1);
         }
+        if (s + 1 < steps) fetch(s + 1);
+      } else {
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int gi = i0 + 16 * (RB * wave + i) + 4 * lk + r;
+            if (gi >= m) continue;
+#pragma unroll
+            for (int j = 0; j < CB; ++j) {
+              const int gj = j0 + 16 * j + li;
+              const float p0 = P[i][j][0][r], p1 = P[i][j][1][r], p2 = P[i][j][2][r];
+              if (gj < n) epi(gi, gj, cx<float>{p0 - p1, Tl::LOW ? p2 : p2 - p0 - p1});
+            }
+          }
+      }
     }
   }
   __syncthreads();

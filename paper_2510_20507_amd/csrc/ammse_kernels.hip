@@ -246,6 +246,7 @@ __device__ __forceinline__ void kq_form(const cx<R>* Q, const zd* Cm, cx<R>* K, 
 // Epilogue of the single-cell Q-path product P = Q X~ (row-major, leading
 // dimension ld): G~ = c~ G^0 + P written over G^{t-2}, and the thread's partial
 // sum of 2 c~ Re<G^0, X~> + Re<X~, P> for the power of the extrapolated step.
+// The reads of X~ and G^0 form the load phase (see has_pre).
 template <class R>
 struct QpathEpi {
   const cx<R>* X;
@@ -254,44 +255,23 @@ struct QpathEpi {
   long ld;
   double ch;
   double acc;
-  static constexpr bool is_tile_epilogue = true;
+  struct L {
+    cx<R> x, g0;
+  };
+  __device__ __forceinline__ L pre(int i, int j) const {
+    const long e = (long)i * ld + j;
+    return {X[e], G0[e]};
+  }
+  template <class V>
+  __device__ __forceinline__ void operator()(int i, int j, V pq, const L& l) {
+    acc += 2.0 * ch * ((double)l.g0.x * l.x.x + (double)l.g0.y * l.x.y) +
+           ((double)l.x.x * pq.x + (double)l.x.y * pq.y);
+    G[(long)i * ld + j] =
+        from_d<R>(zd{ch * (double)l.g0.x + (double)pq.x, ch * (double)l.g0.y + (double)pq.y});
+  }
   template <class V>
   __device__ __forceinline__ void operator()(int i, int j, V pq) {
-    const long e = (long)i * ld + j;
-    const cx<R> x = X[e], g0 = G0[e];
-    acc += 2.0 * ch * ((double)g0.x * x.x + (double)g0.y * x.y) +
-           ((double)x.x * pq.x + (double)x.y * pq.y);
-    G[e] = from_d<R>(zd{ch * (double)g0.x + (double)pq.x, ch * (double)g0.y + (double)pq.y});
-  }
-  // a whole in-range tile of the float MFMA products: X, G^0 and G are
-  // distinct workspace arrays
-  template <int RB, int CB, bool LOW>
-  __device__ __forceinline__ static double tile(const cx<R>* __restrict__ Xr,
-                                                const cx<R>* __restrict__ G0r,
-                                                cx<R>* __restrict__ Gr, long ld, double ch,
-                                                int row0, int col0, int li, int lk,
-                                                const floatx4_t (&P)[RB][CB][3]) {
-    double a = 0.0;
-#pragma unroll
-    for (int i = 0; i < RB; ++i)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int j = 0; j < CB; ++j) {
-          const long e = (long)(row0 + 16 * i + 4 * lk + r) * ld + col0 + 16 * j + li;
-          const float p0 = P[i][j][0][r], p1 = P[i][j][1][r], p2 = P[i][j][2][r];
-          const float px = p0 - p1, py = LOW ? p2 : p2 - p0 - p1;
-          const cx<R> x = Xr[e], g0 = G0r[e];
-          a += 2.0 * ch * ((double)g0.x * x.x + (double)g0.y * x.y) +
-               ((double)x.x * px + (double)x.y * py);
-          Gr[e] = from_d<R>(zd{ch * (double)g0.x + (double)px, ch * (double)g0.y + (double)py});
-        }
-    return a;
-  }
-  template <int RB, int CB, bool LOW>
-  __device__ __forceinline__ void full_tile(int row0, int col0, int li, int lk,
-                                            const floatx4_t (&P)[RB][CB][3]) {
-    acc += tile<RB, CB, LOW>(X, G0, G, ld, ch, row0, col0, li, lk, P);
+    (*this)(i, j, pq, pre(i, j));
   }
 };
 
@@ -531,41 +511,50 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       // one after the other), then a reduce-scatter over the 16 lanes leaves
       // entry (a, b) on lane 4a + b.  The sums are in the storage precision's
       // working type (float with float storage, as in the LDS-resident
-      // kernel), scaled by gscale^2 at the end, and the loads of the lane's
-      // next column are issued before the current column's arithmetic.
+      // kernel), scaled by gscale^2 at the end.  Compiled per N; the lane's
+      // columns go in chunks of CH with the loads of a whole chunk issued
+      // before its arithmetic (CH N = 16 loads in flight with float storage,
+      // 8 with double).
       using TJ = typename std::conditional<sizeof(R) == 4, float, double>::type;
       cx<TJ> sj[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) sj[q] = {TJ(0), TJ(0)};
-      {
+      auto cov = [&](auto nn) __attribute__((always_inline)) {
+        constexpr int NN = decltype(nn)::value;
+        constexpr int CH = (sizeof(R) == 4 ? 16 : 8) / (NN == 3 ? 4 : NN);
         const int nstr = sm.colOff[C];
-        int t = li, c = 0;
-        while (c < C - 1 && t >= sm.colOff[c + 1]) ++c;   // BS of column t
-        cx<R> gn[AMMSE_MAX_RX];
-        auto load = [&](int tt, int cc) {
-          const int nc = sm.cu[cc] * d;
-          const cx<R>* __restrict__ r0 =
-              G + (long)un * sm.colOff[cc] + (long)(uu * N) * nc + (tt - sm.colOff[cc]);
+        int c = 0;
+        for (int t0 = li; t0 < nstr; t0 += 16 * CH) {
+          cx<R> g[CH][NN];
+          bool use[CH];
 #pragma unroll
-          for (int k = 0; k < AMMSE_MAX_RX; ++k)
-            gn[k] = (k < N) ? r0[(long)k * nc] : cx<R>{R(0), R(0)};
-        };
-        if (t < nstr) load(t, c);
-        while (t < nstr) {
-          cx<TJ> g[AMMSE_MAX_RX];
+          for (int q = 0; q < CH; ++q) {
+            const int t = min(t0 + 16 * q, nstr - 1);
+            while (c < C - 1 && t >= sm.colOff[c + 1]) ++c;   // BS of column t
+            const int nc = sm.cu[c] * d, col = t - sm.colOff[c];
+            const cx<R>* r0 = G + (long)un * sm.colOff[c] + (long)(uu * NN) * nc + col;
 #pragma unroll
-          for (int k = 0; k < AMMSE_MAX_RX; ++k) g[k] = {(TJ)gn[k].x, (TJ)gn[k].y};
-          const bool own = c == cown && t - sm.colOff[c] >= j0 && t - sm.colOff[c] < j0 + d;
-          t += 16;
-          while (c < C - 1 && t >= sm.colOff[c + 1]) ++c;
-          if (t < nstr) load(t, c);
-          if (own) continue;
+            for (int k = 0; k < NN; ++k) g[q][k] = r0[(long)k * nc];
+            use[q] = t0 + 16 * q < nstr && !(c == cown && col >= j0 && col < j0 + d);
+          }
 #pragma unroll
-          for (int x = 0; x < AMMSE_MAX_RX; ++x)
+          for (int q = 0; q < CH; ++q) {
+            if (!use[q]) continue;
+            cx<TJ> gt[NN];
 #pragma unroll
-            for (int y = 0; y < AMMSE_MAX_RX; ++y)
-              if (x < N && y < N) sj[x * 4 + y] = sj[x * 4 + y] + mulc(g[x], g[y]);
+            for (int k = 0; k < NN; ++k) gt[k] = {(TJ)g[q][k].x, (TJ)g[q][k].y};
+#pragma unroll
+            for (int x = 0; x < NN; ++x)
+#pragma unroll
+              for (int y = 0; y < NN; ++y) sj[x * 4 + y] = sj[x * 4 + y] + mulc(gt[x], gt[y]);
+          }
         }
+      };
+      switch (N) {
+        case 1: cov(std::integral_constant<int, 1>{}); break;
+        case 2: cov(std::integral_constant<int, 2>{}); break;
+        case 3: cov(std::integral_constant<int, 3>{}); break;
+        default: cov(std::integral_constant<int, 4>{}); break;
       }
 #pragma unroll
       for (int step = 0; step < 4; ++step) {
