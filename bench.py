@@ -174,6 +174,12 @@ def mixed_precision(reps: int = 2):
     am_idx = np.asarray(refj["ammmse"]["index"])
     am = np.asarray(refj["ammmse"]["wsr"])
     flops = float(batch.total_flops_per_iter().sum()) * ITERS
+    # flops the single-cell Q path executes: one product with Q = S H H^H S
+    # ((U N) x (U N) by (U N) x (U d)) per iteration, Q and G^0 once per solve
+    un = (batch.U * batch.N).astype(np.float64)
+    ud = (batch.U * batch.d).astype(np.float64)
+    exec_flops = float((8.0 * un * un * ud * ITERS + 8.0 * un * un * batch.M
+                        + 8.0 * un * batch.M * ud).sum())
     out = {"workload": batch.name, "instances": batch.batch, "M": 256, "users": 64, "N": 2,
            "d": 2, "snr_db": 20, "iters": ITERS}
     modes = [("fp32", ammse.Options(precision=ammse.PREC_FP32, max_iters=ITERS)),
@@ -219,6 +225,9 @@ def mixed_precision(reps: int = 2):
                                   "hbm_algorithmic_bytes": alg_bytes,
                                   "hbm_achieved_GBs": alg_bytes / (t / 1e3) / 1e9,
                                   "hbm_frac": alg_bytes / (t / 1e3) / 1e9 / PEAK_HBM_GBS,
+                                  "executed_flops_per_launch": exec_flops,
+                                  "executed_tflops": exec_flops / (t / 1e3) / 1e12,
+                                  "executed_frac": exec_flops / (t / 1e3) / 1e12 / peak,
                                   "traffic": read_profile_value(prof, "traffic_bytes_per_launch"),
                                   "mfma_busy": read_profile_value(prof, "mfma_busy_fraction"),
                                   "kernel": "ammse_solve_kernel<float> (general, single-cell Q path"

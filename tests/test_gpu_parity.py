@@ -523,3 +523,26 @@ def test_fp32_small_antenna_products(cells, M, N, d):
     assert res.status[0] == 0
     refs = oracle_runs(b, [0], iters=40)
     compare_traces(b, res, refs, [0], opts, 1e-4)
+
+
+@pytest.mark.parametrize("U,M,N,d", [(9, 20, 1, 1), (7, 30, 2, 2), (5, 17, 3, 2), (6, 40, 4, 3),
+                                     (40, 130, 3, 2)])
+def test_q_path_every_receive_dimension(U, M, N, d):
+    """Single-cell instances on the Q path (U N <= M) for every N: the step
+    size's K = C^H Q C (formed per N, entries below the diagonal from their
+    mirrors) and its Lanczos products in column chunks with ragged ends (U N
+    not a multiple of the chunk; U N = 120 > 64 spans several wave rows).
+    FP64 trajectories to 1e-9 and FP32 to the FP32 bound, against the oracle."""
+    b = synth.pack([random_instance(900 + 10 * N + U, M=M, cell_users=[U], N=N, d=d, P=20.0,
+                                    alpha_range=(0.5, 1.5))])
+    T = 40
+    refs = oracle_runs(b, [0], iters=T)
+    say("case: q path", U, M, N, d)
+    res = ammse.solve(b, ammse.Options(precision=ammse.PREC_FP64, max_iters=T), want_trace=True,
+                      force_switch=np.array([refs[0]["switch_iter"]], np.int32))
+    assert res.status[0] == 0
+    np.testing.assert_allclose(res.trace[0], refs[0]["trace"], rtol=1e-9)
+    opts = ammse.Options(precision=ammse.PREC_FP32, max_iters=T, path=ammse.PATH_GENERAL)
+    res = ammse.solve(b, opts, want_trace=True)
+    assert res.status[0] == 0
+    compare_traces(b, res, refs, [0], opts, 1e-4)
