@@ -48,6 +48,25 @@ __device__ __forceinline__ int utid() {
   return x;
 }
 
+// Elementwise pass over n entries: each thread takes entries e = tid + 256 q
+// in trips of QB, with ld(e) (loads only) for every entry of a trip before
+// st(e, loaded) (arithmetic and stores), so that a trip's loads are in flight
+// together instead of each waiting for the previous entry's stores.  An
+// entry's st touches only that entry's own locations.
+template <int QB, class Ld, class St>
+__device__ __forceinline__ void u_batched(int n, Ld&& ld, St&& st) {
+  const int tid = utid();
+  using L = decltype(ld(0));
+  for (int e0 = tid; e0 < n; e0 += QB * AMMSE_BLOCK) {
+    L v[QB];
+#pragma unroll
+    for (int q = 0; q < QB; ++q) v[q] = ld(min(e0 + q * AMMSE_BLOCK, n - 1));
+#pragma unroll
+    for (int q = 0; q < QB; ++q)
+      if (e0 + q * AMMSE_BLOCK < n) st(e0 + q * AMMSE_BLOCK, v[q]);
+  }
+}
+
 template <class R>
 struct USmem {
   alignas(16) char tiles[tile_bytes<R>()];
@@ -142,16 +161,30 @@ __device__ zd u_interference(const UView<R>& w, const cx<R>* G, int uu, int li) 
 #pragma unroll
   for (int q = 0; q < 16; ++q) sj[q] = {0.0, 0.0};
   const cx<R>* __restrict__ r0 = G + (long)(uu * N) * ud;
-  for (int j = li; j < ud; j += 16) {
-    if (j >= j0 && j < j0 + d) continue;
-    zd g[AMMSE_MAX_RX];
+  // the lane's columns j = li (mod 16) in chunks of CH, the loads of a chunk
+  // issued together
+  constexpr int CH = 4;
+  for (int jc = li; jc < ud; jc += 16 * CH) {
+    cx<R> gl[CH][AMMSE_MAX_RX];
 #pragma unroll
-    for (int k = 0; k < AMMSE_MAX_RX; ++k) g[k] = (k < N) ? to_d(r0[(long)k * ud + j]) : zd{0.0, 0.0};
+    for (int c = 0; c < CH; ++c) {
+      const int j = min(jc + 16 * c, ud - 1);
 #pragma unroll
-    for (int x = 0; x < AMMSE_MAX_RX; ++x)
+      for (int k = 0; k < AMMSE_MAX_RX; ++k) gl[c][k] = r0[(long)min(k, N - 1) * ud + j];
+    }
 #pragma unroll
-      for (int y = 0; y < AMMSE_MAX_RX; ++y)
-        if (x < N && y < N) sj[x * 4 + y] = sj[x * 4 + y] + mulc(g[x], g[y]);
+    for (int c = 0; c < CH; ++c) {
+      const int j = jc + 16 * c;
+      if (j >= ud || (j >= j0 && j < j0 + d)) continue;
+      zd g[AMMSE_MAX_RX];
+#pragma unroll
+      for (int k = 0; k < AMMSE_MAX_RX; ++k) g[k] = (k < N) ? to_d(gl[c][k]) : zd{0.0, 0.0};
+#pragma unroll
+      for (int x = 0; x < AMMSE_MAX_RX; ++x)
+#pragma unroll
+        for (int y = 0; y < AMMSE_MAX_RX; ++y)
+          if (x < N && y < N) sj[x * 4 + y] = sj[x * 4 + y] + mulc(g[x], g[y]);
+    }
   }
 #pragma unroll
   for (int step = 0; step < 4; ++step) {
@@ -248,33 +281,46 @@ __device__ void u_step(const UView<R>& w, USmem<R>& sm, int t, double gamma, boo
   const int N = w.N, d = w.d, ud = w.ud, U = w.U, M = w.M;
   u_weights(w, sm, UWi, Ei, stage2, Do, Yo);
   const double om = extrapolate ? fmax((t - 2.0) / (t + 1.0), 0.0) : 0.0;
-  for (int e = tid; e < U * ud; e += AMMSE_BLOCK) {
-    const int u = e / ud, j = e - u * ud;
-    const long g0 = (long)(u * N) * ud + j;
-    zd gh[AMMSE_MAX_RX];
+  {
+    struct LZ {
+      cx<R> a[AMMSE_MAX_RX], q[AMMSE_MAX_RX];
+    };
+    auto ld = [&](int e) {
+      const int u = e / ud, j = e - u * ud;
+      const long g0 = (long)(u * N) * ud + j;
+      LZ l;
 #pragma unroll
-    for (int k = 0; k < AMMSE_MAX_RX; ++k) {
-      gh[k] = {0.0, 0.0};
-      if (k < N) {
-        const cx<R> a = Gp[g0 + (long)k * ud], q = Gq[g0 + (long)k * ud];
-        gh[k] = {(1.0 + om) * (double)a.x - om * (double)q.x,
-                 (1.0 + om) * (double)a.y - om * (double)q.y};
+      for (int k = 0; k < AMMSE_MAX_RX; ++k) {
+        const long o = g0 + (long)min(k, N - 1) * ud;
+        l.a[k] = Gp[o];
+        l.q[k] = Gq[o];
       }
-    }
-    const int j0 = u * d;
-    const bool own = j >= j0 && j < j0 + d;
-    const double is = sm.invsig[u];
+      return l;
+    };
+    u_batched<2>(U * ud, ld, [&](int e, const LZ& l) {
+      const int u = e / ud, j = e - u * ud;
+      const long g0 = (long)(u * N) * ud + j;
+      zd gh[AMMSE_MAX_RX];
 #pragma unroll
-    for (int n = 0; n < AMMSE_MAX_RX; ++n) {
-      if (n < N) {
-        zd acc = {0.0, 0.0};
+      for (int k = 0; k < AMMSE_MAX_RX; ++k)
+        gh[k] = (k < N) ? zd{(1.0 + om) * (double)l.a[k].x - om * (double)l.q[k].x,
+                             (1.0 + om) * (double)l.a[k].y - om * (double)l.q[k].y}
+                        : zd{0.0, 0.0};
+      const int j0 = u * d;
+      const bool own = j >= j0 && j < j0 + d;
+      const double is = sm.invsig[u];
 #pragma unroll
-        for (int k = 0; k < AMMSE_MAX_RX; ++k)
-          if (k < N) acc = acc + Do[u * 16 + n * 4 + k] * gh[k];
-        if (own) acc = acc - Yo[u * 16 + n * 4 + (j - j0)];
-        Z[g0 + (long)n * ud] = from_d<R>(scal(is, acc));
+      for (int n = 0; n < AMMSE_MAX_RX; ++n) {
+        if (n < N) {
+          zd acc = {0.0, 0.0};
+#pragma unroll
+          for (int k = 0; k < AMMSE_MAX_RX; ++k)
+            if (k < N) acc = acc + Do[u * 16 + n * 4 + k] * gh[k];
+          if (own) acc = acc - Yo[u * 16 + n * 4 + (j - j0)];
+          Z[g0 + (long)n * ud] = from_d<R>(scal(is, acc));
+        }
       }
-    }
+    });
   }
   __syncthreads();
   channel_gemm64<R, true>(M, ud, w.un, w.H, M, Z, ud, sm.tiles,
@@ -284,20 +330,27 @@ __device__ void u_step(const UView<R>& w, USmem<R>& sm, int t, double gamma, boo
   __syncthreads();
   double pw = 0.0;
   const int nv = (int)w.v;
-  for (int e = tid; e < nv; e += AMMSE_BLOCK) {
-    const zd v = to_d(Vp[e]), q = to_d(Vq[e]), g = to_d(Gr[e]);
-    const cx<R> x = from_d<R>(zd{(1.0 + om) * v.x - om * q.x - gamma * g.x,
-                                 (1.0 + om) * v.y - om * q.y - gamma * g.y});
-    Vt[e] = x;
-    pw += nrm2(to_d(x));
-  }
+  struct LV {
+    cx<R> v, q, g;
+  };
+  u_batched<4>(
+      nv, [&](int e) { return LV{Vp[e], Vq[e], Gr[e]}; },
+      [&](int e, const LV& l) {
+        const zd v = to_d(l.v), q = to_d(l.q), g = to_d(l.g);
+        const cx<R> x = from_d<R>(zd{(1.0 + om) * v.x - om * q.x - gamma * g.x,
+                                     (1.0 + om) * v.y - om * q.y - gamma * g.y});
+        Vt[e] = x;
+        pw += nrm2(to_d(x));
+      });
   pw = block_sum(pw, sm.red);
   const double s = (pw > w.P) ? sqrt(w.P / pw) : 1.0;
   if (tid == 0) {
     spo[0] = s;
     spo[1] = pw;
   }
-  for (int e = tid; e < nv; e += AMMSE_BLOCK) Vn[e] = from_d<R>(scal(s, to_d(Vt[e])));
+  u_batched<4>(
+      nv, [&](int e) { return Vt[e]; },
+      [&](int e, const cx<R>& x) { Vn[e] = from_d<R>(scal(s, to_d(x))); });
   __syncthreads();
   u_product(w, sm, Gn, Vn);
   __syncthreads();
@@ -413,24 +466,42 @@ __device__ void u_zbar_blocks(const UView<R>& w, USmem<R>& sm, const cx<R>* Gp, 
 #pragma unroll
     for (int q = 0; q < 16; ++q) sj[q] = {0.0, 0.0};
     const long r0 = (long)(uu * N) * ud;
-    for (int j = li; j < ud; j += 16) {
-      zd zb[AMMSE_MAX_RX], gh[AMMSE_MAX_RX];
+    // the lane's columns in chunks of CH, the loads of a chunk issued together
+    // (one column at a time: two more keep the adjoint kernel above 256 registers)
+    constexpr int CH = 1;
+    for (int jc = li; jc < ud; jc += 16 * CH) {
+      cx<R> zl[CH][AMMSE_MAX_RX], al[CH][AMMSE_MAX_RX], ql[CH][AMMSE_MAX_RX];
 #pragma unroll
-      for (int k = 0; k < AMMSE_MAX_RX; ++k) {
-        zb[k] = {0.0, 0.0};
-        gh[k] = {0.0, 0.0};
-        if (k < N) {
-          zb[k] = scal(is, to_d(w.Zb[r0 + (long)k * ud + j]));
-          const cx<R> a = Gp[r0 + (long)k * ud + j], q = Gq[r0 + (long)k * ud + j];
-          gh[k] = {(1.0 + om) * (double)a.x - om * (double)q.x,
-                   (1.0 + om) * (double)a.y - om * (double)q.y};
+      for (int c = 0; c < CH; ++c) {
+        const int j = min(jc + 16 * c, ud - 1);
+#pragma unroll
+        for (int k = 0; k < AMMSE_MAX_RX; ++k) {
+          const long o = r0 + (long)min(k, N - 1) * ud + j;
+          zl[c][k] = w.Zb[o];
+          al[c][k] = Gp[o];
+          ql[c][k] = Gq[o];
         }
       }
 #pragma unroll
-      for (int x = 0; x < AMMSE_MAX_RX; ++x)
+      for (int c = 0; c < CH; ++c) {
+        if (jc + 16 * c >= ud) continue;
+        zd zb[AMMSE_MAX_RX], gh[AMMSE_MAX_RX];
 #pragma unroll
-        for (int y = 0; y < AMMSE_MAX_RX; ++y)
-          if (x < N && y < N) sj[x * 4 + y] = sj[x * 4 + y] + mulc(zb[x], gh[y]);
+        for (int k = 0; k < AMMSE_MAX_RX; ++k) {
+          zb[k] = {0.0, 0.0};
+          gh[k] = {0.0, 0.0};
+          if (k < N) {
+            zb[k] = scal(is, to_d(zl[c][k]));
+            gh[k] = {(1.0 + om) * (double)al[c][k].x - om * (double)ql[c][k].x,
+                     (1.0 + om) * (double)al[c][k].y - om * (double)ql[c][k].y};
+          }
+        }
+#pragma unroll
+        for (int x = 0; x < AMMSE_MAX_RX; ++x)
+#pragma unroll
+          for (int y = 0; y < AMMSE_MAX_RX; ++y)
+            if (x < N && y < N) sj[x * 4 + y] = sj[x * 4 + y] + mulc(zb[x], gh[y]);
+      }
     }
 #pragma unroll
     for (int step = 0; step < 4; ++step) {
@@ -620,26 +691,35 @@ __global__ __launch_bounds__(AMMSE_BLOCK, 1) void unroll_backward_kernel(ammse_k
       const cx<R>* Vtil = w.Vts + (k - 1) * w.v;
       const cx<R>* Gr = w.Grs + (k - 1) * w.v;
       double dot = 0.0;
-      for (int e = tid; e < nv; e += AMMSE_BLOCK) {
-        const zd a = to_d(Vbt[e]), x = to_d(Vtil[e]);
-        dot += a.x * x.x + a.y * x.y;
-      }
+      struct LB {
+        cx<R> a, x;
+      };
+      u_batched<4>(
+          nv, [&](int e) { return LB{Vbt[e], Vtil[e]}; },
+          [&](int, const LB& l) {
+            const zd a = to_d(l.a), x = to_d(l.x);
+            dot += a.x * x.x + a.y * x.y;
+          });
       dot = block_sum(dot, sm.red);
       const bool active = pw > w.P;
       const double c2 = active ? s / pw * dot : 0.0;
       // (c) gamma: gbar = -Re<V~bar, Grad>; V^bar = V~bar; Gradbar = -gamma V~bar
       double gd = 0.0;
-      for (int e = tid; e < nv; e += AMMSE_BLOCK) {
-        const zd a = to_d(Vbt[e]), x = to_d(Vtil[e]);
-        const zd vb = active ? zd{s * a.x - c2 * x.x, s * a.y - c2 * x.y} : a;
-        const zd g = to_d(Gr[e]);
-        gd += vb.x * g.x + vb.y * g.y;
-        const zd v1 = to_d(Vb1[e]), v2 = to_d(Vb2[e]);
-        Vb1[e] = from_d<R>(v1 + scal(1.0 + om, vb));
-        Vb2[e] = from_d<R>(v2 - scal(om, vb));
-        w.Tb[e] = from_d<R>(scal(-gamma, vb));
-        Vbt[e] = {R(0), R(0)};
-      }
+      struct LC {
+        cx<R> a, x, g, v1, v2;
+      };
+      u_batched<4>(
+          nv, [&](int e) { return LC{Vbt[e], Vtil[e], Gr[e], Vb1[e], Vb2[e]}; },
+          [&](int e, const LC& l) {
+            const zd a = to_d(l.a), x = to_d(l.x);
+            const zd vb = active ? zd{s * a.x - c2 * x.x, s * a.y - c2 * x.y} : a;
+            const zd g = to_d(l.g);
+            gd += vb.x * g.x + vb.y * g.y;
+            Vb1[e] = from_d<R>(to_d(l.v1) + scal(1.0 + om, vb));
+            Vb2[e] = from_d<R>(to_d(l.v2) - scal(om, vb));
+            w.Tb[e] = from_d<R>(scal(-gamma, vb));
+            Vbt[e] = {R(0), R(0)};
+          });
       gd = block_sum(gd, sm.red);
       if (tid == 0) q.dgamma[(long)b * T + (t - 1)] = -gd;
       // (d) Grad = 2 H^H Z: Zbar = 2 H Gradbar, dH += 2 Z Gradbar^H
@@ -658,48 +738,86 @@ __global__ __launch_bounds__(AMMSE_BLOCK, 1) void unroll_backward_kernel(ammse_k
       u_zbar_blocks(w, sm, Gp, Gq, om);
       tid = utid();
       const zd* Dt = w.Ds + uo;
-      for (int e = tid; e < U * ud; e += AMMSE_BLOCK) {
-        const int u = e / ud, j = e - u * ud;
-        const long g0 = (long)(u * N) * ud + j;
-        const double is = sm.invsig[u];
-        zd zb[AMMSE_MAX_RX];
+      {
+        struct LE {
+          cx<R> zb[AMMSE_MAX_RX], b1[AMMSE_MAX_RX], b2[AMMSE_MAX_RX];
+        };
+        auto ld = [&](int e) {
+          const int u = e / ud, j = e - u * ud;
+          const long g0 = (long)(u * N) * ud + j;
+          LE l;
 #pragma unroll
-        for (int kk = 0; kk < AMMSE_MAX_RX; ++kk)
-          zb[kk] = (kk < N) ? scal(is, to_d(w.Zb[g0 + (long)kk * ud])) : zd{0.0, 0.0};
-        for (int n = 0; n < N; ++n) {
-          zd acc = {0.0, 0.0};
+          for (int kk = 0; kk < AMMSE_MAX_RX; ++kk) {
+            const long o = g0 + (long)min(kk, N - 1) * ud;
+            l.zb[kk] = w.Zb[o];
+            l.b1[kk] = Gb1[o];
+            l.b2[kk] = Gb2[o];
+          }
+          return l;
+        };
+        u_batched<2>(U * ud, ld, [&](int e, const LE& l) {
+          const int u = e / ud, j = e - u * ud;
+          const long g0 = (long)(u * N) * ud + j;
+          const double is = sm.invsig[u];
+          zd zb[AMMSE_MAX_RX];
 #pragma unroll
           for (int kk = 0; kk < AMMSE_MAX_RX; ++kk)
-            if (kk < N) acc = acc + Dt[u * 16 + n * 4 + kk] * zb[kk];
-          const long o = g0 + (long)n * ud;
-          Gb1[o] = from_d<R>(to_d(Gb1[o]) + scal(1.0 + om, acc));
-          Gb2[o] = from_d<R>(to_d(Gb2[o]) - scal(om, acc));
-        }
+            zb[kk] = (kk < N) ? scal(is, to_d(l.zb[kk])) : zd{0.0, 0.0};
+#pragma unroll
+          for (int n = 0; n < AMMSE_MAX_RX; ++n) {
+            if (n >= N) continue;
+            zd acc = {0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < AMMSE_MAX_RX; ++kk)
+              if (kk < N) acc = acc + Dt[u * 16 + n * 4 + kk] * zb[kk];
+            const long o = g0 + (long)n * ud;
+            Gb1[o] = from_d<R>(to_d(l.b1[n]) + scal(1.0 + om, acc));
+            Gb2[o] = from_d<R>(to_d(l.b2[n]) - scal(om, acc));
+          }
+        });
       }
       __syncthreads();
       // (f) receivers and weights of G^{t-1}
       u_receiver_adjoint(w, sm, Gp, w.UWs + uo, w.Es + uo, w.Los + uo, st2);
       tid = utid();
-      for (int e = tid; e < U * ud; e += AMMSE_BLOCK) {
-        const int u = e / ud, j = e - u * ud;
-        const long g0 = (long)(u * N) * ud + j;
-        const bool own = j >= u * d && j < u * d + d;
-        zd g[AMMSE_MAX_RX];
+      {
+        struct LF {
+          cx<R> g[AMMSE_MAX_RX], b1[AMMSE_MAX_RX];
+        };
+        auto ld = [&](int e) {
+          const int u = e / ud, j = e - u * ud;
+          const long g0 = (long)(u * N) * ud + j;
+          LF l;
 #pragma unroll
-        for (int kk = 0; kk < AMMSE_MAX_RX; ++kk)
-          g[kk] = (kk < N && !own) ? to_d(Gp[g0 + (long)kk * ud]) : zd{0.0, 0.0};
-        for (int n = 0; n < N; ++n) {
-          zd acc = {0.0, 0.0};
-          if (own) {
-            acc = w.Pb[u * 16 + n * 4 + (j - u * d)];
-          } else {
-#pragma unroll
-            for (int kk = 0; kk < AMMSE_MAX_RX; ++kk)
-              if (kk < N) acc = acc + w.Pa[u * 16 + n * 4 + kk] * g[kk];
+          for (int kk = 0; kk < AMMSE_MAX_RX; ++kk) {
+            const long o = g0 + (long)min(kk, N - 1) * ud;
+            l.g[kk] = Gp[o];
+            l.b1[kk] = Gb1[o];
           }
-          const long o = g0 + (long)n * ud;
-          Gb1[o] = from_d<R>(to_d(Gb1[o]) + acc);
-        }
+          return l;
+        };
+        u_batched<2>(U * ud, ld, [&](int e, const LF& l) {
+          const int u = e / ud, j = e - u * ud;
+          const long g0 = (long)(u * N) * ud + j;
+          const bool own = j >= u * d && j < u * d + d;
+          zd g[AMMSE_MAX_RX];
+#pragma unroll
+          for (int kk = 0; kk < AMMSE_MAX_RX; ++kk)
+            g[kk] = (kk < N && !own) ? to_d(l.g[kk]) : zd{0.0, 0.0};
+#pragma unroll
+          for (int n = 0; n < AMMSE_MAX_RX; ++n) {
+            if (n >= N) continue;
+            zd acc = {0.0, 0.0};
+            if (own) {
+              acc = w.Pb[u * 16 + n * 4 + (j - u * d)];
+            } else {
+#pragma unroll
+              for (int kk = 0; kk < AMMSE_MAX_RX; ++kk)
+                if (kk < N) acc = acc + w.Pa[u * 16 + n * 4 + kk] * g[kk];
+            }
+            Gb1[g0 + (long)n * ud] = from_d<R>(to_d(l.b1[n]) + acc);
+          }
+        });
       }
       __syncthreads();
     }
