@@ -880,7 +880,7 @@ __device__ __forceinline__ void fast_body(const ammse_kparams_t& p) {
 __global__ __launch_bounds__(64) void ammse_fast_bound_kernel(ammse_kparams_t p, double* gb) {
   constexpr int M = Shape64::M, UN = Shape64::UN, LD = M + 1;
   __shared__ float2 Hs[UN * LD];
-  __shared__ double2 xs[M];       // broadcast of the vector being multiplied
+  __shared__ float2 xs[M];        // broadcast of the vector being multiplied
   __shared__ double2 tp[64];      // tridiagonal pairs of the Ritz-value search
   const ammse_desc_t D = p.desc[blockIdx.x];
   const int lane = threadIdx.x;
@@ -896,26 +896,37 @@ __global__ __launch_bounds__(64) void ammse_fast_bound_kernel(ammse_kparams_t p,
   const double ltol = 1e-8;
   double ta = 0.0, tb = 0.0, beta_prev = 0.0, tmax = 0.0, theta = 0.0;
   for (int j = 0;; ++j) {
-    // y_r = s_r^2 (H x)_r  (lane r), then w_i = (H^H y)_i  (lane i)
+    // y_r = s_r^2 (H x)_r  (lane r), then w_i = (H^H y)_i  (lane i); the
+    // products in float (H is stored in float) on two accumulator pairs,
+    // combined in double
     __syncthreads();
-    xs[lane] = make_double2(x.x, x.y);
+    xs[lane] = make_float2((float)x.x, (float)x.y);
     __syncthreads();
-    zd y = {0.0, 0.0};
-    for (int k = 0; k < M; ++k) {
-      const float2 h = Hs[lane * LD + k];
-      const double2 xv = xs[k];
-      y = y + zd{(double)h.x, (double)h.y} * zd{xv.x, xv.y};
+    float2 ya = make_float2(0.f, 0.f), yb = make_float2(0.f, 0.f);
+#pragma unroll 16
+    for (int k = 0; k < M; k += 2) {
+      const float2 h0 = Hs[lane * LD + k], h1 = Hs[lane * LD + k + 1];
+      const float2 x0 = xs[k], x1 = xs[k + 1];
+      ya.x = fmaf(-h0.y, x0.y, fmaf(h0.x, x0.x, ya.x));
+      ya.y = fmaf(h0.y, x0.x, fmaf(h0.x, x0.y, ya.y));
+      yb.x = fmaf(-h1.y, x1.y, fmaf(h1.x, x1.x, yb.x));
+      yb.y = fmaf(h1.y, x1.x, fmaf(h1.x, x1.y, yb.y));
     }
-    y = scal(s2, y);
+    const zd y = scal(s2, zd{(double)ya.x + (double)yb.x, (double)ya.y + (double)yb.y});
     __syncthreads();
-    xs[lane] = make_double2(y.x, y.y);
+    xs[lane] = make_float2((float)y.x, (float)y.y);
     __syncthreads();
-    zd w = {0.0, 0.0};
-    for (int r = 0; r < UN; ++r) {
-      const float2 h = Hs[r * LD + lane];
-      const double2 yv = xs[r];
-      w = w + zd{(double)h.x, -(double)h.y} * zd{yv.x, yv.y};
+    float2 wa = make_float2(0.f, 0.f), wb = make_float2(0.f, 0.f);
+#pragma unroll 16
+    for (int r = 0; r < UN; r += 2) {   // conj(H[r][i]) y_r
+      const float2 h0 = Hs[r * LD + lane], h1 = Hs[(r + 1) * LD + lane];
+      const float2 y0 = xs[r], y1 = xs[r + 1];
+      wa.x = fmaf(h0.y, y0.y, fmaf(h0.x, y0.x, wa.x));
+      wa.y = fmaf(-h0.y, y0.x, fmaf(h0.x, y0.y, wa.y));
+      wb.x = fmaf(h1.y, y1.y, fmaf(h1.x, y1.x, wb.x));
+      wb.y = fmaf(-h1.y, y1.x, fmaf(h1.x, y1.y, wb.y));
     }
+    const zd w = {(double)wa.x + (double)wb.x, (double)wa.y + (double)wb.y};
     double al = x.x * w.x + x.y * w.y, yy = nrm2(w), py = pp.x * w.x + pp.y * w.y;
     wave_sum3_dpp(al, yy, py);
     const double bb = sqrt(fmax(yy - al * al - 2.0 * beta_prev * py + beta_prev * beta_prev, 0.0));
