@@ -232,9 +232,21 @@ __device__ void block_gemm_mfma(int m, int n, int k, const TA* __restrict__ A, l
   };
   TA ra[NA];   // raw operand values: converted when stashed, so the
   TB rb[NB];   // prefetch loads stay in flight during the products
-  auto fetch = [&](int s) {
-    const int tile = s / nk, k0 = (s - tile * nk) * KC;
-    const int i0 = (tile / ntn) * TM, j0 = (tile % ntn) * TN;
+  // step cursor (k-chunk, tile row, tile column), advanced step by step (no
+  // divisions): at the top of a step it moves to the next step, which is the
+  // one the prefetch then loads
+  int ck = 0, ci = 0, cj = 0;
+  auto advance = [&]() __attribute__((always_inline)) {
+    if (++ck == nk) {
+      ck = 0;
+      if (++cj == ntn) {
+        cj = 0;
+        ++ci;
+      }
+    }
+  };
+  auto fetch = [&]() __attribute__((always_inline)) {
+    const int k0 = ck * KC, i0 = ci * TM, j0 = cj * TN;
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
       int row, kk;
@@ -253,9 +265,10 @@ __device__ void block_gemm_mfma(int m, int n, int k, const TA* __restrict__ A, l
     }
   };
   floatx4_t P[RB][CB][3];
-  fetch(0);
+  fetch();
   for (int s = 0; s < steps; ++s) {
-    const int tile = s / nk, kc = s - tile * nk;
+    const int kc = ck, i0t = ci * TM, j0t = cj * TN;
+    advance();
     if (kc == 0) {
 #pragma unroll
       for (int i = 0; i < RB; ++i)
@@ -295,14 +308,14 @@ __device__ void block_gemm_mfma(int m, int n, int k, const TA* __restrict__ A, l
       if constexpr (PRE) {
         const int blk = g / (4 / EG), r0 = EG * (g % (4 / EG));
         const int i = blk / CB, j = blk - i * CB;
-        const int i0 = (tile / ntn) * TM, j0 = (tile % ntn) * TN;
+        const int i0 = i0t, j0 = j0t;
         const int gj = min(j0 + 16 * j + li, n - 1);
 #pragma unroll
         for (int r = 0; r < EG; ++r)
           pl[r] = epi.pre(min(i0 + 16 * (RB * wave + i) + 4 * lk + r0 + r, m - 1), gj);
       }
     };
-    if (!(PRE && last) && s + 1 < steps) fetch(s + 1);
+    if (!(PRE && last) && s + 1 < steps) fetch();
     if constexpr (Tl::LOW) {
       bf16x8_t axr[RB], axi[RB], bxr[CB], bxi[CB];
 #pragma unroll
@@ -361,7 +374,7 @@ __device__ void block_gemm_mfma(int m, int n, int k, const TA* __restrict__ A, l
       }
     }
     if (last) {
-      const int i0 = (tile / ntn) * TM, j0 = (tile % ntn) * TN;
+      const int i0 = i0t, j0 = j0t;
       if constexpr (PRE) {
         preload(0);
 #pragma unroll
@@ -377,7 +390,7 @@ __device__ void block_gemm_mfma(int m, int n, int k, const TA* __restrict__ A, l
           }
           if (g + 1 < RB * CB * (4 / EG)) preload(g + 1);
         }
-        if (s + 1 < steps) fetch(s + 1);
+        if (s + 1 < steps) fetch();
       } else {
 #pragma unroll
         for (int i = 0; i < RB; ++i)
@@ -452,9 +465,22 @@ __device__ void block_gemm_mfma_ks(int m, int n, int k, const TA* __restrict__ A
   };
   TA ra[NA];
   TB rb[NB];
-  auto fetch = [&](int s) {
-    const int tile = s / nks, c0 = (s - tile * nks) * KS;       // first chunk of the step
-    const int i0 = (tile / ntn) * TM, j0 = (tile % ntn) * TN;
+  // step cursor (step within the tile, tile row, tile column), advanced step
+  // by step (no divisions): at the top of a step it moves to the next step,
+  // which is the one the prefetch then loads
+  int ck = 0, ci = 0, cj = 0;
+  auto advance = [&]() __attribute__((always_inline)) {
+    if (++ck == nks) {
+      ck = 0;
+      if (++cj == ntn) {
+        cj = 0;
+        ++ci;
+      }
+    }
+  };
+  auto fetch = [&]() __attribute__((always_inline)) {
+    const int c0 = ck * KS;                                     // first chunk of the step
+    const int i0 = ci * TM, j0 = cj * TN;
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
       int slot, row, kk;
@@ -473,9 +499,10 @@ __device__ void block_gemm_mfma_ks(int m, int n, int k, const TA* __restrict__ A
     }
   };
   floatx4_t P[3];
-  fetch(0);
+  fetch();
   for (int s = 0; s < steps; ++s) {
-    const int tile = s / nks, kc = s - tile * nks;
+    const int kc = ck, i0t = ci * TM, j0t = cj * TN;
+    advance();
     if (kc == 0) {
 #pragma unroll
       for (int q = 0; q < 3; ++q) P[q] = floatx4_t{0.f, 0.f, 0.f, 0.f};
@@ -500,7 +527,7 @@ __device__ void block_gemm_mfma_ks(int m, int n, int k, const TA* __restrict__ A
       Bs[TN * LD + col * LD + kk] = (T)(CONJB ? -vb.y : vb.y);
     }
     __syncthreads();
-    if (s + 1 < steps) fetch(s + 1);
+    if (s + 1 < steps) fetch();
     const T* AsR = base + kg * SLOT;
     const T* AsI = AsR + TM * LD;
     const T* BsR = AsI + TM * LD;
@@ -544,7 +571,7 @@ __device__ void block_gemm_mfma_ks(int m, int n, int k, const TA* __restrict__ A
         }
       }
       if (kg == 0) {
-        const int i0 = (tile / ntn) * TM, j0 = (tile % ntn) * TN;
+        const int i0 = i0t, j0 = j0t;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int gi = i0 + 16 * rbk + 4 * lk + r, gj = j0 + 16 * cbk + li;
