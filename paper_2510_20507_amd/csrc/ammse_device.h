@@ -373,6 +373,12 @@ __device__ __forceinline__ zd l4_colk(zd v) {
   return {swz64<PAT>(v.x), swz64<PAT>(v.y)};
 }
 
+// Quotient i / n for 0 <= i < 2^22 from rn = 1 / n (float, n >= 1), without
+// the integer division sequence: (i + 1/2) / n is at least 1 / (2n) away from
+// every integer, more than the float rounding of the product can move it, so
+// truncation gives the exact quotient.
+__device__ __forceinline__ int quot(int i, float rn) { return (int)(((float)i + 0.5f) * rn); }
+
 // 1 / sqrt(x) for finite x >= 1e-300: the hardware estimate refined by two
 // Newton steps y <- y + y (1 - x y^2) / 2, which square the relative error
 // (to about one unit in the last place), in 7 dependent operations instead of

@@ -191,6 +191,7 @@ template <class R, int NN>
 __device__ __forceinline__ void kq_form_n(const cx<R>* __restrict__ Q, const zd* __restrict__ Cm,
                                           cx<R>* __restrict__ K, int U, int tid) {
   const int un = U * NN, ne = un * un;
+  const float run = 1.f / (float)un;
   constexpr int QB = 2;
   for (int e0 = tid; e0 < ne; e0 += QB * AMMSE_BLOCK) {
     cx<R> qb[QB][NN][NN];
@@ -200,7 +201,7 @@ __device__ __forceinline__ void kq_form_n(const cx<R>* __restrict__ Q, const zd*
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
       const int e = min(e0 + q * AMMSE_BLOCK, ne - 1);
-      const int i = e / un, j = e - i * un;
+      const int i = quot(e, run), j = e - i * un;
       const int u = i / NN, a = i - u * NN, v = j / NN, b = j - v * NN;
       ii[q] = i;
       jj[q] = j;
@@ -462,6 +463,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   // G_c = S H_{:,c} (scale_c X_c) for every BS c: X holds the precoders up
   // to the per-BS factor of the sum-power projection, which is applied here
   // (by linearity) instead of rewriting X.
+  const float rN = 1.f / (float)N;   // row i of G belongs to user quot(i, rN)
   auto channel_product = [&](cx<R>* G, const cx<R>* X, const double* scale, bool lowp) {
     for (int c = 0; c < C; ++c) {
       const int nc = sm.cu[c] * d;
@@ -469,7 +471,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
       cx<R>* __restrict__ Gc = G + (long)un * sm.colOff[c];
       const double sc = scale[c];
       auto epi = [&](int i, int j, cx<R> v) {
-        const R f = (R)(sc * sm.invsig[i / N]);
+        const R f = (R)(sc * sm.invsig[quot(i, rN)]);
         Gc[(long)i * nc + j] = {f * v.x, f * v.y};
       };
       if constexpr (sizeof(R) == 4) {
@@ -1536,6 +1538,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
         const int nc = sm.cu[c] * d;
         const long base = (long)un * sm.colOff[c];
         const int ne = U * nc;
+        const float rnc = 1.f / (float)max(nc, 1);
         constexpr int QB = sizeof(R) == 4 ? (NN <= 2 ? 4 : 2) : 1;
         for (int e0 = tid; e0 < ne; e0 += QB * AMMSE_BLOCK) {
           int uq[QB], jq[QB];
@@ -1547,7 +1550,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
           for (int q = 0; q < QB; ++q) {
             const int e = min(e0 + q * AMMSE_BLOCK, ne - 1);
             live[q] = e0 + q * AMMSE_BLOCK < ne;
-            const int u = e / nc, j = e - u * nc;
+            const int u = quot(e, rnc), j = e - u * nc;
             uq[q] = u;
             jq[q] = j;
             gq0[q] = base + (long)(u * NN) * nc + j;

@@ -101,6 +101,7 @@ struct UView {
   zd* Pa;       // U x 16 per-user adjoint blocks (Dbar, then Jbar + Jbar^H)
   zd* Pb;       // U x 16 (Ybar, then Fbar)
   size_t v, g;  // elements of one V / G matrix
+  float rud, rN;  // 1 / (U d) and 1 / N (quotients by quot)
 };
 
 template <class R>
@@ -138,6 +139,8 @@ __device__ UView<R> make_view(const ammse_desc_t& D, const ammse_kparams_t& p,
   w.Pb = (zd*)(ws + L.Pb);
   w.v = (size_t)D.M * D.ud;
   w.g = (size_t)D.un * D.ud;
+  w.rud = 1.f / (float)D.ud;
+  w.rN = 1.f / (float)D.N;
   return w;
 }
 
@@ -147,7 +150,7 @@ __device__ void u_product(const UView<R>& w, USmem<R>& sm, cx<R>* G, const cx<R>
   const int N = w.N, ud = w.ud;
   channel_gemm64<R, false>(w.un, ud, w.M, w.H, w.M, V, ud, sm.tiles,
                          [&](int i, int j, cx<R> v) {
-                           const R f = (R)sm.invsig[i / N];
+                           const R f = (R)sm.invsig[quot(i, w.rN)];
                            G[(long)i * ud + j] = {f * v.x, f * v.y};
                          });
 }
@@ -286,7 +289,7 @@ __device__ void u_step(const UView<R>& w, USmem<R>& sm, int t, double gamma, boo
       cx<R> a[AMMSE_MAX_RX], q[AMMSE_MAX_RX];
     };
     auto ld = [&](int e) {
-      const int u = e / ud, j = e - u * ud;
+      const int u = quot(e, w.rud), j = e - u * ud;
       const long g0 = (long)(u * N) * ud + j;
       LZ l;
 #pragma unroll
@@ -298,7 +301,7 @@ __device__ void u_step(const UView<R>& w, USmem<R>& sm, int t, double gamma, boo
       return l;
     };
     u_batched<2>(U * ud, ld, [&](int e, const LZ& l) {
-      const int u = e / ud, j = e - u * ud;
+      const int u = quot(e, w.rud), j = e - u * ud;
       const long g0 = (long)(u * N) * ud + j;
       zd gh[AMMSE_MAX_RX];
 #pragma unroll
@@ -636,7 +639,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, 1) void unroll_backward_kernel(ammse_k
       }
       cx<R>* GbT = w.Gb + (long)(T % 3) * ng;
       for (int e = tid; e < U * ud; e += AMMSE_BLOCK) {
-        const int u = e / ud, j = e - u * ud;
+        const int u = quot(e, w.rud), j = e - u * ud;
         const double f = -2.0 * gw * sm.alpha[u] / M_LN2;
         const long g0 = (long)(u * N) * ud + j;
         const bool own = j >= u * d && j < u * d + d;
@@ -668,7 +671,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, 1) void unroll_backward_kernel(ammse_k
       // (a) G^t = S H V^t: dH += (S Gbar) V^H, Vbar^t += H^H (S Gbar)
       tid = utid();
       for (int e = tid; e < ng; e += AMMSE_BLOCK) {
-        const double f = sm.invsig[(e / ud) / N];
+        const double f = sm.invsig[quot(quot(e, w.rud), w.rN)];
         const cx<R> x = Gbt[e];
         Gbt[e] = {(R)f * x.x, (R)f * x.y};
       }
@@ -743,7 +746,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, 1) void unroll_backward_kernel(ammse_k
           cx<R> zb[AMMSE_MAX_RX], b1[AMMSE_MAX_RX], b2[AMMSE_MAX_RX];
         };
         auto ld = [&](int e) {
-          const int u = e / ud, j = e - u * ud;
+          const int u = quot(e, w.rud), j = e - u * ud;
           const long g0 = (long)(u * N) * ud + j;
           LE l;
 #pragma unroll
@@ -756,7 +759,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, 1) void unroll_backward_kernel(ammse_k
           return l;
         };
         u_batched<2>(U * ud, ld, [&](int e, const LE& l) {
-          const int u = e / ud, j = e - u * ud;
+          const int u = quot(e, w.rud), j = e - u * ud;
           const long g0 = (long)(u * N) * ud + j;
           const double is = sm.invsig[u];
           zd zb[AMMSE_MAX_RX];
@@ -785,7 +788,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, 1) void unroll_backward_kernel(ammse_k
           cx<R> g[AMMSE_MAX_RX], b1[AMMSE_MAX_RX];
         };
         auto ld = [&](int e) {
-          const int u = e / ud, j = e - u * ud;
+          const int u = quot(e, w.rud), j = e - u * ud;
           const long g0 = (long)(u * N) * ud + j;
           LF l;
 #pragma unroll
@@ -797,7 +800,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, 1) void unroll_backward_kernel(ammse_k
           return l;
         };
         u_batched<2>(U * ud, ld, [&](int e, const LF& l) {
-          const int u = e / ud, j = e - u * ud;
+          const int u = quot(e, w.rud), j = e - u * ud;
           const long g0 = (long)(u * N) * ud + j;
           const bool own = j >= u * d && j < u * d + d;
           zd g[AMMSE_MAX_RX];
@@ -827,7 +830,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, 1) void unroll_backward_kernel(ammse_k
     cx<R>* Gb0 = w.Gb;   // slot 0 mod 3
     tid = utid();
     for (int e = tid; e < ng; e += AMMSE_BLOCK) {
-      const double f = sm.invsig[(e / ud) / N];
+      const double f = sm.invsig[quot(quot(e, w.rud), w.rN)];
       const cx<R> x = Gb0[e];
       Gb0[e] = {(R)f * x.x, (R)f * x.y};
     }
