@@ -313,26 +313,33 @@ __global__ __launch_bounds__(AMMSE_BLOCK, 2) void ammse_bound_gram_kernel(ammse_
     if (p.cell_users[D.cell_off + c] == 0) continue;   // no precoder, no step
     const cx<float>* __restrict__ Hc = H + (long)c * un * M;
     cx<float>* __restrict__ Ac = Ab + (long)c * M * M;
-    for (int e = tid; e < un * M; e += AMMSE_BLOCK) {
-      const double f = sa[(e / M) / N];
-      const cx<float> h = Hc[e];
-      Rb[e] = {(float)(f * (double)h.x), (float)(f * (double)h.y)};
-    }
-    __syncthreads();
-    channel_gemm<float, true, false>(M, M, un, Rb, M, Rb, M, tiles, false, tile,
-                                     [&](int i, int j, cx<float> v) { Ac[(long)i * M + j] = v; });
-    __syncthreads();
-    for (int e = tid; e < M * M; e += AMMSE_BLOCK) {   // exactly Hermitian
-      const int i = e / M, j = e - i * M;
-      if (i < j) {
-        const cx<float> x = Ac[e], y = Ac[(long)j * M + i];
-        const cx<float> mm = {0.5f * (x.x + y.x), 0.5f * (x.y - y.y)};
-        Ac[e] = mm;
-        Ac[(long)j * M + i] = {mm.x, -mm.y};
-      } else if (i == j) {
-        Ac[e].y = 0.f;
+    // four elements per trip, every load issued before the stores; the row's
+    // user by quot (un M < 2^22)
+    const float rM = 1.f / (float)M, rN = 1.f / (float)N;
+    for (int e0 = tid; e0 < un * M; e0 += 4 * AMMSE_BLOCK) {
+      cx<float> h[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) h[q] = Hc[min(e0 + q * AMMSE_BLOCK, un * M - 1)];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = e0 + q * AMMSE_BLOCK;
+        if (e >= un * M) continue;
+        const double f = sa[quot(quot(e, rM), rN)];
+        Rb[e] = {(float)(f * (double)h[q].x), (float)(f * (double)h[q].y)};
       }
     }
+    __syncthreads();
+    // exactly Hermitian: the computed upper triangle, its conjugate transpose
+    // below the diagonal and a real diagonal
+    channel_gemm<float, true, false>(M, M, un, Rb, M, Rb, M, tiles, false, tile,
+                                     [&](int i, int j, cx<float> v) {
+                                       if (i < j) {
+                                         Ac[(long)i * M + j] = v;
+                                         Ac[(long)j * M + i] = {v.x, -v.y};
+                                       } else if (i == j) {
+                                         Ac[(long)i * M + j] = {v.x, 0.f};
+                                       }
+                                     });
     __syncthreads();
   }
   float2* qs = qsa + wave * (AMMSE_GRAM_WAVE_N + 16);
@@ -877,6 +884,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     // two elements per trip, all loads of both issued before their arithmetic
     // (the stores to R would otherwise order each trip's loads after the
     // previous trip's store)
+    const float rM = 1.f / (float)M, rd = 1.f / (float)d;   // quot: ud M <= 2^22
     for (int e0 = tid; e0 < ud * M; e0 += 2 * AMMSE_BLOCK) {
       cx<R> hv[2][4];
       zd cv[2][4];
@@ -884,8 +892,8 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int e = min(e0 + q * AMMSE_BLOCK, ud * M - 1);
-        const int i = e / M, m = e - i * M;
-        const int u = i / d, s = i - u * d;
+        const int i = quot(e, rM), m = e - i * M;
+        const int u = quot(i, rd), s = i - u * d;
         uu[q] = u;
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
