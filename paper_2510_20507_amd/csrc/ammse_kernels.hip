@@ -55,6 +55,7 @@ struct Smem {
   double lb[AMMSE_MAX_LANCZOS];
   double2 tp[64];   // Sturm-count operands of the FP32 Lanczos checks (wave 0)
   double red[16];
+  double gfix;   // the fixed step gamma_c of the options
   int fail;
   int imin;
 };
@@ -1379,6 +1380,11 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
   int iters_run = 0;
   int status = 0;
   bool have_bound = false;   // sm.gbound computed (once per solve, when first needed)
+  // a given fixed step (gamma_c > 0): its value waits in LDS, so that no
+  // register of the iteration loop holds it
+  const bool fixed_gamma = p.gamma_c > 0.0;
+  if (tid == 0) sm.gfix = p.gamma_c;
+  __syncthreads();
 
   for (int t = 1; t <= T; ++t) {
     const bool lowp = t <= p.lowp_iters;   // bfloat16 products in this iteration
@@ -1436,7 +1442,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     // step size of this iteration: adaptive in the windows, otherwise fixed
     const bool adaptive = t <= p.T_c || (p.rearm && switch_iter >= 1 && t >= switch_iter &&
                                          t < switch_iter + p.T_c);
-    const bool use_bound = !wm && stage2 && !adaptive && !(p.gamma_c > 0.0) &&
+    const bool use_bound = !wm && stage2 && !adaptive && !fixed_gamma &&
                            p.step_rule == AMMSE_STEP_BOUND;
     if (use_bound && !have_bound && bgram && p.bound_pre) {
       // written by ammse_bound_gram_kernel (launched before this kernel)
@@ -1509,8 +1515,8 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
           __syncthreads();
         }
       }
-    } else if (p.gamma_c > 0.0) {
-      if (tid < C) sm.gamma[tid] = p.gamma_c;
+    } else if (fixed_gamma) {
+      if (tid < C) sm.gamma[tid] = sm.gfix;
       __syncthreads();
     } else if (use_bound) {
       if (tid < C) sm.gamma[tid] = sm.gbound[tid];
@@ -1542,18 +1548,34 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
     // tighter budget).
     auto zbuild = [&](auto nn) __attribute__((always_inline)) {
       constexpr int NN = decltype(nn)::value;
+      // float storage with N <= 2: the users' D and Y blocks staged in LDS
+      // (the product tiles, free here), read there in the arithmetic, so the
+      // registers of their loads go to more elements per trip
+      constexpr bool DL = sizeof(R) == 4 && NN <= 2 && QP != 0;
+      cx<T>* Dl = (cx<T>*)sm.tiles;
+      cx<T>* Yl = Dl + U * NN * NN;
+      if constexpr (DL) {
+        static_assert(!DL || 2 * AMMSE_MAX_USERS * 4 * sizeof(cx<float>) <= tile_bytes<R>(),
+                      "the D and Y blocks fit the tile area");
+        for (int e = tid; e < U * NN * NN; e += AMMSE_BLOCK) {
+          const int u = e / (NN * NN), r = e - u * (NN * NN), n = r / NN, k = r - n * NN;
+          Dl[e] = DmT[u * 16 + n * 4 + k];
+          Yl[e] = YmT[u * 16 + n * 4 + k];
+        }
+        __syncthreads();
+      }
       for (int c = 0; c < C; ++c) {
         const int nc = sm.cu[c] * d;
         const long base = (long)un * sm.colOff[c];
         const int ne = U * nc;
         const float rnc = 1.f / (float)max(nc, 1);
-        constexpr int QB = sizeof(R) == 4 ? (NN <= 2 ? 4 : 2) : 1;
+        constexpr int QB = sizeof(R) == 4 ? (NN <= 2 ? (DL ? 6 : 4) : 2) : 1;
         for (int e0 = tid; e0 < ne; e0 += QB * AMMSE_BLOCK) {
           int uq[QB], jq[QB];
           long gq0[QB];
           bool live[QB];
           cx<R> ga[QB][NN], gb[QB][NN], x1[QB][NN], x2[QB][NN];
-          cx<T> dm[QB][NN][NN];
+          cx<T> dm[DL ? 1 : QB][NN][NN];
 #pragma unroll
           for (int q = 0; q < QB; ++q) {
             const int e = min(e0 + q * AMMSE_BLOCK, ne - 1);
@@ -1562,6 +1584,7 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
             uq[q] = u;
             jq[q] = j;
             gq0[q] = base + (long)(u * NN) * nc + j;
+            if (!live[q]) continue;   // (no loads for the trip's slots past the end)
 #pragma unroll
             for (int k = 0; k < NN; ++k) {
               ga[q][k] = Gp[gq0[q] + (long)k * nc];
@@ -1571,10 +1594,12 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
                 x2[q][k] = X2[gq0[q] + (long)k * nc];
               }
             }
+            if constexpr (!DL) {
 #pragma unroll
-            for (int n = 0; n < NN; ++n)
+              for (int n = 0; n < NN; ++n)
 #pragma unroll
-              for (int k = 0; k < NN; ++k) dm[q][n][k] = DmT[u * 16 + n * 4 + k];
+                for (int k = 0; k < NN; ++k) dm[q][n][k] = DmT[u * 16 + n * 4 + k];
+            }
           }
 #pragma unroll
           for (int q = 0; q < QB; ++q) {
@@ -1587,12 +1612,19 @@ __global__ __launch_bounds__(AMMSE_BLOCK, sizeof(R) == 4 ? 2 : 1) void ammse_sol
             const int j0 = sm.local[u] * d;
             const bool own = sm.cellOf[u] == c && j >= j0 && j < j0 + d;
             const T is = (T)sm.invsig[u];
+            const int qd = DL ? 0 : q;
+            if constexpr (DL) {
+#pragma unroll
+              for (int n = 0; n < NN; ++n)
+#pragma unroll
+                for (int k = 0; k < NN; ++k) dm[0][n][k] = Dl[(u * NN + n) * NN + k];
+            }
 #pragma unroll
             for (int n = 0; n < NN; ++n) {
               cx<T> acc = {T(0), T(0)};
 #pragma unroll
-              for (int k = 0; k < NN; ++k) acc = acc + dm[q][n][k] * gh[k];
-              if (own) acc = acc - YmT[u * 16 + n * 4 + (j - j0)];
+              for (int k = 0; k < NN; ++k) acc = acc + dm[qd][n][k] * gh[k];
+              if (own) acc = acc - (DL ? Yl[(u * NN + n) * NN + (j - j0)] : YmT[u * 16 + n * 4 + (j - j0)]);
               const long e = gq0[q] + (long)n * nc;
               if (!live[q]) continue;
               if (rpath) {
