@@ -225,6 +225,9 @@ def mixed_precision(reps: int = 2):
                                   "hbm_algorithmic_bytes": alg_bytes,
                                   "hbm_achieved_GBs": alg_bytes / (t / 1e3) / 1e9,
                                   "hbm_frac": alg_bytes / (t / 1e3) / 1e9 / PEAK_HBM_GBS,
+                                  "note": "frac counts the method's two products with H per "
+                                          "iteration; the single-cell Q path executes one "
+                                          "(U N)^2 (U d) product instead (executed_frac)",
                                   "executed_flops_per_launch": exec_flops,
                                   "executed_tflops": exec_flops / (t / 1e3) / 1e12,
                                   "executed_frac": exec_flops / (t / 1e3) / 1e12 / peak,
